@@ -1,0 +1,412 @@
+// Small dense float64 linear algebra for the line search (Section 6.1.2,
+// eq. (logdet_blocks), App. A.1) and for the neighbour identity of App. A.2.
+//
+// Line search in whitened form.  With W_II = R R^T (R lower), B0 = W_II^{-1}
+// and C(alpha) = B0 + alpha B1 + alpha^2 B2 (the Schur complement of
+// A + alpha Delta on the block, eq. (logdet_blocks)):
+//     R^T C(alpha) R = I + alpha E1 + alpha^2 E2,
+//     E1 = R^T Delta_II R + K1 + K1^T,    K1 = R^T M R^{-T},  M = Delta_IN W_NI
+//     E2 = K1 K1^T - R^T (Delta_IN W_NN Delta_NI) R
+// so  log det(A + alpha Delta) - log det A = log det(I + alpha E1 + alpha^2 E2)
+// and A + alpha Delta > 0 iff that matrix is PD (eq. (Schurs_PDness)).  The
+// Cholesky of I + E keeps the identity implicit and sums log1p of the pivots,
+// so the change keeps full relative accuracy however small the step.
+#include "sic_internal.h"
+
+namespace sic {
+
+namespace {
+
+constexpr int CH_NB = 256;        // largest block handled by the Cholesky kernel
+constexpr int CH_T = 32;          // tile width
+constexpr int CH_PMAX = CH_NB - CH_T;
+constexpr int CH_PLD = CH_T + 1;  // padded panel row
+
+// In-place lower Cholesky of one nb x nb matrix per workgroup (batch over
+// blockIdx.x, matrices `stride` doubles apart, leading dimension ld), tiled
+// right-looking with 32-wide tiles: factor the diagonal tile in LDS, solve
+// the panel below it with the rows held in registers, then update the
+// trailing lower triangle from the panel staged in LDS.
+// identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
+// out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0.  Only the lower
+// triangle is read and the factor overwrites it.
+__global__ __launch_bounds__(1024) void k_chol(double* __restrict__ M, int64_t stride, int nb,
+                                               int ld, int identity, double* __restrict__ out) {
+    __shared__ double lds[CH_PMAX * CH_PLD];
+    __shared__ double ldiag[CH_T];
+    __shared__ double xbuf[CH_PMAX];
+    double* A = M + (int64_t)blockIdx.x * stride;
+    const int tid = threadIdx.x;
+    const int ti = tid / CH_T, tj = tid % CH_T;
+    double logdet = 0.0;
+    int bad = 0;
+    for (int k0 = 0; k0 < nb && !bad; k0 += CH_T) {
+        const int kw = nb - k0 < CH_T ? nb - k0 : CH_T;
+        double* D = lds;   // diagonal tile, D[i * CH_PLD + j]
+        D[ti * CH_PLD + tj] = (ti < kw && tj < kw && tj <= ti) ? A[(int64_t)(k0 + ti) * ld + k0 + tj] : 0.0;
+        __syncthreads();
+        for (int k = 0; k < kw; ++k) {
+            const double t = D[k * CH_PLD + k];
+            const double piv = identity ? 1.0 + t : t;
+            if (!(piv > 0.0) || !isfinite(piv)) {
+                bad = 1;   // every thread read the same pivot
+                break;
+            }
+            logdet += identity ? log1p(t) : log(t);
+            const double lkk = sqrt(piv);
+            if (tid == 0) ldiag[k] = lkk;
+            if (tj == k && ti > k && ti < kw) D[ti * CH_PLD + k] /= lkk;
+            __syncthreads();
+            if (ti > k && tj > k && tj <= ti && ti < kw)
+                D[ti * CH_PLD + tj] -= D[ti * CH_PLD + k] * D[tj * CH_PLD + k];
+            __syncthreads();
+        }
+        if (bad) break;
+        if (ti < kw && tj <= ti)
+            A[(int64_t)(k0 + ti) * ld + k0 + tj] = (tj == ti) ? ldiag[ti] : D[ti * CH_PLD + tj];
+        // panel rows r = p0 + ti + 32 q, column k0 + tj
+        const int p0 = k0 + CH_T;
+        const int pr = nb - p0;
+        if (pr > 0) {
+            double preg[CH_PMAX / CH_T];
+#pragma unroll
+            for (int q = 0; q < CH_PMAX / CH_T; ++q) {
+                const int r = p0 + ti + CH_T * q;
+                preg[q] = (r < nb && tj < kw) ? A[(int64_t)r * ld + k0 + tj] : 0.0;
+            }
+            for (int jc = 0; jc < kw; ++jc) {
+                if (tj == jc) {
+#pragma unroll
+                    for (int q = 0; q < CH_PMAX / CH_T; ++q) {
+                        preg[q] /= ldiag[jc];
+                        xbuf[ti + CH_T * q] = preg[q];
+                    }
+                }
+                __syncthreads();
+                if (tj > jc && tj < kw) {
+                    const double l = D[tj * CH_PLD + jc];
+#pragma unroll
+                    for (int q = 0; q < CH_PMAX / CH_T; ++q) preg[q] -= xbuf[ti + CH_T * q] * l;
+                }
+                __syncthreads();
+            }
+            // stage the finished panel (D is no longer needed) and store it
+            double* P = lds;
+#pragma unroll
+            for (int q = 0; q < CH_PMAX / CH_T; ++q) {
+                const int rr = ti + CH_T * q;
+                const int r = p0 + rr;
+                P[rr * CH_PLD + tj] = (r < nb && tj < kw) ? preg[q] : 0.0;
+                if (r < nb && tj < kw) A[(int64_t)r * ld + k0 + tj] = preg[q];
+            }
+            __syncthreads();
+            // trailing lower triangle: A[r][c] -= P[r] . P[c]
+            const int total = pr * pr;
+            for (int idx = tid; idx < total; idx += 1024) {
+                const int rr = idx / pr, cc = idx - rr * pr;
+                if (cc > rr) continue;
+                double s = 0.0;
+#pragma unroll 8
+                for (int j = 0; j < CH_T; ++j) s += P[rr * CH_PLD + j] * P[cc * CH_PLD + j];
+                A[(int64_t)(p0 + rr) * ld + p0 + cc] -= s;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[2 * blockIdx.x] = logdet;
+        out[2 * blockIdx.x + 1] = bad ? 0.0 : 1.0;
+    }
+}
+
+// Solve L X = B (trans = 0) or L^T X = B (trans = 1) in place, L nb x nb lower
+// (leading dimension ldl), B nb x ncols row-major (leading dimension ldb).
+// One thread per right-hand side; four partial sums break the FMA chain.
+__global__ void k_trsm_lower(const double* __restrict__ L, int nb, int ldl, double* __restrict__ B,
+                             int ncols, int ldb, int trans) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncols) return;
+    if (!trans) {
+        for (int i = 0; i < nb; ++i) {
+            double s0 = B[(int64_t)i * ldb + col], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            const double* li = L + (int64_t)i * ldl;
+            int k = 0;
+            for (; k + 3 < i; k += 4) {
+                s0 -= li[k] * B[(int64_t)k * ldb + col];
+                s1 -= li[k + 1] * B[(int64_t)(k + 1) * ldb + col];
+                s2 -= li[k + 2] * B[(int64_t)(k + 2) * ldb + col];
+                s3 -= li[k + 3] * B[(int64_t)(k + 3) * ldb + col];
+            }
+            for (; k < i; ++k) s0 -= li[k] * B[(int64_t)k * ldb + col];
+            B[(int64_t)i * ldb + col] = ((s0 + s1) + (s2 + s3)) / li[i];
+        }
+    } else {
+        for (int i = nb - 1; i >= 0; --i) {
+            double s0 = B[(int64_t)i * ldb + col], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int k = i + 1;
+            for (; k + 3 < nb; k += 4) {
+                s0 -= L[(int64_t)k * ldl + i] * B[(int64_t)k * ldb + col];
+                s1 -= L[(int64_t)(k + 1) * ldl + i] * B[(int64_t)(k + 1) * ldb + col];
+                s2 -= L[(int64_t)(k + 2) * ldl + i] * B[(int64_t)(k + 2) * ldb + col];
+                s3 -= L[(int64_t)(k + 3) * ldl + i] * B[(int64_t)(k + 3) * ldb + col];
+            }
+            for (; k < nb; ++k) s0 -= L[(int64_t)k * ldl + i] * B[(int64_t)k * ldb + col];
+            B[(int64_t)i * ldb + col] = ((s0 + s1) + (s2 + s3)) / L[(int64_t)i * ldl + i];
+        }
+    }
+}
+
+// C = alpha * op(A) op(B) + beta * C; op(X) = X or X^T; row-major with leading dims.
+// 16 x 16 output tile per 256-thread workgroup, 16-deep LDS stages.
+__global__ __launch_bounds__(256) void k_gemm_small(int M, int N, int K, double alpha,
+                                                    const double* __restrict__ A, int lda, int ta,
+                                                    const double* __restrict__ B, int ldb, int tb,
+                                                    double beta, double* __restrict__ C, int ldc) {
+    __shared__ double sa[16][17], sb[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        {   // sa[ty][tx] = op(A)[blockIdx.y*16 + ty][k0 + tx]
+            const int r = blockIdx.y * 16 + ty, k = k0 + tx;
+            double v = 0.0;
+            if (r < M && k < K) v = ta ? A[(int64_t)k * lda + r] : A[(int64_t)r * lda + k];
+            sa[ty][tx] = v;
+        }
+        {   // sb[ty][tx] = op(B)[k0 + ty][blockIdx.x*16 + tx]
+            const int k = k0 + ty, c = blockIdx.x * 16 + tx;
+            double v = 0.0;
+            if (k < K && c < N) v = tb ? B[(int64_t)c * ldb + k] : B[(int64_t)k * ldb + c];
+            sb[ty][tx] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) acc += sa[ty][kk] * sb[kk][tx];
+        __syncthreads();
+    }
+    if (i < M && j < N) {
+        const int64_t o = (int64_t)i * ldc + j;
+        C[o] = alpha * acc + (beta != 0.0 ? beta * C[o] : 0.0);
+    }
+}
+
+// Copy the leading nb x nb block of a (ld) matrix into a packed nb x nb buffer.
+__global__ void k_copy_block(const double* __restrict__ src, int ld, int nb, double* __restrict__ dst) {
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) dst[(int64_t)i * nb + j] = src[(int64_t)i * ld + j];
+}
+
+// Delta_II as a dense symmetric b x b matrix from the coordinates with p < b.
+__global__ void k_ls_d11(const int64_t* __restrict__ cptr, const int32_t* __restrict__ c_p,
+                         const double* __restrict__ delta, int b, double* __restrict__ D11) {
+    const int ci = blockIdx.x;
+    for (int64_t t = cptr[ci] + threadIdx.x; t < cptr[ci + 1]; t += blockDim.x) {
+        const int p = c_p[t];
+        if (p < b) {
+            D11[(int64_t)p * b + ci] = delta[t];
+            D11[(int64_t)ci * b + p] = delta[t];
+        }
+    }
+}
+
+// M[c][q] = sum_{t in column c, p_t in N} Delta_t W[p_t][q],  q < b   (M = Delta_IN W_NI)
+__global__ void k_ls_m(const int64_t* __restrict__ cptr, const int32_t* __restrict__ c_p,
+                       const double* __restrict__ delta, const double* __restrict__ WJJ, int jp,
+                       int b, double* __restrict__ Mo) {
+    const int ci = blockIdx.x;
+    for (int q = threadIdx.x; q < b; q += blockDim.x) {
+        double s = 0.0;
+        for (int64_t t = cptr[ci]; t < cptr[ci + 1]; ++t) {
+            const int p = c_p[t];
+            if (p >= b) s += delta[t] * WJJ[(int64_t)p * jp + q];
+        }
+        Mo[(int64_t)ci * b + q] = s;
+    }
+}
+
+// Y[pp][c] = sum_{t in column c, p_t in N} W[b+pp][p_t] Delta_t   (Y = W_NN Delta_NI, nN x b)
+__global__ void k_ls_y(const int64_t* __restrict__ cptr, const int32_t* __restrict__ c_p,
+                       const double* __restrict__ delta, const double* __restrict__ WJJ, int jp,
+                       int b, int nN, double* __restrict__ Y) {
+    const int ci = blockIdx.y;
+    const int pp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pp >= nN) return;
+    const double* wrow = WJJ + (int64_t)(b + pp) * jp;
+    double s = 0.0;
+    for (int64_t t = cptr[ci]; t < cptr[ci + 1]; ++t) {
+        const int p = c_p[t];
+        if (p >= b) s += wrow[p] * delta[t];
+    }
+    Y[(int64_t)pp * b + ci] = s;
+}
+
+// P[c][c'] = sum_{t in column c, p_t in N} Delta_t Y[p_t - b][c']   (P = Delta_IN W_NN Delta_NI)
+__global__ void k_ls_p(const int64_t* __restrict__ cptr, const int32_t* __restrict__ c_p,
+                       const double* __restrict__ delta, const double* __restrict__ Y, int b,
+                       double* __restrict__ P) {
+    const int ci = blockIdx.x;
+    for (int q = threadIdx.x; q < b; q += blockDim.x) {
+        double s = 0.0;
+        for (int64_t t = cptr[ci]; t < cptr[ci + 1]; ++t) {
+            const int p = c_p[t];
+            if (p >= b) s += delta[t] * Y[(int64_t)(p - b) * b + q];
+        }
+        P[(int64_t)ci * b + q] = s;
+    }
+}
+
+// E1 = D1 + X + X^T (X = K1^T), E2 = XtX - RPR, both symmetrised.
+__global__ void k_ls_e(const double* __restrict__ D1, const double* __restrict__ X,
+                       const double* __restrict__ XtX, const double* __restrict__ RPR, int b,
+                       double* __restrict__ E1, double* __restrict__ E2) {
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < b; j += blockDim.x) {
+        const int64_t o = (int64_t)i * b + j, ot = (int64_t)j * b + i;
+        E1[o] = 0.5 * (D1[o] + D1[ot]) + X[o] + X[ot];
+        E2[o] = 0.5 * (XtX[o] + XtX[ot]) - 0.5 * (RPR[o] + RPR[ot]);
+    }
+}
+
+__global__ void k_ls_trials(const double* __restrict__ E1, const double* __restrict__ E2, int b,
+                            const double* __restrict__ alphas, double* __restrict__ C) {
+    const int trial = blockIdx.y;
+    const int i = blockIdx.x;
+    const double a = alphas[trial];
+    double* Ct = C + (int64_t)trial * b * b;
+    for (int j = threadIdx.x; j < b; j += blockDim.x) {
+        const int64_t o = (int64_t)i * b + j;
+        Ct[o] = a * E1[o] + a * a * E2[o];
+    }
+}
+
+__device__ inline double abs_change(double a, double d) {
+    // |a + d| - |a| without rounding a + d when the sign is kept
+    if (a != 0.0) {
+        const double s = a + d;
+        if ((s > 0.0) == (a > 0.0) && s != 0.0) return a > 0.0 ? d : -d;
+        return fabs(s) - fabs(a);
+    }
+    return fabs(d);
+}
+
+// lin[trial] = sum_t w_t (alpha S_t Delta_t + lam (|A_t + alpha Delta_t| - |A_t|)),
+// w_t = 1 on the diagonal, 2 off it (both triangles of the pair).
+__global__ __launch_bounds__(256) void k_ls_linear(int64_t ncoord, const int32_t* __restrict__ c_p,
+                                                   const int32_t* __restrict__ c_ci,
+                                                   const double* __restrict__ c_S,
+                                                   const double* __restrict__ c_A,
+                                                   const double* __restrict__ delta, double lam,
+                                                   const double* __restrict__ alphas,
+                                                   double* __restrict__ lin) {
+    __shared__ double red[256];
+    const double a = alphas[blockIdx.x];
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < ncoord; t += 256) {
+        const double w = (c_p[t] == c_ci[t]) ? 1.0 : 2.0;
+        const double d = delta[t];
+        s += w * (a * c_S[t] * d + lam * abs_change(c_A[t], a * d));
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lin[blockIdx.x] = red[0];
+}
+
+__global__ void k_zero_upper(double* __restrict__ M, int nb, int ld) {
+    const int i = blockIdx.x;
+    for (int j = i + 1 + threadIdx.x; j < nb; j += blockDim.x) M[(int64_t)i * ld + j] = 0.0;
+}
+
+__global__ void k_identity_minus(const double* __restrict__ K, int b, double* __restrict__ out) {
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < b; j += blockDim.x)
+        out[(int64_t)i * b + j] = (i == j ? 1.0 : 0.0) - K[(int64_t)i * b + j];
+}
+
+}  // namespace
+
+void launch_zero_upper(double* M, int nb, int ld, hipStream_t s) {
+    if (nb <= 1) return;
+    hipLaunchKernelGGL(k_zero_upper, dim3(nb), dim3(256), 0, s, M, nb, ld);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_identity_minus(const double* K, int b, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_identity_minus, dim3(b), dim3(256), 0, s, K, b, out);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,
+                 hipStream_t s) {
+    if (nb > CH_NB) throw SicError(SIC_ETOOBIG, "block larger than the Cholesky kernel supports");
+    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(1024), 0, s, M, stride, nb, ld, identity, out);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_trsm_lower(const double* L, int nb, int ldl, double* B, int ncols, int ldb, int trans,
+                       hipStream_t s) {
+    if (ncols <= 0 || nb <= 0) return;
+    hipLaunchKernelGGL(k_trsm_lower, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, s, L, nb, ldl,
+                       B, ncols, ldb, trans);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_gemm_small(int M, int N, int K, double alpha, const double* A, int lda, int ta,
+                       const double* B, int ldb, int tb, double beta, double* C, int ldc,
+                       hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    dim3 grid((unsigned)((N + 15) / 16), (unsigned)((M + 15) / 16));
+    hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb,
+                       beta, C, ldc);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_copy_block(const double* src, int ld, int nb, double* dst, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_copy_block, dim3(nb), dim3(256), 0, s, src, ld, nb, dst);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_ls_terms(const int64_t* cptr, const int32_t* c_p, const double* delta,
+                     const double* WJJ, int jp, int b, int nN, double* D11, double* Mo, double* Y,
+                     double* P, hipStream_t s) {
+    SIC_HIP(hipMemsetAsync(D11, 0, sizeof(double) * b * b, s));
+    hipLaunchKernelGGL(k_ls_d11, dim3(b), dim3(64), 0, s, cptr, c_p, delta, b, D11);
+    SIC_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_ls_m, dim3(b), dim3(256), 0, s, cptr, c_p, delta, WJJ, jp, b, Mo);
+    SIC_CHECK_LAUNCH();
+    if (nN > 0) {
+        hipLaunchKernelGGL(k_ls_y, dim3((unsigned)((nN + 255) / 256), (unsigned)b), dim3(256), 0, s,
+                           cptr, c_p, delta, WJJ, jp, b, nN, Y);
+        SIC_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_ls_p, dim3(b), dim3(256), 0, s, cptr, c_p, delta, Y, b, P);
+        SIC_CHECK_LAUNCH();
+    } else {
+        SIC_HIP(hipMemsetAsync(P, 0, sizeof(double) * b * b, s));
+    }
+}
+
+void launch_ls_e(const double* D1, const double* X, const double* XtX, const double* RPR, int b,
+                 double* E1, double* E2, hipStream_t s) {
+    hipLaunchKernelGGL(k_ls_e, dim3(b), dim3(256), 0, s, D1, X, XtX, RPR, b, E1, E2);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_ls_trials(const double* E1, const double* E2, int b, const double* alphas, int ntrial,
+                      double* C, hipStream_t s) {
+    hipLaunchKernelGGL(k_ls_trials, dim3(b, ntrial), dim3(256), 0, s, E1, E2, b, alphas, C);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_ls_linear(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, const double* c_S,
+                      const double* c_A, const double* delta, double lam, const double* alphas,
+                      int ntrial, double* lin, hipStream_t s) {
+    hipLaunchKernelGGL(k_ls_linear, dim3(ntrial), dim3(256), 0, s, ncoord, c_p, c_ci, c_S, c_A, delta,
+                       lam, alphas, lin);
+    SIC_CHECK_LAUNCH();
+}
+
+}  // namespace sic

@@ -1,0 +1,164 @@
+// Covariance columns from the samples (Section 6: the samples are stored, S is
+// never formed; the trace term costs O(nnz * m), Section 6.1.2).
+//
+//   S_J = X^T X[:, J] / m      (n x b, dense, finest level)
+//   S_rc = X[:, r] . X[:, c] / m  for listed pairs (coarse levels, Section 7:
+//                                  only the entries of C_l are needed)
+//
+// X is m x n row-major float64.  The dense block is an MFMA contraction over
+// the m samples (v_mfma_f64_16x16x4f64); sampled entries are wave-wide dot
+// products over rows of the transposed copy Xt (n x m row-major).
+#include "sic_internal.h"
+
+namespace sic {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int SJ_TILE = 64;   // output tile: 64 rows of S_J x 64 block columns
+constexpr int SJ_KC = 16;     // samples staged per LDS round
+constexpr int SJ_PAD = 4;
+
+// One workgroup = 4 waves = one 64 x 64 output tile; wave (wr, wc) owns a
+// 32 x 32 quadrant as 2 x 2 MFMA 16x16 accumulators.
+// MFMA f64 16x16x4 operand layout: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; the 16x16 result sits in 4 registers per lane as
+// D[4*(l/16) + v][l%16], v = 0..3.
+__global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ X, int64_t n,
+                                                     int64_t m, int64_t j0, int b,
+                                                     double* __restrict__ out, double invm) {
+    __shared__ double sA[SJ_KC][SJ_TILE + SJ_PAD];
+    __shared__ double sB[SJ_KC][SJ_TILE + SJ_PAD];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int64_t i0 = (int64_t)blockIdx.x * SJ_TILE;   // rows of S_J (variables)
+    const int c0 = blockIdx.y * SJ_TILE;                // block columns
+    // loader mapping: 16 rows x 64 columns, 4 consecutive doubles per thread
+    const int lr = tid >> 4;          // 0..15
+    const int lc = (tid & 15) * 4;    // 0..60
+    double4_t acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb) acc[a][bb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t r0 = 0; r0 < m; r0 += SJ_KC) {
+        const int64_t r = r0 + lr;
+        const bool rok = r < m;
+        const double* xrow = X + r * n;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t ia = i0 + lc + q;
+            const int cb = c0 + lc + q;
+            sA[lr][lc + q] = (rok && ia < n) ? xrow[ia] : 0.0;
+            sB[lr][lc + q] = (rok && cb < b) ? xrow[j0 + cb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < SJ_KC; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = sA[kr][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) bv[bb] = sB[kr][wc * 32 + bb * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb)
+                    acc[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[bb], acc[a][bb], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + v;
+                const int c = c0 + wc * 32 + bb * 16 + (lane & 15);
+                if (i < n && c < b) out[i * b + c] = acc[a][bb][v] * invm;
+            }
+}
+
+__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X, int64_t m, int64_t n,
+                                                   double* __restrict__ Xt) {
+    __shared__ double tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int64_t c0 = (int64_t)blockIdx.x * 32;   // column of X (variable)
+    const int64_t r0 = (int64_t)blockIdx.y * 32;   // row of X (sample)
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        tile[k][tx] = (r < m && c < n) ? X[r * n + c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (c < n && r < m) Xt[c * m + r] = tile[tx][k];
+    }
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_diag_s(const double* __restrict__ Xt, int64_t n, int64_t m,
+                                                double* __restrict__ d, double invm) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const double* x = Xt + i * m;
+    double s = 0.0;
+    for (int64_t r = lane; r < m; r += 64) s += x[r] * x[r];
+    s = wave_sum(s);
+    if (lane == 0) d[i] = s * invm;
+}
+
+__global__ __launch_bounds__(256) void k_sddmm(const double* __restrict__ Xt, int64_t m,
+                                               const int32_t* __restrict__ rows,
+                                               const int32_t* __restrict__ cols, int64_t count,
+                                               double* __restrict__ out, double invm) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= count) return;
+    const double* x = Xt + (int64_t)rows[t] * m;
+    const double* y = Xt + (int64_t)cols[t] * m;
+    double s = 0.0;
+    for (int64_t r = lane; r < m; r += 64) s += x[r] * y[r];
+    s = wave_sum(s);
+    if (lane == 0) out[t] = s * invm;
+}
+
+}  // namespace
+
+void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b, double* out,
+                        hipStream_t s) {
+    dim3 grid((unsigned)((n + SJ_TILE - 1) / SJ_TILE), (unsigned)((b + SJ_TILE - 1) / SJ_TILE));
+    hipLaunchKernelGGL(k_sj_gemm_f64, grid, dim3(256), 0, s, X, n, m, j0, b, out, 1.0 / (double)m);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_transpose(const double* X, int64_t m, int64_t n, double* Xt, hipStream_t s) {
+    dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, X, m, n, Xt);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_diag_s(const double* Xt, int64_t n, int64_t m, double* d, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_s, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, Xt, n, m, d,
+                       1.0 / (double)m);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_sddmm(const double* Xt, int64_t m, const int32_t* rows, const int32_t* cols,
+                  int64_t count, double* out, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_sddmm, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, s, Xt, m, rows,
+                       cols, count, out, 1.0 / (double)m);
+    SIC_CHECK_LAUNCH();
+}
+
+}  // namespace sic

@@ -1,0 +1,113 @@
+// Small device utilities: single-workgroup prefix scans and index helpers
+// used to compact free sets, neighbourhoods and CSR rows in a fixed order.
+#include "sic_internal.h"
+
+namespace sic {
+
+namespace {
+
+constexpr int SCAN_THREADS = 1024;
+
+// Exclusive scan of `count` int32 values into int64 (out has count+1 entries,
+// out[count] = total). One workgroup; each thread owns a contiguous chunk.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_i32(const int32_t* __restrict__ in,
+                                                           int64_t count, int64_t* __restrict__ out,
+                                                           int64_t* __restrict__ total_out) {
+    __shared__ int64_t sums[SCAN_THREADS];
+    const int t = threadIdx.x;
+    const int64_t chunk = (count + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t b0 = t * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
+    int64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += in[i];
+    sums[t] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        int64_t v = t >= off ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? sums[t - 1] : 0;
+    for (int64_t i = b0; i < b1; ++i) {
+        out[i] = run;
+        run += in[i];
+    }
+    if (t == SCAN_THREADS - 1) {
+        out[count] = sums[t];
+        if (total_out) *total_out = sums[t];
+    }
+}
+
+// Scan of per-(tile, column) counts in column-major order (column outer,
+// tile inner): offsets[tile*b + c] = number of entries of columns < c plus
+// entries of column c in tiles < tile. colptr[c] = offsets[0*b + c].
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* __restrict__ cnt,
+                                                                int tiles, int b,
+                                                                int32_t* __restrict__ offsets,
+                                                                int64_t* __restrict__ colptr) {
+    __shared__ int64_t sums[SCAN_THREADS];
+    const int t = threadIdx.x;
+    const int64_t count = (int64_t)tiles * b;
+    const int64_t chunk = (count + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t b0 = t * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
+    int64_t s = 0;
+    for (int64_t q = b0; q < b1; ++q) {
+        const int64_t c = q / tiles, tile = q % tiles;
+        s += cnt[tile * b + c];
+    }
+    sums[t] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        int64_t v = t >= off ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? sums[t - 1] : 0;
+    for (int64_t q = b0; q < b1; ++q) {
+        const int64_t c = q / tiles, tile = q % tiles;
+        offsets[tile * b + c] = (int32_t)run;
+        if (tile == 0) colptr[c] = run;
+        run += cnt[tile * b + c];
+    }
+    if (t == SCAN_THREADS - 1) colptr[b] = sums[t];
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t count, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ void k_iota_i32(int32_t* __restrict__ p, int64_t count, int32_t start) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = start + (int32_t)i;
+}
+
+}  // namespace
+
+void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* total, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(SCAN_THREADS), 0, s, in, count, out, total);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets, int64_t* colptr,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_colmajor, dim3(1), dim3(SCAN_THREADS), 0, s, cnt, tiles, b, offsets,
+                       colptr);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
+    SIC_CHECK_LAUNCH();
+}
+
+void launch_iota_i32(int32_t* p, int64_t count, int32_t start, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count,
+                       start);
+    SIC_CHECK_LAUNCH();
+}
+
+}  // namespace sic

@@ -1,0 +1,190 @@
+// Internal declarations of the sic library (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sic.h"
+
+namespace sic {
+
+struct HipError : std::runtime_error {
+    hipError_t code;
+    HipError(hipError_t c, const std::string& what) : std::runtime_error(what), code(c) {}
+};
+
+struct SicError : std::runtime_error {
+    int code;
+    SicError(int c, const std::string& what) : std::runtime_error(what), code(c) {}
+};
+
+#define SIC_HIP(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            throw ::sic::HipError(_e, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+    } while (0)
+
+#define SIC_CHECK_LAUNCH() SIC_HIP(hipGetLastError())
+
+// Bytes of device memory allocated through DevBuf (for the HBM budget).
+extern size_t g_dev_bytes;
+extern size_t g_dev_budget;
+// Largest dynamic LDS a workgroup may use on the current device.
+extern size_t CD_MAX_LDS_BYTES;
+
+// Device buffer with grow-only capacity (contents are not kept on growth).
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) {
+            (void)hipFree(p);
+            g_dev_bytes -= cap * sizeof(T);
+        }
+        p = nullptr;
+        cap = 0;
+    }
+    void reserve(size_t count) {
+        if (count <= cap && p) return;
+        release();
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        if (g_dev_budget && g_dev_bytes + bytes > g_dev_budget)
+            throw SicError(SIC_ENOMEM, "HBM budget exceeded by a " + std::to_string(bytes) +
+                                           "-byte buffer");
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw SicError(SIC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        cap = count ? count : 1;
+        g_dev_bytes += cap * sizeof(T);
+    }
+};
+
+// Symmetric sparse matrix on the device: full CSR (both triangles), sorted columns.
+struct DevCSR {
+    int64_t n = 0, nnz = 0;
+    DevBuf<int64_t> rowptr;
+    DevBuf<int32_t> col;
+    DevBuf<double> val;
+};
+
+// ---------------------------------------------------------------- k_sj.hip
+void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b, double* out,
+                        hipStream_t s);
+void launch_transpose(const double* X, int64_t m, int64_t n, double* Xt, hipStream_t s);
+void launch_diag_s(const double* Xt, int64_t n, int64_t m, double* d, hipStream_t s);
+void launch_sddmm(const double* Xt, int64_t m, const int32_t* rows, const int32_t* cols,
+                  int64_t count, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- k_cg.hip
+struct CGWork {
+    DevBuf<double> R, Z, P, Q, dinv, part, scal;
+    DevBuf<int32_t> flags;
+};
+struct CGResult {
+    int iterations = 0;
+    double max_rel_res = 0;
+    bool converged = false;
+};
+CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
+                  double tol, int max_iter, CGWork& wk, hipStream_t s);
+
+// ---------------------------------------------------------------- k_util.hip
+void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* total, hipStream_t s);
+void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets, int64_t* colptr,
+                          hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
+void launch_iota_i32(int32_t* p, int64_t count, int32_t start, hipStream_t s);
+
+// ---------------------------------------------------------------- k_screen.hip
+void launch_scatter_aj(const DevCSR& A, int64_t j0, int b, double* AJ, hipStream_t s);
+void launch_screen_fine(int pass, int64_t n, int64_t j0, int b, int rows_per_tile, int tiles,
+                        double lam, const double* SJ, const double* WI, const double* AJ,
+                        int32_t* tilecount, const int32_t* offsets, int32_t* e_row, double* e_g,
+                        double* e_s, double* e_a, double* e_w, int32_t* nflag, double* kkt,
+                        hipStream_t s);
+void launch_kkt_accumulate(const double* kkt, int tiles, double* acc, hipStream_t s);
+void launch_nbr_compact(const int32_t* flag, const int64_t* scan, int64_t n, int64_t j0, int b,
+                        int32_t* Jp, int32_t* lmap, hipStream_t s);
+void launch_flag_compact(const int32_t* flag, const int64_t* scan, int64_t n, int32_t* list,
+                         int32_t* map, hipStream_t s);
+void launch_reset_rows(const int32_t* list, int64_t count, int32_t* flag, int32_t* map, hipStream_t s);
+void launch_coord_count(const int64_t* colptr, const int32_t* e_row, int64_t j0, int b,
+                        int32_t* ccount, hipStream_t s);
+void launch_coord_fill(const int64_t* colptr, const int32_t* e_row, const double* e_s,
+                       const double* e_a, const int64_t* cptr, const int32_t* lmap, int64_t j0,
+                       int b, int32_t* c_p, int32_t* c_e, double* c_S, double* c_A, hipStream_t s);
+void launch_gather_wjj(int mode, const int32_t* Jp, int jp, int b, const double* WI,
+                       const double* WN, int64_t nN, const double* WII, const double* WNC,
+                       int64_t nC, const int32_t* cmap, double* WJJ, hipStream_t s);
+void launch_expand_cand(const int64_t* crow, int64_t j0, int b, int64_t base, int32_t* cand_col,
+                        hipStream_t s);
+void launch_flag_cand(const int32_t* ccol, int64_t base, int64_t count, int64_t j0, int b,
+                      int32_t* flag, hipStream_t s);
+void launch_a2_k(const DevCSR& A, int64_t j0, int b, const double* WNC, int64_t nC,
+                 const int32_t* cmap, double* K, int32_t* err, hipStream_t s);
+void launch_dense_aii(const DevCSR& A, int64_t j0, int b, double* out, hipStream_t s);
+void launch_screen_coarse(int pass, const int64_t* crow, const int32_t* ccol, int64_t base,
+                          int64_t j0, int b, double lam, const double* S_cand, const double* WII,
+                          const double* WNC, int64_t nC, const int32_t* cmap, const double* AJ,
+                          int32_t* ccount, const int64_t* colptr, int32_t* e_row, double* e_g,
+                          double* e_s, double* e_a, double* e_w, int32_t* nflag, hipStream_t s);
+
+// ---------------------------------------------------------------- k_cd.hip
+size_t cd_lds_bytes(int jp, bool u_in_lds);
+void launch_cd_prep(const int64_t* cptr, int b, int64_t ncoord, const int32_t* c_p,
+                    const double* WJJ, int jp, int32_t* c_ci, double* c_a, double* c_inva,
+                    double* c_wtc, double* c_wtt, double* delta, hipStream_t s);
+void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const double* c_S,
+               const double* c_A, const double* c_inva, const double* c_wtc, const double* WJJ,
+               double lam, int max_sweeps, double tol, double* U, double* delta, double* mu_col,
+               double* ug, double* stats, hipStream_t s);
+
+// ---------------------------------------------------------------- k_dense.hip
+void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,
+                 hipStream_t s);
+void launch_zero_upper(double* M, int nb, int ld, hipStream_t s);
+void launch_trsm_lower(const double* L, int nb, int ldl, double* B, int ncols, int ldb, int trans,
+                       hipStream_t s);
+void launch_gemm_small(int M, int N, int K, double alpha, const double* A, int lda, int ta,
+                       const double* B, int ldb, int tb, double beta, double* C, int ldc,
+                       hipStream_t s);
+void launch_copy_block(const double* src, int ld, int nb, double* dst, hipStream_t s);
+void launch_ls_terms(const int64_t* cptr, const int32_t* c_p, const double* delta,
+                     const double* WJJ, int jp, int b, int nN, double* D11, double* Mo, double* Y,
+                     double* P, hipStream_t s);
+void launch_ls_e(const double* D1, const double* X, const double* XtX, const double* RPR, int b,
+                 double* E1, double* E2, hipStream_t s);
+void launch_ls_trials(const double* E1, const double* E2, int b, const double* alphas, int ntrial,
+                      double* C, hipStream_t s);
+void launch_ls_linear(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, const double* c_S,
+                      const double* c_A, const double* delta, double lam, const double* alphas,
+                      int ntrial, double* lin, hipStream_t s);
+void launch_identity_minus(const double* K, int b, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- k_update.hip
+void launch_upd_newvals(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, const double* c_A,
+                        const double* delta, double alpha, const int32_t* Jp, int64_t j0, int b,
+                        double* ANEW, hipStream_t s);
+void launch_upd_reset(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, const int32_t* Jp,
+                      int64_t j0, int b, double* ANEW, hipStream_t s);
+void launch_upd_rows(int pass, int64_t n, int64_t j0, int b, const DevCSR& A, const int32_t* lmap,
+                     const int64_t* cptr, const int32_t* c_p, const int32_t* Jp, const double* ANEW,
+                     int32_t* cnt, const int64_t* nrowptr, int32_t* ncol, double* nval,
+                     hipStream_t s);
+
+}  // namespace sic

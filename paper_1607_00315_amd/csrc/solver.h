@@ -1,0 +1,120 @@
+// Host-side state of the solver: context, problem, block working set.
+#pragma once
+
+#include "sic_internal.h"
+
+namespace sic {
+
+struct Options {
+    int block = 256;
+    double cg_tol_I = 1e-5, cg_tol_N = 1e-4;
+    int cg_max_iter = 1000;
+    double cd_tol = 1e-4;
+    int cd_max_sweeps = 20;
+    int ls_max_trials = 31;
+    int max_cycles = 100;
+    uint64_t flags = 0;
+    int precision = SIC_FP64;
+};
+
+// Scratch of one block update; sized on demand, reused across blocks.
+struct BlockWork {
+    DevBuf<double> SJ, WI, AJ, ANEW, WN, WJJ, U, ug;
+    DevBuf<int32_t> cols;
+    // free lists
+    DevBuf<int64_t> colptr;
+    DevBuf<int32_t> e_row, tilecount, offsets, nflag, ccount;
+    DevBuf<double> e_g, e_s, e_a, e_w, kkt, kkt_acc;
+    // neighbourhood
+    DevBuf<int64_t> scan_n;
+    DevBuf<int32_t> Jp, lmap;
+    // coordinates
+    DevBuf<int64_t> cptr;
+    DevBuf<int32_t> c_p, c_e, c_ci;
+    DevBuf<double> c_S, c_A, c_a, c_inva, c_wtc, c_wtt, delta, mu, cdstats;
+    // line search
+    DevBuf<double> Rb, D11, Mo, Y, Pm, T1, D1, X, XtX, RPR, E1, E2, C, chol_out, alphas, lin;
+    // coarse levels
+    DevBuf<int32_t> cand_col, cflag, cmap, NC, err;
+    DevBuf<double> S_cand, WNC, WII, Kb, AII;
+    // CSR rebuild
+    DevBuf<int32_t> rcount;
+    CGWork cg;
+    int64_t n_init = 0;   // n for which flag/map arrays are initialised
+    int b_init = 0;
+};
+
+struct BlockResult {
+    int64_t j0 = 0;
+    int b = 0;
+    int level = 0;
+    int64_t E = 0, nN = 0, nC = 0, ncoord = 0, jp = 0;
+    int cg_iters_I = 0, cg_iters_N = 0;
+    double cg_res_I = 0, cg_res_N = 0;
+    int cd_sweeps = 0;
+    double cd_last_maxmu = 0;
+    double alpha = 0, dF = 0;
+    int trials = 0;
+    int64_t nnz_after = 0;
+};
+
+struct Problem {
+    int64_t n = 0, m = 0;
+    double lam = 0;
+    DevBuf<double> X, Xt, diagS;
+    DevCSR A[2];
+    int cur = 0;
+    double F = 0;
+    int64_t max_nnz = 0;
+    // level set C_l as a symmetric CSR pattern (device) plus host row pointers
+    DevBuf<int64_t> crow;
+    DevBuf<int32_t> ccol;
+    std::vector<int64_t> crow_h;
+    bool level_set = false;
+    // free pairs (key i*n+j, i<=j) and |g| recorded by the last finest sweep
+    std::vector<int64_t> rec_key;
+    std::vector<double> rec_g;
+    std::vector<int64_t> rec_seq;
+    DevCSR& Acur() { return A[cur]; }
+};
+
+struct Context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Options opt;
+    size_t budget = 0;
+    BlockWork work;
+    sic_trace_entry* trace = nullptr;
+    int trace_cap = 0;
+    // pinned staging for small device-to-host reads
+    int64_t* h_i64 = nullptr;
+    double* h_f64 = nullptr;
+    BlockResult last;
+};
+
+// problem setup / transfer
+void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n, int64_t m,
+                  double lam);
+void set_identity(Context& C, Problem& P);
+void set_A_host(Context& C, Problem& P, const sic_csr* A);
+void get_A_host(Context& C, Problem& P, sic_csr* out);
+void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count);
+
+// algorithm
+BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, bool record,
+                         double tolI, double tolN);
+void initial_free_set(Context& C, Problem& P);
+struct SweepResult {
+    double kkt_max = 0, kkt_l1 = 0;
+    int64_t cg_iters = 0, cd_sweeps = 0, blocks = 0;
+};
+SweepResult sweep(Context& C, Problem& P, bool fine, double tolI, double tolN);
+void hierarchy_host(int64_t n, const std::vector<int64_t>& supp,
+                    const std::vector<int64_t>& fkey, const std::vector<double>& fg,
+                    std::vector<int64_t>& ranking, std::vector<int64_t>& sizes);
+std::vector<int64_t> support_keys(Context& C, Problem& P);
+int solve_problem(Context& C, Problem& P, double tol, sic_info* info);
+double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1);
+
+}  // namespace sic

@@ -1,0 +1,881 @@
+// The multilevel block coordinate-descent solver on the host side:
+//   block_update  one block of Algorithm 2 at the finest level or, restricted
+//                 to a level set C_l, at a coarse level (Section 7, App. A.2)
+//   sweep         one relaxation = the blocks in order
+//   solve_problem Algorithm 1 cycles until the KKT target
+// Every arithmetic step runs in the kernels of this library; the host only
+// sequences launches, reads back the few sizes that shape the next launch,
+// and builds the nested level sets from the recorded free set.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "solver.h"
+
+namespace sic {
+
+size_t g_dev_bytes = 0;
+size_t g_dev_budget = 0;
+size_t CD_MAX_LDS_BYTES = 65536;
+
+namespace {
+
+constexpr int ROWS_PER_TILE = 64;
+
+void sync(Context& C) { SIC_HIP(hipStreamSynchronize(C.stream)); }
+
+int64_t read_i64(Context& C, const int64_t* d) {
+    SIC_HIP(hipMemcpyAsync(C.h_i64, d, sizeof(int64_t), hipMemcpyDeviceToHost, C.stream));
+    sync(C);
+    return C.h_i64[0];
+}
+
+void ensure_flags(Context& C, int64_t n, int b) {
+    BlockWork& W = C.work;
+    if (W.n_init == n && W.b_init >= b) return;
+    W.nflag.reserve(n);
+    W.cflag.reserve(n);
+    W.lmap.reserve(n);
+    W.cmap.reserve(n);
+    SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, C.stream));
+    SIC_HIP(hipMemsetAsync(W.cflag.p, 0, sizeof(int32_t) * n, C.stream));
+    launch_fill_i32(W.lmap.p, n, -1, C.stream);
+    launch_fill_i32(W.cmap.p, n, -1, C.stream);
+    W.ANEW.reserve((size_t)n * b);
+    SIC_HIP(hipMemsetAsync(W.ANEW.p, 0, sizeof(double) * n * b, C.stream));
+    W.n_init = n;
+    W.b_init = b;
+}
+
+struct LineSearch {
+    double alpha = 0, dF = 0;
+    int trials = 0;
+    bool wii_pd = true;
+};
+
+// Whitened Schur-complement matrices E1, E2 of the line search (see k_dense.hip):
+// log det(A + a Delta) - log det A = log det(I + a E1 + a^2 E2).
+void ls_prepare(Context& C, int jp, int b, int64_t nN) {
+    BlockWork& W = C.work;
+    hipStream_t s = C.stream;
+    const size_t bb = (size_t)b * b;
+    W.Rb.reserve(bb); W.D11.reserve(bb); W.Mo.reserve(bb); W.Pm.reserve(bb);
+    W.T1.reserve(bb); W.D1.reserve(bb); W.X.reserve(bb); W.XtX.reserve(bb);
+    W.RPR.reserve(bb); W.E1.reserve(bb); W.E2.reserve(bb);
+    W.Y.reserve((size_t)std::max<int64_t>(nN, 1) * b);
+    W.C.reserve(4 * bb);
+    W.chol_out.reserve(16);
+    W.alphas.reserve(4);
+    W.lin.reserve(4);
+    // R R^T = W_II
+    launch_copy_block(W.WJJ.p, jp, b, W.Rb.p, s);
+    launch_chol(W.Rb.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s);
+    launch_zero_upper(W.Rb.p, b, b, s);
+    launch_ls_terms(W.cptr.p, W.c_p.p, W.delta.p, W.WJJ.p, jp, b, (int)nN, W.D11.p, W.Mo.p, W.Y.p,
+                    W.Pm.p, s);
+    // X = R^{-1} (M^T R) = K1^T
+    launch_gemm_small(b, b, b, 1.0, W.Mo.p, b, 1, W.Rb.p, b, 0, 0.0, W.X.p, b, s);
+    launch_trsm_lower(W.Rb.p, b, b, W.X.p, b, b, 0, s);
+    // D1 = R^T Delta_II R
+    launch_gemm_small(b, b, b, 1.0, W.D11.p, b, 0, W.Rb.p, b, 0, 0.0, W.T1.p, b, s);
+    launch_gemm_small(b, b, b, 1.0, W.Rb.p, b, 1, W.T1.p, b, 0, 0.0, W.D1.p, b, s);
+    // RPR = R^T P R
+    launch_gemm_small(b, b, b, 1.0, W.Pm.p, b, 0, W.Rb.p, b, 0, 0.0, W.T1.p, b, s);
+    launch_gemm_small(b, b, b, 1.0, W.Rb.p, b, 1, W.T1.p, b, 0, 0.0, W.RPR.p, b, s);
+    // XtX = K1 K1^T
+    launch_gemm_small(b, b, b, 1.0, W.X.p, b, 1, W.X.p, b, 0, 0.0, W.XtX.p, b, s);
+    launch_ls_e(W.D1.p, W.X.p, W.XtX.p, W.RPR.p, b, W.E1.p, W.E2.p, s);
+}
+
+// Evaluate nt <= 4 trial steps: log det change, PD flag, linear terms.
+// Returns whether W_II itself factored (positive definite).
+bool ls_eval(Context& C, int b, int64_t ncoord, double lam, const double* al, int nt,
+             double* logdet, int* pd, double* lin) {
+    BlockWork& W = C.work;
+    hipStream_t s = C.stream;
+    const size_t bb = (size_t)b * b;
+    double h_out[10];
+    SIC_HIP(hipMemcpyAsync(W.alphas.p, al, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+    launch_ls_trials(W.E1.p, W.E2.p, b, W.alphas.p, nt, W.C.p, s);
+    launch_chol(W.C.p, (int64_t)bb, nt, b, b, 1, W.chol_out.p + 2, s);
+    launch_ls_linear(ncoord, W.c_p.p, W.c_ci.p, W.c_S.p, W.c_A.p, W.delta.p, lam, W.alphas.p, nt,
+                     W.lin.p, s);
+    SIC_HIP(hipMemcpyAsync(h_out, W.chol_out.p, sizeof(double) * (2 + 2 * nt),
+                           hipMemcpyDeviceToHost, s));
+    SIC_HIP(hipMemcpyAsync(lin, W.lin.p, sizeof(double) * nt, hipMemcpyDeviceToHost, s));
+    sync(C);
+    for (int t = 0; t < nt; ++t) {
+        logdet[t] = h_out[2 + 2 * t];
+        pd[t] = h_out[2 + 2 * t + 1] != 0.0;
+    }
+    return h_out[1] != 0.0;
+}
+
+// Step length by the backtracking rule of Section 6.1.2: alpha = 2^-i,
+// non-PD trials skipped, then continue while F keeps decreasing; alpha = 0
+// when no trial decreases F. Trials are evaluated four at a time.
+LineSearch line_search(Context& C, double lam, int jp, int b, int64_t nN, int64_t ncoord) {
+    ls_prepare(C, jp, b, nN);
+    LineSearch res;
+    bool have = false, stop = false;
+    double best_a = 0.0, best_f = 0.0;
+    int i = 0;
+    const int max_trials = std::max(1, C.opt.ls_max_trials);
+    while (!stop && i < max_trials) {
+        const int nt = std::min(4, max_trials - i);
+        double al[4], ld[4], lin[4];
+        int pd[4];
+        for (int t = 0; t < nt; ++t) al[t] = std::ldexp(1.0, -(i + t));
+        res.wii_pd = ls_eval(C, b, ncoord, lam, al, nt, ld, pd, lin);
+        if (!res.wii_pd) break;
+        for (int t = 0; t < nt; ++t) {
+            res.trials++;
+            if (!pd[t]) {
+                if (have) { stop = true; break; }
+                continue;
+            }
+            const double f = lin[t] - ld[t];
+            if (!have || f < best_f) {
+                have = true;
+                best_a = al[t];
+                best_f = f;
+                continue;
+            }
+            stop = true;
+            break;
+        }
+        i += nt;
+    }
+    if (have && best_f < 0.0 && res.wii_pd) {
+        res.alpha = best_a;
+        res.dF = best_f;
+    }
+    return res;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ setup
+
+__global__ void k_to_f64_from_f32(const float* __restrict__ in, int64_t count, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = (double)in[i];
+}
+
+__global__ void k_to_f64_from_bf16(const uint16_t* __restrict__ in, int64_t count, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = (double)__uint_as_float(((unsigned int)in[i]) << 16);
+}
+
+void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n, int64_t m,
+                  double lam) {
+    hipStream_t s = C.stream;
+    P.n = n;
+    P.m = m;
+    P.lam = lam;
+    const size_t count = (size_t)n * m;
+    P.X.reserve(count);
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, X) == hipSuccess)
+        on_device = attr.type == hipMemoryTypeDevice;
+    (void)hipGetLastError();
+    size_t esz = x_dtype == SIC_X_F64 ? 8 : (x_dtype == SIC_X_F32 ? 4 : 2);
+    if (x_dtype == SIC_X_F64) {
+        SIC_HIP(hipMemcpyAsync(P.X.p, X, count * esz,
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    } else {
+        DevBuf<char> tmp;
+        tmp.reserve(count * esz);
+        SIC_HIP(hipMemcpyAsync(tmp.p, X, count * esz,
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        const unsigned grid = (unsigned)((count + 255) / 256);
+        if (x_dtype == SIC_X_F32)
+            hipLaunchKernelGGL(k_to_f64_from_f32, dim3(grid), dim3(256), 0, s,
+                               (const float*)tmp.p, (int64_t)count, P.X.p);
+        else
+            hipLaunchKernelGGL(k_to_f64_from_bf16, dim3(grid), dim3(256), 0, s,
+                               (const uint16_t*)tmp.p, (int64_t)count, P.X.p);
+        SIC_CHECK_LAUNCH();
+        sync(C);
+    }
+    P.Xt.reserve(count);
+    launch_transpose(P.X.p, m, n, P.Xt.p, s);
+    P.diagS.reserve(n);
+    launch_diag_s(P.Xt.p, n, m, P.diagS.p, s);
+    std::vector<double> d(n);
+    SIC_HIP(hipMemcpyAsync(d.data(), P.diagS.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    sync(C);
+    for (double v : d)
+        if (!std::isfinite(v)) throw SicError(SIC_ENONFINITE, "non-finite value in X");
+    set_identity(C, P);
+    double tr = 0.0;
+    for (double v : d) tr += v;
+    P.F = tr + lam * (double)n;   // F(I) = -log det I + tr(S) + lam * n
+    P.level_set = false;
+}
+
+void set_identity(Context& C, Problem& P) {
+    const int64_t n = P.n;
+    DevCSR& A = P.A[P.cur];
+    std::vector<int64_t> rp(n + 1);
+    std::vector<int32_t> cl(n);
+    std::vector<double> vl(n, 1.0);
+    for (int64_t i = 0; i <= n; ++i) rp[i] = i;
+    for (int64_t i = 0; i < n; ++i) cl[i] = (int32_t)i;
+    A.n = n;
+    A.nnz = n;
+    A.rowptr.reserve(n + 1);
+    A.col.reserve(n);
+    A.val.reserve(n);
+    SIC_HIP(hipMemcpyAsync(A.rowptr.p, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, C.stream));
+    SIC_HIP(hipMemcpyAsync(A.col.p, cl.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, C.stream));
+    SIC_HIP(hipMemcpyAsync(A.val.p, vl.data(), sizeof(double) * n, hipMemcpyHostToDevice, C.stream));
+    sync(C);
+    P.max_nnz = n;
+}
+
+void set_A_host(Context& C, Problem& P, const sic_csr* in) {
+    const int64_t n = P.n;
+    if (!in || in->n != n || !in->rowptr || (in->nnz > 0 && (!in->col || !in->val)))
+        throw SicError(SIC_EINVAL, "warm start CSR does not match the problem");
+    if (in->rowptr[0] != 0 || in->rowptr[n] != in->nnz)
+        throw SicError(SIC_EINVAL, "warm start CSR row pointers are inconsistent");
+    bool diag_ok = true;
+    for (int64_t i = 0; i < n && diag_ok; ++i) {
+        bool found = false;
+        for (int64_t e = in->rowptr[i]; e < in->rowptr[i + 1]; ++e) {
+            if (!std::isfinite(in->val[e])) throw SicError(SIC_ENONFINITE, "non-finite warm start");
+            if (e > in->rowptr[i] && in->col[e] <= in->col[e - 1])
+                throw SicError(SIC_EINVAL, "warm start columns must be sorted and unique");
+            if (in->col[e] == i) found = in->val[e] > 0.0;
+        }
+        diag_ok = found;
+    }
+    if (!diag_ok) throw SicError(SIC_ENOTPD, "warm start has a non-positive diagonal");
+    DevCSR& A = P.A[P.cur];
+    A.n = n;
+    A.nnz = in->nnz;
+    A.rowptr.reserve(n + 1);
+    A.col.reserve(std::max<int64_t>(in->nnz, 1));
+    A.val.reserve(std::max<int64_t>(in->nnz, 1));
+    SIC_HIP(hipMemcpyAsync(A.rowptr.p, in->rowptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, C.stream));
+    if (in->nnz) {
+        SIC_HIP(hipMemcpyAsync(A.col.p, in->col, sizeof(int32_t) * in->nnz, hipMemcpyHostToDevice, C.stream));
+        SIC_HIP(hipMemcpyAsync(A.val.p, in->val, sizeof(double) * in->nnz, hipMemcpyHostToDevice, C.stream));
+    }
+    sync(C);
+    P.max_nnz = std::max(P.max_nnz, in->nnz);
+}
+
+void get_A_host(Context& C, Problem& P, sic_csr* out) {
+    DevCSR& A = P.Acur();
+    const int64_t n = P.n, nnz = A.nnz;
+    out->n = n;
+    out->nnz = nnz;
+    out->rowptr = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+    out->col = (int32_t*)malloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    out->val = (double*)malloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+    if (!out->rowptr || !out->col || !out->val) {
+        free(out->rowptr); free(out->col); free(out->val);
+        out->rowptr = nullptr; out->col = nullptr; out->val = nullptr;
+        throw SicError(SIC_ENOMEM, "host allocation for the result failed");
+    }
+    SIC_HIP(hipMemcpyAsync(out->rowptr, A.rowptr.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, C.stream));
+    if (nnz) {
+        SIC_HIP(hipMemcpyAsync(out->col, A.col.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, C.stream));
+        SIC_HIP(hipMemcpyAsync(out->val, A.val.p, sizeof(double) * nnz, hipMemcpyDeviceToHost, C.stream));
+    }
+    sync(C);
+}
+
+void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count) {
+    const int64_t n = P.n;
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t i = keys[t] / n, j = keys[t] % n;
+        if (i < 0 || j < 0 || i >= n || j >= n || i > j)
+            throw SicError(SIC_EINVAL, "level key out of range (expects i*n+j with i <= j)");
+        cnt[i + 1]++;
+        if (i != j) cnt[j + 1]++;
+    }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    const int64_t total = cnt[n];
+    std::vector<int32_t> col(std::max<int64_t>(total, 1));
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t i = keys[t] / n, j = keys[t] % n;
+        col[pos[i]++] = (int32_t)j;
+        if (i != j) col[pos[j]++] = (int32_t)i;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        std::sort(col.begin() + cnt[i], col.begin() + cnt[i + 1]);
+        auto last = std::unique(col.begin() + cnt[i], col.begin() + cnt[i + 1]);
+        if (last != col.begin() + cnt[i + 1]) throw SicError(SIC_EINVAL, "duplicate level keys");
+    }
+    P.crow.reserve(n + 1);
+    P.ccol.reserve(std::max<int64_t>(total, 1));
+    SIC_HIP(hipMemcpyAsync(P.crow.p, cnt.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, C.stream));
+    if (total)
+        SIC_HIP(hipMemcpyAsync(P.ccol.p, col.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice, C.stream));
+    sync(C);
+    P.crow_h = std::move(cnt);
+    P.level_set = true;
+}
+
+// ------------------------------------------------------------------ one block
+
+BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, bool record,
+                         double tolI, double tolN) {
+    hipStream_t s = C.stream;
+    BlockWork& W = C.work;
+    const int64_t n = P.n;
+    DevCSR& A = P.Acur();
+    if (!fine && !P.level_set) throw SicError(SIC_EINVAL, "coarse block without a level set");
+    ensure_flags(C, n, b);
+    BlockResult R;
+    R.j0 = j0;
+    R.b = b;
+    R.level = fine ? 0 : 1;
+    const size_t nb = (size_t)n * b;
+    W.AJ.reserve(nb);
+    SIC_HIP(hipMemsetAsync(W.AJ.p, 0, sizeof(double) * nb, s));
+    launch_scatter_aj(A, j0, b, W.AJ.p, s);
+    W.colptr.reserve(b + 1);
+    W.ccount.reserve(b);
+    W.kkt_acc.reserve(2);
+    int64_t nC = 0;
+    if (fine) {
+        // (a) S_J, (b) W_I, (c) screening over all rows
+        W.SJ.reserve(nb);
+        W.WI.reserve(nb);
+        W.cols.reserve(std::max<int64_t>(b, 1));
+        launch_sj_gemm_f64(P.X.p, n, P.m, j0, b, W.SJ.p, s);
+        launch_iota_i32(W.cols.p, b, (int32_t)j0, s);
+        CGResult cg = block_cg(A, W.cols.p, b, W.WI.p, b, tolI, C.opt.cg_max_iter, W.cg, s);
+        R.cg_iters_I = cg.iterations;
+        R.cg_res_I = cg.max_rel_res;
+        const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
+        W.tilecount.reserve((size_t)tiles * b);
+        W.offsets.reserve((size_t)tiles * b);
+        W.kkt.reserve(2 * (size_t)tiles);
+        launch_screen_fine(0, n, j0, b, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, W.WI.p, W.AJ.p,
+                           W.tilecount.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           W.nflag.p, W.kkt.p, s);
+        if (record) launch_kkt_accumulate(W.kkt.p, tiles, W.kkt_acc.p, s);
+        launch_scan_colmajor(W.tilecount.p, tiles, b, W.offsets.p, W.colptr.p, s);
+        R.E = read_i64(C, W.colptr.p + b);
+        const size_t E = (size_t)std::max<int64_t>(R.E, 1);
+        W.e_row.reserve(E); W.e_g.reserve(E); W.e_s.reserve(E); W.e_a.reserve(E); W.e_w.reserve(E);
+        launch_screen_fine(1, n, j0, b, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, W.WI.p, W.AJ.p,
+                           W.tilecount.p, W.offsets.p, W.e_row.p, W.e_g.p, W.e_s.p, W.e_a.p,
+                           W.e_w.p, W.nflag.p, W.kkt.p, s);
+    } else {
+        // coarse level: candidates C_l of the block columns, S by sampled dot
+        // products, W_{N^C} by CG and W_II by the neighbour identity (App. A.2)
+        const int64_t base = P.crow_h[j0];
+        const int64_t cnt = P.crow_h[j0 + b] - base;
+        W.cand_col.reserve(std::max<int64_t>(cnt, 1));
+        W.S_cand.reserve(std::max<int64_t>(cnt, 1));
+        launch_expand_cand(P.crow.p, j0, b, base, W.cand_col.p, s);
+        launch_sddmm(P.Xt.p, P.m, P.ccol.p + base, W.cand_col.p, cnt, W.S_cand.p, s);
+        launch_flag_cand(P.ccol.p, base, cnt, j0, b, W.cflag.p, s);
+        W.scan_n.reserve(n + 1);
+        launch_scan_i32(W.cflag.p, n, W.scan_n.p, nullptr, s);
+        nC = read_i64(C, W.scan_n.p + n);
+        R.nC = nC;
+        W.NC.reserve(std::max<int64_t>(nC, 1));
+        launch_flag_compact(W.cflag.p, W.scan_n.p, n, W.NC.p, W.cmap.p, s);
+        W.WNC.reserve((size_t)n * std::max<int64_t>(nC, 1));
+        if (nC > 0) {
+            CGResult cg = block_cg(A, W.NC.p, (int)nC, W.WNC.p, nC, tolI, C.opt.cg_max_iter, W.cg, s);
+            R.cg_iters_N = cg.iterations;
+            R.cg_res_N = cg.max_rel_res;
+        }
+        const size_t bb = (size_t)b * b;
+        W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb);
+        W.err.reserve(1);
+        W.chol_out.reserve(16);
+        SIC_HIP(hipMemsetAsync(W.err.p, 0, sizeof(int32_t), s));
+        launch_a2_k(A, j0, b, W.WNC.p, nC, W.cmap.p, W.Kb.p, W.err.p, s);
+        launch_dense_aii(A, j0, b, W.AII.p, s);
+        launch_chol(W.AII.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s);
+        launch_zero_upper(W.AII.p, b, b, s);
+        launch_identity_minus(W.Kb.p, b, W.WII.p, s);
+        launch_trsm_lower(W.AII.p, b, b, W.WII.p, b, b, 0, s);
+        launch_trsm_lower(W.AII.p, b, b, W.WII.p, b, b, 1, s);
+        double h[2];
+        int32_t herr = 0;
+        SIC_HIP(hipMemcpyAsync(h, W.chol_out.p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(&herr, W.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        sync(C);
+        if (herr) throw SicError(SIC_EINTERNAL, "support of A is not inside the level set");
+        if (h[1] == 0.0) throw SicError(SIC_ENOTPD, "diagonal block of A is not positive definite");
+        launch_screen_coarse(0, P.crow.p, P.ccol.p, base, j0, b, P.lam, W.S_cand.p, W.WII.p,
+                             W.WNC.p, nC, W.cmap.p, W.AJ.p, W.ccount.p, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, nullptr, W.nflag.p, s);
+        launch_scan_i32(W.ccount.p, b, W.colptr.p, nullptr, s);
+        R.E = read_i64(C, W.colptr.p + b);
+        const size_t E = (size_t)std::max<int64_t>(R.E, 1);
+        W.e_row.reserve(E); W.e_g.reserve(E); W.e_s.reserve(E); W.e_a.reserve(E); W.e_w.reserve(E);
+        launch_screen_coarse(1, P.crow.p, P.ccol.p, base, j0, b, P.lam, W.S_cand.p, W.WII.p,
+                             W.WNC.p, nC, W.cmap.p, W.AJ.p, W.ccount.p, W.colptr.p, W.e_row.p,
+                             W.e_g.p, W.e_s.p, W.e_a.p, W.e_w.p, W.nflag.p, s);
+    }
+    // neighbourhood N and J' = I u N
+    W.scan_n.reserve(n + 1);
+    launch_scan_i32(W.nflag.p, n, W.scan_n.p, nullptr, s);
+    R.nN = read_i64(C, W.scan_n.p + n);
+    const int64_t nN = R.nN;
+    const int64_t jp64 = b + nN;
+    if (jp64 > (int64_t)INT32_MAX / 2) throw SicError(SIC_ETOOBIG, "neighbourhood too large");
+    const int jp = (int)jp64;
+    R.jp = jp;
+    W.Jp.reserve(jp);
+    launch_nbr_compact(W.nflag.p, W.scan_n.p, n, j0, b, W.Jp.p, W.lmap.p, s);
+    // coordinates
+    W.cptr.reserve(b + 1);
+    launch_coord_count(W.colptr.p, W.e_row.p, j0, b, W.ccount.p, s);
+    launch_scan_i32(W.ccount.p, b, W.cptr.p, nullptr, s);
+    R.ncoord = read_i64(C, W.cptr.p + b);
+    const int64_t nc = R.ncoord;
+    const size_t ncs = (size_t)std::max<int64_t>(nc, 1);
+    W.c_p.reserve(ncs); W.c_e.reserve(ncs); W.c_ci.reserve(ncs);
+    W.c_S.reserve(ncs); W.c_A.reserve(ncs); W.c_a.reserve(ncs); W.c_inva.reserve(ncs);
+    W.c_wtc.reserve(ncs); W.c_wtt.reserve(ncs); W.delta.reserve(ncs); W.mu.reserve(ncs);
+    launch_coord_fill(W.colptr.p, W.e_row.p, W.e_s.p, W.e_a.p, W.cptr.p, W.lmap.p, j0, b, W.c_p.p,
+                      W.c_e.p, W.c_S.p, W.c_A.p, s);
+    // W_N at the finest level
+    if (fine && nN > 0) {
+        W.WN.reserve((size_t)n * nN);
+        CGResult cg = block_cg(A, W.Jp.p + b, (int)nN, W.WN.p, nN, tolN, C.opt.cg_max_iter, W.cg, s);
+        R.cg_iters_N = cg.iterations;
+        R.cg_res_N = cg.max_rel_res;
+    }
+    // W on J' x J'
+    W.WJJ.reserve((size_t)jp * jp);
+    launch_gather_wjj(fine ? 0 : 1, W.Jp.p, jp, b, W.WI.p, W.WN.p, nN, W.WII.p, W.WNC.p, nC,
+                      W.cmap.p, W.WJJ.p, s);
+    // (d) coordinate descent
+    W.U.reserve((size_t)jp * b);
+    W.ug.reserve(jp);
+    W.cdstats.reserve(4);
+    SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
+    launch_cd_prep(W.cptr.p, b, nc, W.c_p.p, W.WJJ.p, jp, W.c_ci.p, W.c_a.p, W.c_inva.p, W.c_wtc.p,
+                   W.c_wtt.p, W.delta.p, s);
+    launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, P.lam,
+              C.opt.cd_max_sweeps, C.opt.cd_tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.cdstats.p, s);
+    double cds[3];
+    SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    // (e) line search
+    LineSearch ls = line_search(C, P.lam, jp, b, nN, nc);
+    R.cd_sweeps = (int)cds[0];
+    R.cd_last_maxmu = cds[1];
+    if (!ls.wii_pd) throw SicError(SIC_EINTERNAL, "W_II is not positive definite (inaccurate inverse columns)");
+    R.alpha = ls.alpha;
+    R.dF = ls.dF;
+    R.trials = ls.trials;
+    // A <- A + alpha Delta
+    if (ls.alpha != 0.0) {
+        DevCSR& An = P.A[1 - P.cur];
+        const int64_t cap = A.nnz + 2 * nc;
+        An.n = n;
+        An.rowptr.reserve(n + 1);
+        An.col.reserve(std::max<int64_t>(cap, 1));
+        An.val.reserve(std::max<int64_t>(cap, 1));
+        W.rcount.reserve(n);
+        launch_upd_newvals(nc, W.c_p.p, W.c_ci.p, W.c_A.p, W.delta.p, ls.alpha, W.Jp.p, j0, b,
+                           W.ANEW.p, s);
+        launch_upd_rows(0, n, j0, b, A, W.lmap.p, W.cptr.p, W.c_p.p, W.Jp.p, W.ANEW.p, W.rcount.p,
+                        nullptr, nullptr, nullptr, s);
+        launch_scan_i32(W.rcount.p, n, An.rowptr.p, nullptr, s);
+        An.nnz = read_i64(C, An.rowptr.p + n);
+        if (An.nnz > cap) throw SicError(SIC_EINTERNAL, "CSR rebuild exceeded its bound");
+        launch_upd_rows(1, n, j0, b, A, W.lmap.p, W.cptr.p, W.c_p.p, W.Jp.p, W.ANEW.p, W.rcount.p,
+                        An.rowptr.p, An.col.p, An.val.p, s);
+        launch_upd_reset(nc, W.c_p.p, W.c_ci.p, W.Jp.p, j0, b, W.ANEW.p, s);
+        P.cur = 1 - P.cur;
+        P.F += ls.dF;
+        P.max_nnz = std::max(P.max_nnz, An.nnz);
+    }
+    R.nnz_after = P.Acur().nnz;
+    // free pairs and |g| for the next hierarchy
+    if (record && R.E > 0) {
+        std::vector<int64_t> cp(b + 1);
+        std::vector<int32_t> rows(R.E);
+        std::vector<double> g(R.E);
+        SIC_HIP(hipMemcpyAsync(cp.data(), W.colptr.p, sizeof(int64_t) * (b + 1), hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(rows.data(), W.e_row.p, sizeof(int32_t) * R.E, hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(g.data(), W.e_g.p, sizeof(double) * R.E, hipMemcpyDeviceToHost, s));
+        sync(C);
+        int64_t seq = (int64_t)P.rec_seq.size();
+        for (int ci = 0; ci < b; ++ci) {
+            const int64_t c = j0 + ci;
+            for (int64_t e = cp[ci]; e < cp[ci + 1]; ++e) {
+                const int64_t r = rows[e];
+                const int64_t key = r <= c ? r * n + c : c * n + r;
+                P.rec_key.push_back(key);
+                P.rec_g.push_back(std::fabs(g[e]));
+                P.rec_seq.push_back(seq++);
+            }
+        }
+    }
+    // reset per-block flags and maps
+    SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, s));
+    launch_reset_rows(W.Jp.p, jp, nullptr, W.lmap.p, s);
+    if (!fine && nC > 0) launch_reset_rows(W.NC.p, nC, W.cflag.p, W.cmap.p, s);
+    sync(C);
+    C.last = R;
+    return R;
+}
+
+// ------------------------------------------------------------------ sweeps
+
+static void finish_records(Problem& P) {
+    const size_t N = P.rec_key.size();
+    std::vector<size_t> idx(N);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        if (P.rec_key[a] != P.rec_key[b]) return P.rec_key[a] < P.rec_key[b];
+        return P.rec_seq[a] < P.rec_seq[b];
+    });
+    std::vector<int64_t> k;
+    std::vector<double> g;
+    k.reserve(N);
+    g.reserve(N);
+    for (size_t t = 0; t < N; ++t) {
+        const size_t i = idx[t];
+        if (t + 1 < N && P.rec_key[idx[t + 1]] == P.rec_key[i]) continue;   // keep the latest
+        k.push_back(P.rec_key[i]);
+        g.push_back(P.rec_g[i]);
+    }
+    P.rec_key = std::move(k);
+    P.rec_g = std::move(g);
+    P.rec_seq.clear();
+}
+
+void initial_free_set(Context& C, Problem& P) {
+    // W = A^{-1} = I at A = I: free pairs are |S_ij| > lambda plus the diagonal
+    hipStream_t s = C.stream;
+    BlockWork& W = C.work;
+    const int64_t n = P.n;
+    const int b = std::min<int64_t>(C.opt.block, n);
+    ensure_flags(C, n, b);
+    P.rec_key.clear();
+    P.rec_g.clear();
+    P.rec_seq.clear();
+    W.kkt_acc.reserve(2);
+    for (int64_t j0 = 0; j0 < n; j0 += b) {
+        const int bb = (int)std::min<int64_t>(b, n - j0);
+        const size_t nb = (size_t)n * bb;
+        W.SJ.reserve(nb);
+        W.AJ.reserve(nb);
+        W.colptr.reserve(bb + 1);
+        SIC_HIP(hipMemsetAsync(W.AJ.p, 0, sizeof(double) * nb, s));
+        launch_scatter_aj(P.Acur(), j0, bb, W.AJ.p, s);
+        launch_sj_gemm_f64(P.X.p, n, P.m, j0, bb, W.SJ.p, s);
+        const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
+        W.tilecount.reserve((size_t)tiles * bb);
+        W.offsets.reserve((size_t)tiles * bb);
+        W.kkt.reserve(2 * (size_t)tiles);
+        launch_screen_fine(0, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, nullptr, W.AJ.p,
+                           W.tilecount.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           W.nflag.p, W.kkt.p, s);
+        launch_scan_colmajor(W.tilecount.p, tiles, bb, W.offsets.p, W.colptr.p, s);
+        const int64_t E = read_i64(C, W.colptr.p + bb);
+        const size_t Es = (size_t)std::max<int64_t>(E, 1);
+        W.e_row.reserve(Es); W.e_g.reserve(Es); W.e_s.reserve(Es); W.e_a.reserve(Es); W.e_w.reserve(Es);
+        launch_screen_fine(1, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, nullptr, W.AJ.p,
+                           W.tilecount.p, W.offsets.p, W.e_row.p, W.e_g.p, W.e_s.p, W.e_a.p,
+                           W.e_w.p, W.nflag.p, W.kkt.p, s);
+        std::vector<int64_t> cp(bb + 1);
+        std::vector<int32_t> rows(Es);
+        std::vector<double> g(Es);
+        SIC_HIP(hipMemcpyAsync(cp.data(), W.colptr.p, sizeof(int64_t) * (bb + 1), hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(rows.data(), W.e_row.p, sizeof(int32_t) * Es, hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(g.data(), W.e_g.p, sizeof(double) * Es, hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, s));
+        sync(C);
+        int64_t seq = (int64_t)P.rec_seq.size();
+        for (int ci = 0; ci < bb; ++ci) {
+            const int64_t c = j0 + ci;
+            for (int64_t e = cp[ci]; e < cp[ci + 1]; ++e) {
+                const int64_t r = rows[e];
+                const int64_t key = r <= c ? r * n + c : c * n + r;
+                P.rec_key.push_back(key);
+                P.rec_g.push_back(std::fabs(g[e]));
+                P.rec_seq.push_back(seq++);
+            }
+        }
+    }
+    finish_records(P);
+}
+
+SweepResult sweep(Context& C, Problem& P, bool fine, double tolI, double tolN) {
+    SweepResult S;
+    const int64_t n = P.n;
+    const int b = (int)std::min<int64_t>(C.opt.block, n);
+    if (fine) {
+        C.work.kkt_acc.reserve(2);
+        SIC_HIP(hipMemsetAsync(C.work.kkt_acc.p, 0, sizeof(double) * 2, C.stream));
+        P.rec_key.clear();
+        P.rec_g.clear();
+        P.rec_seq.clear();
+    }
+    for (int64_t j0 = 0; j0 < n; j0 += b) {
+        const int bb = (int)std::min<int64_t>(b, n - j0);
+        BlockResult R = block_update(C, P, j0, bb, fine, fine, tolI, tolN);
+        S.cg_iters += R.cg_iters_I + R.cg_iters_N;
+        S.cd_sweeps += R.cd_sweeps;
+        S.blocks += 1;
+    }
+    if (fine) {
+        double acc[2];
+        SIC_HIP(hipMemcpyAsync(acc, C.work.kkt_acc.p, sizeof(double) * 2, hipMemcpyDeviceToHost, C.stream));
+        sync(C);
+        S.kkt_max = acc[0];
+        S.kkt_l1 = acc[1];
+        finish_records(P);
+    }
+    return S;
+}
+
+// ------------------------------------------------------------------ hierarchy
+
+void hierarchy_host(int64_t n, const std::vector<int64_t>& supp, const std::vector<int64_t>& fkey,
+                    const std::vector<double>& fg, std::vector<int64_t>& ranking,
+                    std::vector<int64_t>& sizes) {
+    (void)n;
+    std::vector<int64_t> sp(supp);
+    std::sort(sp.begin(), sp.end());
+    sp.erase(std::unique(sp.begin(), sp.end()), sp.end());
+    std::vector<size_t> rest;
+    rest.reserve(fkey.size());
+    for (size_t t = 0; t < fkey.size(); ++t)
+        if (!std::binary_search(sp.begin(), sp.end(), fkey[t])) rest.push_back(t);
+    std::sort(rest.begin(), rest.end(), [&](size_t a, size_t b) {
+        if (fg[a] != fg[b]) return fg[a] > fg[b];
+        return fkey[a] < fkey[b];
+    });
+    ranking = sp;
+    for (size_t t : rest) ranking.push_back(fkey[t]);
+    const int64_t nf = (int64_t)ranking.size(), ns = (int64_t)sp.size();
+    sizes.clear();
+    sizes.push_back(std::max((nf + 1) / 2, ns));
+    while (sizes.back() != ns) sizes.push_back(std::max((sizes.back() + 1) / 2, ns));
+}
+
+std::vector<int64_t> support_keys(Context& C, Problem& P) {
+    DevCSR& A = P.Acur();
+    const int64_t n = P.n;
+    std::vector<int64_t> rp(n + 1);
+    std::vector<int32_t> cl(std::max<int64_t>(A.nnz, 1));
+    SIC_HIP(hipMemcpyAsync(rp.data(), A.rowptr.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, C.stream));
+    SIC_HIP(hipMemcpyAsync(cl.data(), A.col.p, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost, C.stream));
+    sync(C);
+    std::vector<int64_t> keys;
+    keys.reserve(A.nnz / 2 + n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (cl[e] >= i) keys.push_back(i * n + cl[e]);
+    return keys;   // ascending: rows ascending, columns sorted
+}
+
+// ------------------------------------------------------------------ exact KKT
+
+double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1) {
+    hipStream_t s = C.stream;
+    BlockWork& W = C.work;
+    const int64_t n = P.n;
+    const int b = (int)std::min<int64_t>(C.opt.block, n);
+    ensure_flags(C, n, b);
+    W.kkt_acc.reserve(2);
+    SIC_HIP(hipMemsetAsync(W.kkt_acc.p, 0, sizeof(double) * 2, s));
+    for (int64_t j0 = 0; j0 < n; j0 += b) {
+        const int bb = (int)std::min<int64_t>(b, n - j0);
+        const size_t nb = (size_t)n * bb;
+        W.SJ.reserve(nb); W.WI.reserve(nb); W.AJ.reserve(nb);
+        W.cols.reserve(bb);
+        SIC_HIP(hipMemsetAsync(W.AJ.p, 0, sizeof(double) * nb, s));
+        launch_scatter_aj(P.Acur(), j0, bb, W.AJ.p, s);
+        launch_sj_gemm_f64(P.X.p, n, P.m, j0, bb, W.SJ.p, s);
+        launch_iota_i32(W.cols.p, bb, (int32_t)j0, s);
+        block_cg(P.Acur(), W.cols.p, bb, W.WI.p, bb, tol_cg, C.opt.cg_max_iter * 4, W.cg, s);
+        const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
+        W.tilecount.reserve((size_t)tiles * bb);
+        W.kkt.reserve(2 * (size_t)tiles);
+        launch_screen_fine(0, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, W.WI.p, W.AJ.p,
+                           W.tilecount.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           W.nflag.p, W.kkt.p, s);
+        launch_kkt_accumulate(W.kkt.p, tiles, W.kkt_acc.p, s);
+        SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, s));
+    }
+    double acc[2];
+    SIC_HIP(hipMemcpyAsync(acc, W.kkt_acc.p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    sync(C);
+    if (l1) *l1 = acc[1];
+    return acc[0];
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+
+static double a_l1_norm(Context& C, Problem& P) {
+    DevCSR& A = P.Acur();
+    std::vector<double> v(std::max<int64_t>(A.nnz, 1));
+    SIC_HIP(hipMemcpyAsync(v.data(), A.val.p, sizeof(double) * A.nnz, hipMemcpyDeviceToHost, C.stream));
+    sync(C);
+    double s = 0.0;
+    for (int64_t e = 0; e < A.nnz; ++e) s += std::fabs(v[e]);
+    return s;
+}
+
+int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    auto secs = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+    const bool ml = !(C.opt.flags & SIC_FLAG_NO_MULTILEVEL);
+    const bool verbose = (C.opt.flags & SIC_FLAG_VERBOSE) != 0;
+    initial_free_set(C, P);
+    double kkt_prev = INFINITY, kkt_l1 = INFINITY;
+    int status = SIC_ENOCONV;
+    int cycles = 0, sweeps = 0, trace_len = 0;
+    int64_t blocks = 0, cg_it = 0, cd_sw = 0;
+    for (int cyc = 0; cyc < C.opt.max_cycles; ++cyc) {
+        const double tolI = std::min(C.opt.cg_tol_I, std::max(1e-12, 0.01 * kkt_prev));
+        const double tolN = std::min(C.opt.cg_tol_N, std::max(1e-12, 0.01 * kkt_prev));
+        int levels = 0;
+        if (ml) {
+            std::vector<int64_t> ranking, sizes;
+            hierarchy_host(P.n, support_keys(C, P), P.rec_key, P.rec_g, ranking, sizes);
+            for (int l = (int)sizes.size() - 1; l >= 0; --l) {
+                set_level_keys(C, P, ranking.data(), sizes[l]);
+                SweepResult sr = sweep(C, P, false, tolI, tolN);
+                blocks += sr.blocks;
+                cg_it += sr.cg_iters;
+                cd_sw += sr.cd_sweeps;
+                ++sweeps;
+                ++levels;
+            }
+        }
+        SweepResult sr = sweep(C, P, true, tolI, tolN);
+        blocks += sr.blocks;
+        cg_it += sr.cg_iters;
+        cd_sw += sr.cd_sweeps;
+        ++sweeps;
+        ++cycles;
+        kkt_prev = sr.kkt_max;
+        kkt_l1 = sr.kkt_l1;
+        if (verbose)
+            fprintf(stderr, "[sic] cycle %d levels %d F=%.15e kkt=%.3e nnz=%lld t=%.3fs\n", cyc,
+                    levels, P.F, sr.kkt_max, (long long)P.Acur().nnz, secs());
+        if (C.trace && trace_len < C.trace_cap) {
+            sic_trace_entry& e = C.trace[trace_len++];
+            e.seconds = secs();
+            e.objective = P.F;
+            e.kkt_max = sr.kkt_max;
+            e.nnz = P.Acur().nnz;
+            e.cycle = cyc;
+            e.levels = levels;
+        }
+        if (sr.kkt_max <= tol) {
+            status = SIC_OK;
+            break;
+        }
+    }
+    double kkt_final = kkt_prev;
+    if (C.opt.flags & SIC_FLAG_FINAL_KKT) {
+        kkt_final = exact_kkt(C, P, std::max(1e-13, std::min(1e-10, 0.01 * tol)), &kkt_l1);
+        status = kkt_final <= tol ? SIC_OK : SIC_ENOCONV;
+    }
+    if (info) {
+        info->objective = P.F;
+        info->kkt_max = kkt_final;
+        const double l1 = a_l1_norm(C, P);
+        info->kkt_rel_l1 = l1 > 0 ? kkt_l1 / l1 : INFINITY;
+        info->nnz = P.Acur().nnz;
+        info->max_nnz = P.max_nnz;
+        info->cycles = cycles;
+        info->sweeps = sweeps;
+        info->blocks = blocks;
+        info->cg_iterations = cg_it;
+        info->cd_sweeps = cd_sw;
+        info->seconds = secs();
+        info->status = status;
+        info->trace_len = trace_len;
+    }
+    return status;
+}
+
+// ------------------------------------------------------------------ standalone steps
+
+static void load_coords(Context& C, int jp, int b, const double* wjj, const int64_t* cptr,
+                        const int32_t* cp, const double* S, const double* A) {
+    BlockWork& W = C.work;
+    hipStream_t s = C.stream;
+    const int64_t nc = cptr[b];
+    const size_t ncs = (size_t)std::max<int64_t>(nc, 1);
+    W.WJJ.reserve((size_t)jp * jp);
+    W.cptr.reserve(b + 1);
+    W.c_p.reserve(ncs); W.c_ci.reserve(ncs); W.c_S.reserve(ncs); W.c_A.reserve(ncs);
+    W.c_a.reserve(ncs); W.c_inva.reserve(ncs); W.c_wtc.reserve(ncs); W.c_wtt.reserve(ncs);
+    W.delta.reserve(ncs); W.mu.reserve(ncs);
+    W.U.reserve((size_t)jp * b);
+    W.ug.reserve(jp);
+    W.cdstats.reserve(4);
+    SIC_HIP(hipMemcpyAsync(W.WJJ.p, wjj, sizeof(double) * jp * jp, hipMemcpyHostToDevice, s));
+    SIC_HIP(hipMemcpyAsync(W.cptr.p, cptr, sizeof(int64_t) * (b + 1), hipMemcpyHostToDevice, s));
+    if (nc) {
+        SIC_HIP(hipMemcpyAsync(W.c_p.p, cp, sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+        SIC_HIP(hipMemcpyAsync(W.c_S.p, S, sizeof(double) * nc, hipMemcpyHostToDevice, s));
+        SIC_HIP(hipMemcpyAsync(W.c_A.p, A, sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    }
+    launch_cd_prep(W.cptr.p, b, nc, W.c_p.p, W.WJJ.p, jp, W.c_ci.p, W.c_a.p, W.c_inva.p, W.c_wtc.p,
+                   W.c_wtt.p, W.delta.p, s);
+}
+
+int step_cd_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cptr,
+                 const int32_t* cp, const double* S, const double* A, double lambda, int max_sweeps,
+                 double tol, double* delta_out, double* stats_out) {
+    BlockWork& W = C.work;
+    hipStream_t s = C.stream;
+    load_coords(C, jp, b, wjj, cptr, cp, S, A);
+    const int64_t nc = cptr[b];
+    SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
+    launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, lambda,
+              max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.cdstats.p, s);
+    if (nc) SIC_HIP(hipMemcpyAsync(delta_out, W.delta.p, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+    double st[3];
+    SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    sync(C);
+    if (stats_out) std::copy(st, st + 3, stats_out);
+    return SIC_OK;
+}
+
+int step_ls_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cptr,
+                 const int32_t* cp, const double* S, const double* A, const double* delta,
+                 double lambda, double* alpha, double* dF, int* trials, double* logdet_out,
+                 int n_alpha) {
+    BlockWork& W = C.work;
+    hipStream_t s = C.stream;
+    load_coords(C, jp, b, wjj, cptr, cp, S, A);
+    const int64_t nc = cptr[b];
+    if (nc) SIC_HIP(hipMemcpyAsync(W.delta.p, delta, sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    LineSearch ls = line_search(C, lambda, jp, b, jp - b, nc);
+    if (!ls.wii_pd) throw SicError(SIC_ENOTPD, "W_II is not positive definite");
+    if (alpha) *alpha = ls.alpha;
+    if (dF) *dF = ls.dF;
+    if (trials) *trials = ls.trials;
+    for (int i = 0; logdet_out && i < n_alpha; i += 4) {
+        const int nt = std::min(4, n_alpha - i);
+        double al[4], ld[4], lin[4];
+        int pd[4];
+        for (int t = 0; t < nt; ++t) al[t] = std::ldexp(1.0, -(i + t));
+        ls_eval(C, b, nc, lambda, al, nt, ld, pd, lin);
+        for (int t = 0; t < nt; ++t) logdet_out[i + t] = pd[t] ? ld[t] : NAN;
+    }
+    return SIC_OK;
+}
+
+}  // namespace sic

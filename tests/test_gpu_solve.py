@@ -1,0 +1,109 @@
+"""End-to-end parity of sic_solve against the CPU oracle (through the C-ABI).
+
+Bar (float64 path): identical support, exact KKT max-norm of the GPU result
+<= 1e-6 (measured by the oracle with a dense inverse), relative objective
+within 1e-8 of the oracle's minimiser.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import core, quic_plain
+from synth import workload
+from tests.helpers import announce, csr_to_dense, check_csr_valid
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(X, lam, tol, **opts):
+    from paper_1607_00315_amd import sic
+    with sic.Context(**opts) as c:
+        (rp, col, val), info, trace = c.solve(X, lam, tol)
+    n = X.shape[1]
+    check_csr_valid(rp, col, val, n)
+    return csr_to_dense(rp, col, val, n), info
+
+
+def _exact_kkt(A, S, lam):
+    W = np.linalg.inv(A)
+    return core.kkt_max(S - W, A, lam)
+
+
+@pytest.mark.parametrize("name,multilevel", [("chain_n200_m100", True), ("chain_n200_m100", False),
+                                             ("chain_n64_m48", True), ("random_n600_m300", True),
+                                             ("grid_n900_m600", True)])
+def test_solve_matches_oracle(name, multilevel):
+    from paper_1607_00315_amd import sic
+    X, P, spec = workload(name)
+    lam = spec["lam"]
+    S = core.covariance(X)
+    announce(f"solve {name} lam={lam} b={spec['block']} multilevel={multilevel}")
+    flags = 0 if multilevel else sic.FLAG_NO_MULTILEVEL
+    A, info = _solve(X, lam, 1e-7, block=spec["block"], flags=flags)
+    Aq, _ = quic_plain.solve(S, lam, tol=1e-12)
+    assert np.array_equal(A, A.T)
+    assert np.array_equal(A != 0, Aq != 0), \
+        f"support differs: {np.count_nonzero(A)} vs {np.count_nonzero(Aq)}"
+    assert _exact_kkt(A, S, lam) <= 1e-6
+    F, Fq = core.objective(A, S, lam), core.objective(Aq, S, lam)
+    assert abs(F - Fq) <= 1e-8 * abs(Fq)
+    # the tracked objective follows the true one
+    assert abs(info["objective"] - F) <= 1e-8 * abs(F)
+    assert info["status"] == 0
+
+
+def test_diagonal_regime():
+    X, P, spec = workload("chain_n64_m48")
+    S = core.covariance(X)
+    lam = 1.01 * np.max(np.abs(S - np.diag(np.diag(S))))
+    announce("solve diagonal regime chain_n64")
+    A, info = _solve(X, lam, 1e-9, block=16)
+    np.testing.assert_allclose(A, np.diag(1.0 / (np.diag(S) + lam)), rtol=1e-12, atol=0)
+
+
+def test_lambda_zero_many_samples():
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((400, 40)) @ np.diag(np.linspace(0.5, 2.0, 40))
+    S = core.covariance(X)
+    announce("solve lambda=0 n=40 m=400")
+    A, info = _solve(X, 0.0, 1e-9, block=16)
+    np.testing.assert_allclose(A, np.linalg.inv(S), rtol=1e-7, atol=1e-9)
+
+
+def test_single_variable_and_tiny_blocks():
+    X = np.array([[1.0], [2.0], [-1.0]])
+    announce("solve n=1")
+    A, info = _solve(X, 0.3, 1e-12, block=8)
+    assert A[0, 0] == pytest.approx(1.0 / (2.0 + 0.3), rel=1e-14)
+    X, P, spec = workload("chain_n64_m48")
+    S = core.covariance(X)
+    announce("solve chain_n64 b=1 and b=7")
+    Aq, _ = quic_plain.solve(S, spec["lam"], tol=1e-12)
+    for b in (1, 7):
+        A, info = _solve(X, spec["lam"], 1e-7, block=b)
+        assert np.array_equal(A != 0, Aq != 0)
+
+
+def test_invalid_arguments_rejected():
+    from paper_1607_00315_amd import sic
+    X = np.ones((5, 10))
+    announce("invalid arguments")
+    with sic.Context() as c:
+        for lam, tol in [(-1.0, 1e-6), (0.1, 0.0), (0.0, 1e-6)]:   # lam=0 with m <= n
+            with pytest.raises(sic.SicError) as e:
+                c.solve(X, lam, tol)
+            assert e.value.code == sic.SIC_EINVAL
+        Xbad = np.ones((20, 4))
+        Xbad[3, 2] = np.nan
+        with pytest.raises(sic.SicError) as e:
+            c.solve(Xbad, 0.1, 1e-6)
+        assert e.value.code == sic.SIC_ENONFINITE
+
+
+def test_device_input_pointer():
+    import torch
+    X, P, spec = workload("chain_n64_m48")
+    announce("solve with a device pointer for X")
+    A1, _ = _solve(X, spec["lam"], 1e-8, block=16)
+    A2, _ = _solve(torch.from_numpy(X).cuda(), spec["lam"], 1e-8, block=16)
+    assert np.array_equal(A1, A2)

@@ -250,8 +250,8 @@ int sic_prob_create(sic_ctx* ctx, const double* X, int64_t n, int64_t m, double 
 }
 
 void sic_prob_destroy(sic_prob* p) {
-    if (!p) return;
-    (void)hipStreamSynchronize(p->ctx->c.stream);
+    // Device buffers are released with hipFree, which waits for pending work;
+    // the owning context is not touched (it may already be destroyed).
     delete p;
 }
 

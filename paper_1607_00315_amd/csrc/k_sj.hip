@@ -24,7 +24,7 @@ constexpr int SJ_PAD = 4;
 // 32 x 32 quadrant as 2 x 2 MFMA 16x16 accumulators.
 // MFMA f64 16x16x4 operand layout: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; the 16x16 result sits in 4 registers per lane as
-// D[4*(l/16) + v][l%16], v = 0..3.
+// D[(l/16) + 4*v][l%16], v = 0..3 (checked with a lane-layout probe).
 __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ X, int64_t n,
                                                      int64_t m, int64_t j0, int b,
                                                      double* __restrict__ out, double invm) {
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ 
         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + v;
+                const int64_t i = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * v;
                 const int c = c0 + wc * 32 + bb * 16 + (lane & 15);
                 if (i < n && c < b) out[i * b + c] = acc[a][bb][v] * invm;
             }

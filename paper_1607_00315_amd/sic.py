@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import weakref
 
 import numpy as np
 
@@ -125,6 +126,14 @@ def lib():
     """Load libsic.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime (same soname as the system one).
+        # Loading it first makes libsic.so bind to that runtime, so device
+        # pointers and streams from torch are valid here and a single HIP
+        # runtime lives in the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1607_00315_amd.build` (no CPU fallback exists)")
@@ -206,12 +215,15 @@ class Context:
             o.trace = ct.cast(self._trace, ct.POINTER(TraceEntry))
             o.trace_cap = trace_cap
         self._opts = o
+        self._probs = weakref.WeakSet()
         h = ct.c_void_p()
         _check(lib().sic_create(ct.byref(h), ct.byref(o)), "sic_create")
         self.h = h
 
     def close(self):
         if getattr(self, "h", None):
+            for p in list(self._probs):
+                p.close()
             lib().sic_destroy(self.h)
             self.h = None
 
@@ -286,6 +298,7 @@ class Prob:
         _check(lib().sic_prob_create(ctx.h, _data_ptr(X), self.n, self.m, float(lam), ct.byref(h)),
                "sic_prob_create")
         self.h = h
+        ctx._probs.add(self)
 
     def close(self):
         if getattr(self, "h", None):

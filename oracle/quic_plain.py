@@ -91,8 +91,12 @@ def linesearch_dense(A, D, S, lam, i_max: int = 30, beta: float = 0.5):
 
 
 def solve(S: np.ndarray, lam: float, tol: float = 1e-10, max_iter: int = 200,
-          A0: np.ndarray | None = None, verbose: bool = False):
-    """Return (A*, info) with info['history'] = [(iter, F, kkt_max, nnz, seconds)]."""
+          A0: np.ndarray | None = None, verbose: bool = False, max_seconds: float | None = None):
+    """Return (A*, info) with info['history'] = [(iter, F, kkt_max, nnz, seconds)].
+
+    ``seconds`` is the time spent before the iteration's own work; with
+    ``max_seconds`` the loop stops at the first iteration start past it.
+    """
     S = np.asarray(S, dtype=np.float64)
     n = S.shape[0]
     A = np.eye(n) if A0 is None else np.array(A0, dtype=np.float64, copy=True)
@@ -110,6 +114,8 @@ def solve(S: np.ndarray, lam: float, tol: float = 1e-10, max_iter: int = 200,
         if verbose:
             print(f"[oracle] it={it} F={F:.15e} kkt={kkt:.3e} nnz={np.count_nonzero(A)}", flush=True)
         if kkt <= tol:
+            break
+        if max_seconds is not None and hist[-1][4] >= max_seconds:
             break
         mask = np.triu(free_mask(G, A, lam))
         ri, ci = np.nonzero(mask)

@@ -22,16 +22,18 @@
 //      the next column.
 // One workgroup per block: the chain is inherently sequential; everything
 // around it is spread over 8 waves.
-#include "sic_internal.h"
+#include "profiler.h"
 
 namespace sic {
 
 namespace {
 
-constexpr int CD_THREADS = 512;
+constexpr int CD_THREADS = 1024;
 constexpr int CD_WAVES = CD_THREADS / 64;
 constexpr int CD_CHUNK = 64;
 constexpr int CD_WPAD = CD_CHUNK + 1;
+constexpr int CD_COLCAP = 1024;   // steps of one column staged in LDS for the fold
+constexpr int CD_MAXB = 256;      // largest block
 
 __device__ inline double readlane_d(double v, int l) {
     const long long bits = __double_as_longlong(v);
@@ -84,12 +86,21 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(
     const double* __restrict__ c_inva, const double* __restrict__ c_wtc,
     const double* __restrict__ WJJ, double lam, int max_sweeps, double tol,
     double* __restrict__ U, double* __restrict__ delta, double* __restrict__ mu_col,
-    double* __restrict__ ug, double* __restrict__ stats) {
+    double* __restrict__ ug, unsigned char* __restrict__ markg, double* __restrict__ stats) {
     extern __shared__ double sm[];
-    double* zs = sm;                          // [CD_CHUNK]
-    double* wcs = zs + CD_CHUNK;              // [CD_CHUNK]
-    double* ws = wcs + CD_CHUNK;              // [CD_CHUNK][CD_WPAD]
-    double* u = U_IN_LDS ? ws + CD_CHUNK * CD_WPAD : ug;   // [jp]
+    double* zs = sm;                              // [CD_CHUNK] dots of the chunk
+    double* wcs = zs + CD_CHUNK;                  // [CD_CHUNK] W_{r_k, c}
+    double* ws = wcs + CD_CHUNK;                  // [CD_CHUNK][CD_WPAD] W among the chunk
+    double* cs_inva = ws + CD_CHUNK * CD_WPAD;    // [CD_CHUNK] chunk coordinate data
+    double* cs_S = cs_inva + CD_CHUNK;
+    double* cs_A = cs_S + CD_CHUNK;
+    double* cs_d = cs_A + CD_CHUNK;
+    int* cs_p = (int*)(cs_d + CD_CHUNK);          // [CD_CHUNK]
+    double* colmu = cs_d + CD_CHUNK + CD_CHUNK / 2;   // [CD_COLCAP] steps of the column
+    int* colp = (int*)(colmu + CD_COLCAP);        // [CD_COLCAP]
+    double* wc_row = colmu + CD_COLCAP + CD_COLCAP / 2;   // [CD_MAXB] W_{c, I}
+    double* u = U_IN_LDS ? wc_row + CD_MAXB : ug;         // [jp] U[:, c]
+    unsigned char* mark = U_IN_LDS ? (unsigned char*)(u + jp) : markg;   // [jp]
     __shared__ double s_red[CD_WAVES];
     __shared__ int s_stop;
     __shared__ double s_maxmu;
@@ -97,84 +108,165 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+    for (int q = tid; q < jp; q += CD_THREADS) mark[q] = 0;
+    __syncthreads();
     int sweeps = 0;
     double maxmu = 0.0;
+    // phase clocks (thread 0): u load, staging + dots, chain, fold
+    long long tph[4] = {0, 0, 0, 0};
+    long long tlast = wall_clock64();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         maxmu = 0.0;   // meaningful in wave 0
         for (int ci = 0; ci < b; ++ci) {
             const int64_t t0 = cptr[ci], t1 = cptr[ci + 1];
             if (t0 == t1) continue;
+            const int64_t kc = t1 - t0;
+            // (1) u = U[:, c] and W_{c, I} into LDS
             for (int p = tid; p < jp; p += CD_THREADS) u[p] = U[(int64_t)p * b + ci];
+            for (int q = tid; q < b; q += CD_THREADS) wc_row[q] = WJJ[(int64_t)ci * jp + q];
             __syncthreads();
-            const double wcc = WJJ[(int64_t)ci * jp + ci];
+            if (tid == 0) { const long long now = wall_clock64(); tph[0] += now - tlast; tlast = now; }
+            const double wcc = wc_row[ci];
             for (int64_t k0 = t0; k0 < t1; k0 += CD_CHUNK) {
                 const int K = (int)((t1 - k0) < CD_CHUNK ? (t1 - k0) : CD_CHUNK);
-                // (2) dots z_k = W_{r_k, J'} . u
-                for (int kk = wave; kk < K; kk += CD_WAVES) {
-                    const double* row = WJJ + (int64_t)c_p[k0 + kk] * jp;
-                    double s = 0.0;
-                    for (int q = lane; q < jp; q += 64) s += row[q] * u[q];
-                    s = wave_sum(s);
-                    if (lane == 0) zs[kk] = s;
+                // stage the chunk's coordinate data; mark its rows for the capture below
+                if (tid < K) {
+                    const int p = c_p[k0 + tid];
+                    cs_p[tid] = p;
+                    wcs[tid] = c_wtc[k0 + tid];
+                    cs_inva[tid] = c_inva[k0 + tid];
+                    cs_S[tid] = c_S[k0 + tid];
+                    cs_A[tid] = c_A[k0 + tid];
+                    cs_d[tid] = delta[k0 + tid];
+                    mark[p] = (unsigned char)(tid + 1);
                 }
-                // W among the chunk's rows, and W_{r_k, c}
-                for (int idx = tid; idx < K * K; idx += CD_THREADS) {
-                    const int kk = idx / K, tt = idx - kk * K;
-                    ws[kk * CD_WPAD + tt] =
-                        WJJ[(int64_t)c_p[k0 + kk] * jp + c_p[k0 + tt]];
-                }
-                for (int kk = tid; kk < K; kk += CD_THREADS) wcs[kk] = c_wtc[k0 + kk];
                 __syncthreads();
-                // (3) the serial chain, one coordinate per step
+                // (2) dots z_k = W_{r_k, J'} u, eight independent loads in flight per
+                //     lane; W among the chunk's rows is captured from the same rows
+                for (int kk = wave; kk < K; kk += CD_WAVES) {
+                    const double* row = WJJ + (int64_t)cs_p[kk] * jp;
+                    double* wsk = ws + kk * CD_WPAD;
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                    double a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
+                    int q = lane;
+                    for (; q + 7 * 64 < jp; q += 8 * 64) {
+                        double r[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) r[i] = row[q + 64 * i];
+                        a0 += r[0] * u[q];
+                        a1 += r[1] * u[q + 64];
+                        a2 += r[2] * u[q + 128];
+                        a3 += r[3] * u[q + 192];
+                        a4 += r[4] * u[q + 256];
+                        a5 += r[5] * u[q + 320];
+                        a6 += r[6] * u[q + 384];
+                        a7 += r[7] * u[q + 448];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int mk = mark[q + 64 * i];
+                            if (mk) wsk[mk - 1] = r[i];
+                        }
+                    }
+                    for (; q < jp; q += 64) {
+                        const double r = row[q];
+                        a0 += r * u[q];
+                        const int mk = mark[q];
+                        if (mk) wsk[mk - 1] = r;
+                    }
+                    const double sdot = wave_sum(((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7)));
+                    if (lane == 0) zs[kk] = sdot;
+                }
+                __syncthreads();
+                if (tid == 0) { const long long now = wall_clock64(); tph[1] += now - tlast; tlast = now; }
+                // (3) the serial chain, one coordinate per step; coordinate k's data
+                //     sits in lane k and is broadcast with readlane
                 if (wave == 0) {
-                    double z = lane < K ? zs[lane] : 0.0;
-                    const double wk = lane < K ? wcs[lane] : 0.0;
+                    const bool on = lane < K;
+                    double z = on ? zs[lane] : 0.0;
+                    const double wk = on ? wcs[lane] : 0.0;
+                    const int rp = on ? cs_p[lane] : 0;
+                    const double rinva = on ? cs_inva[lane] : 0.0;
+                    const double rS = on ? cs_S[lane] : 0.0;
+                    const double rA = on ? cs_A[lane] : 0.0;
+                    double rd = on ? cs_d[lane] : 0.0;
+                    double rmu = 0.0;
+                    double wnext = on ? ws[lane * CD_WPAD] : 0.0;
                     for (int tt = 0; tt < K; ++tt) {
-                        const int64_t t = k0 + tt;
-                        const int p = c_p[t];
+                        const double wrow = wnext;
+                        if (tt + 1 < K) wnext = on ? ws[lane * CD_WPAD + tt + 1] : 0.0;
+                        const int p = __builtin_amdgcn_readlane(rp, tt);
                         const double zt = readlane_d(z, tt);
-                        const double wtc = c_wtc[t];
-                        const double inva = c_inva[t];
-                        const double bb = c_S[t] - wtc + zt;
-                        const double d_old = delta[t];
-                        const double x = c_A[t] + d_old;
+                        const double wtc = readlane_d(wk, tt);
+                        const double inva = readlane_d(rinva, tt);
+                        const double d_old = readlane_d(rd, tt);
+                        const double x = readlane_d(rA, tt) + d_old;
+                        const double bb = readlane_d(rS, tt) - wtc + zt;
                         const double y = x - bb * inva;
                         const double thr = lam * inva;
                         const double sh = y > thr ? y - thr : (y < -thr ? y + thr : 0.0);
                         const double mu = sh - x;
                         if (p != ci)
-                            z += mu * (ws[lane * CD_WPAD + tt] * wcc + wk * wtc);
+                            z += mu * (wrow * wcc + wk * wtc);
                         else
                             z += mu * wk * wcc;
-                        if (lane == 0) {
-                            delta[t] = d_old + mu;
-                            mu_col[t] = mu;
-                            u[p] += mu * wcc;
-                            if (p != ci) u[ci] += mu * wtc;
+                        if (lane == tt) {
+                            rd = d_old + mu;
+                            rmu = mu;
                         }
                         maxmu = fmax(maxmu, fabs(mu));
                     }
+                    if (on) {
+                        delta[k0 + lane] = rd;
+                        mu_col[k0 + lane] = rmu;
+                        const int64_t slot = k0 - t0 + lane;
+                        if (slot < CD_COLCAP) {
+                            colmu[slot] = rmu;
+                            colp[slot] = rp;
+                        }
+                        // u_r += mu W_cc for every step (r = c on the diagonal step)
+                        if (rmu != 0.0) u[rp] += rmu * wcc;
+                    }
+                    // u_c += sum over off-diagonal steps of mu W_rc
+                    const double contrib = wave_sum((on && rp != ci) ? rmu * wk : 0.0);
+                    if (lane == 0) u[ci] += contrib;
                 }
+                if (tid < K) mark[cs_p[tid]] = 0;
                 __syncthreads();
+                if (tid == 0) { const long long now = wall_clock64(); tph[2] += now - tlast; tlast = now; }
             }
-            // (4) fold the column's steps into U:  U_r += mu W_c,  U_c += mu W_r
-            for (int q = tid; q < b; q += CD_THREADS) {
-                const double wcq = WJJ[(int64_t)ci * jp + q];
+            // (4) fold the column's steps into U:  U_r += mu W_c for rows r != c, one
+            //     independent update per (coordinate, block column) pair, and
+            //     U_c += sum_t mu_t W_{r_t} with four partial sums per block column
+            {
+                const bool in_lds = kc <= CD_COLCAP;
+#pragma unroll 4
+                for (int64_t idx = tid; idx < kc * b; idx += CD_THREADS) {
+                    const int64_t t = idx / b;
+                    const int q = (int)(idx - t * b);
+                    const double mu = in_lds ? colmu[t] : mu_col[t0 + t];
+                    const int p = in_lds ? colp[t] : c_p[t0 + t];
+                    if (mu != 0.0 && p != ci) U[(int64_t)p * b + q] += mu * wc_row[q];
+                }
+                const int h = tid / CD_MAXB, q = tid - h * CD_MAXB;
                 double acc = 0.0;
-                for (int64_t t = t0; t < t1; ++t) {
-                    const double mu = mu_col[t];
-                    if (mu == 0.0) continue;
-                    const int p = c_p[t];
-                    if (p != ci) {
-                        U[(int64_t)p * b + q] += mu * wcq;
-                        acc += mu * WJJ[(int64_t)p * jp + q];
-                    } else {
-                        acc += mu * wcq;
+                if (q < b) {
+#pragma unroll 4
+                    for (int64_t t = h; t < kc; t += CD_THREADS / CD_MAXB) {
+                        const double mu = in_lds ? colmu[t] : mu_col[t0 + t];
+                        const int p = in_lds ? colp[t] : c_p[t0 + t];
+                        if (mu != 0.0) acc += mu * WJJ[(int64_t)p * jp + q];
                     }
                 }
-                U[(int64_t)ci * b + q] += acc;
+                ws[h * CD_MAXB + q] = acc;
+                __syncthreads();
+                if (h == 0 && q < b) {
+                    double sacc = 0.0;
+                    for (int g2 = 0; g2 < CD_THREADS / CD_MAXB; ++g2) sacc += ws[g2 * CD_MAXB + q];
+                    U[(int64_t)ci * b + q] += sacc;
+                }
             }
             __syncthreads();
+            if (tid == 0) { const long long now = wall_clock64(); tph[3] += now - tlast; tlast = now; }
         }
         // stopping rule: max|mu| <= tol * max|Delta|
         if (tid == 0) s_maxmu = maxmu;
@@ -195,14 +287,18 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(
         ++sweeps;
         if (s_stop) break;
     }
-    if (tid == 0) stats[0] = (double)sweeps;
+    if (tid == 0) {
+        stats[0] = (double)sweeps;
+        for (int i = 0; i < 4; ++i) stats[3 + i] = (double)tph[i];
+    }
 }
 
 }  // namespace
 
 size_t cd_lds_bytes(int jp, bool u_in_lds) {
-    return sizeof(double) * ((size_t)2 * CD_CHUNK + (size_t)CD_CHUNK * CD_WPAD +
-                             (u_in_lds ? (size_t)jp : 0));
+    const size_t fixed = (size_t)6 * CD_CHUNK + CD_CHUNK / 2 + (size_t)CD_CHUNK * CD_WPAD +
+                         (size_t)CD_COLCAP + CD_COLCAP / 2 + CD_MAXB;
+    return sizeof(double) * fixed + (u_in_lds ? (size_t)jp * (sizeof(double) + 1) : 0);
 }
 
 void launch_cd_prep(const int64_t* cptr, int b, int64_t ncoord, const int32_t* c_p,
@@ -217,7 +313,8 @@ void launch_cd_prep(const int64_t* cptr, int b, int64_t ncoord, const int32_t* c
 void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const double* c_S,
                const double* c_A, const double* c_inva, const double* c_wtc, const double* WJJ,
                double lam, int max_sweeps, double tol, double* U, double* delta, double* mu_col,
-               double* ug, double* stats, hipStream_t s) {
+               double* ug, unsigned char* markg, double* stats, hipStream_t s) {
+    prof_begin(KK_CD, s);
     const size_t lds_full = cd_lds_bytes(jp, true);
     const bool in_lds = lds_full <= CD_MAX_LDS_BYTES;
     const size_t lds = cd_lds_bytes(jp, in_lds);
@@ -231,13 +328,14 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
         }
         hipLaunchKernelGGL(k_cd<true>, dim3(1), dim3(CD_THREADS), lds, s, jp, b, cptr, c_p, c_S,
                            c_A, c_inva, c_wtc, WJJ, lam, max_sweeps, tol, U, delta, mu_col, ug,
-                           stats);
+                           markg, stats);
     } else {
         hipLaunchKernelGGL(k_cd<false>, dim3(1), dim3(CD_THREADS), lds, s, jp, b, cptr, c_p, c_S,
                            c_A, c_inva, c_wtc, WJJ, lam, max_sweeps, tol, U, delta, mu_col, ug,
-                           stats);
+                           markg, stats);
     }
     SIC_CHECK_LAUNCH();
+    prof_end(KK_CD, s, 0.0, 0.0);   // latency-bound chain: time only
 }
 
 }  // namespace sic

@@ -6,14 +6,17 @@
 // All k right-hand sides run together on row-major n x k blocks, so that one
 // sparse row of A gathers whole 64-column segments of the direction block
 // (coalesced 512-byte reads) and the per-column CG scalars stay independent.
-// One iteration is two kernels:
-//   spmm:   p = z + beta p,  q = A z + beta q  (= A p),   partial p.q
-//   update: x += alpha p, r -= alpha q, z = D^{-1} r,      partial r.z, r.r
-// The per-column reductions finish in the last workgroup to arrive (a fixed
-// summation order, so results do not depend on scheduling), which also
-// derives alpha, beta and the convergence flag; a converged solve turns the
-// remaining queued launches into no-ops.
-#include "sic_internal.h"
+// One iteration is four launches:
+//   spmm:       p = z + beta p,  q = A z + beta q  (= A p),   partial p.q
+//   fin_alpha:  alpha = r.z / p.q per column (one small workgroup per 64 columns)
+//   update:     x += alpha p, r -= alpha q, z = D^{-1} r,     partial r.z, r.r
+//   fin_beta:   beta = r.z_new / r.z_old, residual norms, convergence per tile
+// The per-column reductions are finished in separate small launches rather
+// than by the last workgroup to arrive: a device-scope fence in every
+// workgroup would write back the L2 of each XCD. Summation order is fixed,
+// so results do not depend on scheduling. Convergence is tracked per
+// 64-column tile; launches for a converged tile return at once.
+#include "profiler.h"
 
 namespace sic {
 
@@ -23,7 +26,8 @@ constexpr int CG_THREADS = 512;     // 8 waves, one matrix row per wave at a tim
 constexpr int CG_WAVES = CG_THREADS / 64;
 constexpr int CG_ROW_TILES = 128;   // row partitions (partials per column)
 
-enum { F_DONE = 0, F_CNT_A = 1, F_CNT_B = 2, F_ITER = 3, F_FIRST = 4 };
+// per-tile control block: [0] done, [1] iterations finished
+enum { T_DONE = 0, T_ITER = 1, T_INTS = 2 };
 enum { S_RZ = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3 };
 
 __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -36,10 +40,10 @@ __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __r
     dinv[i] = d > 0.0 ? 1.0 / d : 1.0;
 }
 
-__global__ void k_cg_init(int64_t n, int k, const int32_t* __restrict__ cols,
+__global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __restrict__ cols,
                           const double* __restrict__ dinv, double* __restrict__ R,
                           double* __restrict__ Z, double* __restrict__ scal,
-                          int* __restrict__ flags) {
+                          int* __restrict__ tctl, double* __restrict__ tres) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < k) {
         const int64_t c = cols[j];
@@ -50,13 +54,10 @@ __global__ void k_cg_init(int64_t n, int k, const int32_t* __restrict__ cols,
         scal[j * 4 + S_BETA] = 0.0;
         scal[j * 4 + S_RR] = 1.0;
     }
-    if (j == 0) {
-        flags[F_DONE] = 0;
-        flags[F_CNT_A] = 0;
-        flags[F_CNT_B] = 0;
-        flags[F_ITER] = 0;
-        flags[F_FIRST] = 1;
-        scal[4 * k] = 1.0;
+    if (j < col_tiles) {
+        tctl[j * T_INTS + T_DONE] = 0;
+        tctl[j * T_INTS + T_ITER] = 0;
+        tres[j] = 1.0;
     }
 }
 
@@ -65,10 +66,10 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadId
 __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, int64_t n, int k, const double* __restrict__ Z,
-    double* __restrict__ P, double* __restrict__ Q, double* __restrict__ scal,
-    double* __restrict__ part, int* __restrict__ flags) {
-    if (__builtin_nontemporal_load(&flags[F_DONE])) return;
-    const bool first = flags[F_FIRST] != 0;
+    double* __restrict__ P, double* __restrict__ Q, const double* __restrict__ scal,
+    double* __restrict__ part, const int* __restrict__ tctl) {
+    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
+    const bool first = tctl[blockIdx.x * T_INTS + T_ITER] == 0;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
     const int j = blockIdx.x * 64 + lane;
@@ -95,7 +96,6 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
         }
     }
     __shared__ double red[CG_WAVES][64];
-    __shared__ int last;
     red[wave][lane] = pq;
     __syncthreads();
     if (wave == 0) {
@@ -103,28 +103,35 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
         for (int w = 0; w < CG_WAVES; ++w) s += red[w][lane];
         if (jok) part[(int64_t)blockIdx.y * k + j] = s;
     }
-    __threadfence();
+}
+
+// alpha = r.z / p.q for the 64 columns of tile blockIdx.x (4 partial sums per column)
+__global__ __launch_bounds__(256) void k_cg_fin_alpha(int k, int row_tiles,
+                                                      const double* __restrict__ part,
+                                                      double* __restrict__ scal,
+                                                      const int* __restrict__ tctl) {
+    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    double s = 0.0;
+    if (j < k)
+        for (int t = g; t < row_tiles; t += 4) s += part[(int64_t)t * k + j];
+    red[g][c] = s;
     __syncthreads();
-    if (threadIdx.x == 0)
-        last = atomicAdd(&flags[F_CNT_A], 1) == (int)(gridDim.x * gridDim.y) - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    for (int jj = threadIdx.x; jj < k; jj += CG_THREADS) {
-        double s = 0.0;
-        for (unsigned t = 0; t < gridDim.y; ++t) s += part[(int64_t)t * k + jj];
-        const double rz = scal[jj * 4 + S_RZ];
-        scal[jj * 4 + S_ALPHA] = (s > 0.0 && rz > 0.0) ? rz / s : 0.0;
+    if (g == 0 && j < k) {
+        const double pq = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+        const double rz = scal[j * 4 + S_RZ];
+        scal[j * 4 + S_ALPHA] = (pq > 0.0 && rz > 0.0) ? rz / pq : 0.0;
     }
-    if (threadIdx.x == 0) flags[F_CNT_A] = 0;
 }
 
 __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     int64_t n, int k, const double* __restrict__ dinv, double* __restrict__ W,
     double* __restrict__ R, double* __restrict__ Z, const double* __restrict__ P,
-    const double* __restrict__ Q, double* __restrict__ scal, double* __restrict__ part,
-    int* __restrict__ flags, double tol) {
-    if (__builtin_nontemporal_load(&flags[F_DONE])) return;
+    const double* __restrict__ Q, const double* __restrict__ scal, double* __restrict__ part,
+    const int* __restrict__ tctl) {
+    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
     const int j = blockIdx.x * 64 + lane;
@@ -145,8 +152,6 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
         }
     }
     __shared__ double red[2][CG_WAVES][64];
-    __shared__ int last;
-    __shared__ double wmax[CG_WAVES];
     red[0][wave][lane] = rz;
     red[1][wave][lane] = rr;
     __syncthreads();
@@ -161,37 +166,46 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
             part[((int64_t)blockIdx.y * k + j) * 2 + 1] = s1;
         }
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0)
-        last = atomicAdd(&flags[F_CNT_B], 1) == (int)(gridDim.x * gridDim.y) - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double mx = 0.0;
-    for (int jj = threadIdx.x; jj < k; jj += CG_THREADS) {
-        double s0 = 0.0, s1 = 0.0;
-        for (unsigned t = 0; t < gridDim.y; ++t) {
-            s0 += part[((int64_t)t * k + jj) * 2 + 0];
-            s1 += part[((int64_t)t * k + jj) * 2 + 1];
+}
+
+// beta, new r.z, residual norms; the tile converges when every column's
+// relative residual ||r_j|| / ||e_j|| = ||r_j|| is at most tol.
+__global__ __launch_bounds__(256) void k_cg_fin_beta(int k, int row_tiles,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ scal,
+                                                     int* __restrict__ tctl,
+                                                     double* __restrict__ tres, double tol) {
+    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
+    __shared__ double red[2][4][64];
+    __shared__ double mx[64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    double s0 = 0.0, s1 = 0.0;
+    if (j < k)
+        for (int t = g; t < row_tiles; t += 4) {
+            s0 += part[((int64_t)t * k + j) * 2 + 0];
+            s1 += part[((int64_t)t * k + j) * 2 + 1];
         }
-        const double rz_old = scal[jj * 4 + S_RZ];
-        scal[jj * 4 + S_BETA] = rz_old > 0.0 ? s0 / rz_old : 0.0;
-        scal[jj * 4 + S_RZ] = s0;
-        scal[jj * 4 + S_RR] = s1;
-        mx = fmax(mx, sqrt(s1));
-    }
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    if (lane == 0) wmax[wave] = mx;
+    red[0][g][c] = s0;
+    red[1][g][c] = s1;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int w = 0; w < CG_WAVES; ++w) m = fmax(m, wmax[w]);
-        scal[4 * k] = m;
-        flags[F_ITER] += 1;
-        flags[F_FIRST] = 0;
-        flags[F_CNT_B] = 0;
-        if (m <= tol) flags[F_DONE] = 1;
+    if (g == 0) {
+        double res = 0.0;
+        if (j < k) {
+            const double rz = (red[0][0][c] + red[0][1][c]) + (red[0][2][c] + red[0][3][c]);
+            const double rr = (red[1][0][c] + red[1][1][c]) + (red[1][2][c] + red[1][3][c]);
+            const double rz_old = scal[j * 4 + S_RZ];
+            scal[j * 4 + S_BETA] = rz_old > 0.0 ? rz / rz_old : 0.0;
+            scal[j * 4 + S_RZ] = rz;
+            scal[j * 4 + S_RR] = rr;
+            res = sqrt(rr);
+        }
+        for (int off = 32; off > 0; off >>= 1) res = fmax(res, __shfl_xor(res, off, 64));
+        if (c == 0) {
+            tres[blockIdx.x] = res;
+            tctl[blockIdx.x * T_INTS + T_ITER] += 1;
+            if (res <= tol) tctl[blockIdx.x * T_INTS + T_DONE] = 1;
+        }
     }
 }
 
@@ -216,42 +230,99 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
     int row_tiles = (int)std::min<int64_t>(CG_ROW_TILES, (n + CG_WAVES - 1) / CG_WAVES);
     if (row_tiles < 1) row_tiles = 1;
     wk.part.reserve((size_t)row_tiles * k * 2);
-    wk.scal.reserve((size_t)4 * k + 1);
-    wk.flags.reserve(8);
+    wk.scal.reserve((size_t)4 * k + col_tiles);
+    wk.flags.reserve((size_t)T_INTS * col_tiles);
+    double* tres = wk.scal.p + 4 * k;
     SIC_HIP(hipMemsetAsync(W, 0, nk * sizeof(double), s));
     SIC_HIP(hipMemsetAsync(wk.R.p, 0, nk * sizeof(double), s));
     SIC_HIP(hipMemsetAsync(wk.Z.p, 0, nk * sizeof(double), s));
     hipLaunchKernelGGL(k_cg_dinv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        A.rowptr.p, A.col.p, A.val.p, n, wk.dinv.p);
     SIC_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, n, k, d_cols,
-                       wk.dinv.p, wk.R.p, wk.Z.p, wk.scal.p, wk.flags.p);
+    const int init_n = std::max(k, col_tiles);
+    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0, s, n, k,
+                       col_tiles, d_cols, wk.dinv.p, wk.R.p, wk.Z.p, wk.scal.p, wk.flags.p, tres);
     SIC_CHECK_LAUNCH();
     dim3 grid(col_tiles, row_tiles);
-    int host_flags[8];
-    double host_res = 0.0;
+    std::vector<int> hctl((size_t)T_INTS * col_tiles);
+    std::vector<double> hres(col_tiles);
     int launched = 0;
-    while (launched < max_iter) {
+    int active = col_tiles;   // tiles still iterating (as of the last check)
+    // algorithmic traffic of one tile-launch (bytes): the sparse matrix once,
+    // each n x 64 block touched once per read or write
+    const double mat = (double)A.nnz * 12.0 + (double)(n + 1) * 8.0;
+    struct Rec {
+        int64_t spmm, upd;
+        int iter;
+    };
+    std::vector<Rec> recs;
+    bool done = false;
+    while (launched < max_iter && !done) {
         const int chunk = std::min(launched < 16 ? 4 : 8, max_iter - launched);
+        recs.clear();
         for (int c = 0; c < chunk; ++c) {
+            const int it = launched + c;
+            const double nkb = (double)n * k * 8.0;
+            Rec r;
+            r.iter = it;
+            prof_begin(KK_CG_SPMM, s);
             hipLaunchKernelGGL(k_cg_spmm, grid, dim3(CG_THREADS), 0, s, A.rowptr.p, A.col.p,
                                A.val.p, n, k, wk.Z.p, wk.P.p, wk.Q.p, wk.scal.p, wk.part.p,
                                wk.flags.p);
             SIC_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_cg_update, grid, dim3(CG_THREADS), 0, s, n, k, wk.dinv.p, W,
-                               wk.R.p, wk.Z.p, wk.P.p, wk.Q.p, wk.scal.p, wk.part.p, wk.flags.p,
-                               tol);
+            r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
+                              2.0 * A.nnz * k + 4.0 * n * k);
+            hipLaunchKernelGGL(k_cg_fin_alpha, dim3(col_tiles), dim3(256), 0, s, k, row_tiles,
+                               wk.part.p, wk.scal.p, wk.flags.p);
             SIC_CHECK_LAUNCH();
+            prof_begin(KK_CG_UPDATE, s);
+            hipLaunchKernelGGL(k_cg_update, grid, dim3(CG_THREADS), 0, s, n, k, wk.dinv.p, W,
+                               wk.R.p, wk.Z.p, wk.P.p, wk.Q.p, wk.scal.p, wk.part.p, wk.flags.p);
+            SIC_CHECK_LAUNCH();
+            r.upd = prof_end(KK_CG_UPDATE, s, 7.0 * nkb + n * 8.0, 10.0 * n * k);
+            hipLaunchKernelGGL(k_cg_fin_beta, dim3(col_tiles), dim3(256), 0, s, k, row_tiles,
+                               wk.part.p, wk.scal.p, wk.flags.p, tres, tol);
+            SIC_CHECK_LAUNCH();
+            recs.push_back(r);
         }
         launched += chunk;
-        SIC_HIP(hipMemcpyAsync(host_flags, wk.flags.p, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(&host_res, wk.scal.p + 4 * k, sizeof(double), hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(hctl.data(), wk.flags.p, sizeof(int) * hctl.size(),
+                               hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(hres.data(), tres, sizeof(double) * col_tiles,
+                               hipMemcpyDeviceToHost, s));
         SIC_HIP(hipStreamSynchronize(s));
-        if (host_flags[F_DONE]) break;
+        // a launch did work only for the tiles still iterating at its index:
+        // scale its algorithmic bytes, drop launches that found nothing to do
+        for (const Rec& r : recs) {
+            int working = 0;
+            for (int t = 0; t < col_tiles; ++t) working += hctl[t * T_INTS + T_ITER] > r.iter;
+            if (working == 0) {
+                prof_discard(r.spmm);
+                prof_discard(r.upd);
+            } else if (working < col_tiles) {
+                prof_scale(r.spmm, (double)working / col_tiles);
+                prof_scale(r.upd, (double)working / col_tiles);
+            }
+        }
+        done = true;
+        active = 0;
+        for (int t = 0; t < col_tiles; ++t)
+            if (!hctl[t * T_INTS + T_DONE]) {
+                done = false;
+                ++active;
+            }
     }
-    res.iterations = host_flags[F_ITER];
-    res.converged = host_flags[F_DONE] != 0;
-    res.max_rel_res = host_res;
+    (void)active;
+    prof_flush();
+    int iters = 0;
+    double mres = 0.0;
+    for (int t = 0; t < col_tiles; ++t) {
+        iters = std::max(iters, hctl[t * T_INTS + T_ITER]);
+        mres = std::max(mres, hres[t]);
+    }
+    res.iterations = iters;
+    res.converged = done;
+    res.max_rel_res = mres;
     return res;
 }
 

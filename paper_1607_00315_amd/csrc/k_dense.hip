@@ -11,7 +11,7 @@
 // and A + alpha Delta > 0 iff that matrix is PD (eq. (Schurs_PDness)).  The
 // Cholesky of I + E keeps the identity implicit and sums log1p of the pivots,
 // so the change keeps full relative accuracy however small the step.
-#include "sic_internal.h"
+#include "profiler.h"
 
 namespace sic {
 
@@ -342,8 +342,10 @@ void launch_identity_minus(const double* K, int b, double* out, hipStream_t s) {
 void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,
                  hipStream_t s) {
     if (nb > CH_NB) throw SicError(SIC_ETOOBIG, "block larger than the Cholesky kernel supports");
+    prof_begin(KK_CHOL, s);
     hipLaunchKernelGGL(k_chol, dim3(batch), dim3(1024), 0, s, M, stride, nb, ld, identity, out);
     SIC_CHECK_LAUNCH();
+    prof_end(KK_CHOL, s, 16.0 * nb * nb * (double)batch, (double)nb * nb * nb / 3.0 * batch);
 }
 
 void launch_trsm_lower(const double* L, int nb, int ldl, double* B, int ncols, int ldb, int trans,
@@ -359,9 +361,11 @@ void launch_gemm_small(int M, int N, int K, double alpha, const double* A, int l
                        hipStream_t s) {
     if (M <= 0 || N <= 0) return;
     dim3 grid((unsigned)((N + 15) / 16), (unsigned)((M + 15) / 16));
+    prof_begin(KK_GEMM, s);
     hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb,
                        beta, C, ldc);
     SIC_CHECK_LAUNCH();
+    prof_end(KK_GEMM, s, 8.0 * ((double)M * K + (double)K * N + 2.0 * M * N), 2.0 * (double)M * N * K);
 }
 
 void launch_copy_block(const double* src, int ld, int nb, double* dst, hipStream_t s) {

@@ -8,7 +8,7 @@
 // column-major order (column c ascending, row r ascending), both triangles of
 // the in-block part included; the descent coordinates are the subset with
 // r outside I or r <= c.
-#include "sic_internal.h"
+#include "profiler.h"
 
 namespace sic {
 
@@ -335,9 +335,12 @@ void launch_screen_fine(int pass, int64_t n, int64_t j0, int b, int rows_per_til
                         int32_t* tilecount, const int32_t* offsets, int32_t* e_row, double* e_g,
                         double* e_s, double* e_a, double* e_w, int32_t* nflag, double* kkt,
                         hipStream_t s) {
+    prof_begin(KK_SCREEN, s);
     hipLaunchKernelGGL(k_screen_fine, dim3(tiles), dim3(256), 0, s, pass, n, j0, b, rows_per_tile,
                        lam, SJ, WI, AJ, tilecount, offsets, e_row, e_g, e_s, e_a, e_w, nflag, kkt);
     SIC_CHECK_LAUNCH();
+    // algorithmic: S_J, W_I (when present) and A_J read once
+    prof_end(KK_SCREEN, s, (double)n * b * 8.0 * (WI ? 3.0 : 2.0), 4.0 * (double)n * b);
 }
 
 void launch_kkt_accumulate(const double* kkt, int tiles, double* acc, hipStream_t s) {

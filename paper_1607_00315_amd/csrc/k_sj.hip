@@ -8,7 +8,7 @@
 // X is m x n row-major float64.  The dense block is an MFMA contraction over
 // the m samples (v_mfma_f64_16x16x4f64); sampled entries are wave-wide dot
 // products over rows of the transposed copy Xt (n x m row-major).
-#include "sic_internal.h"
+#include "profiler.h"
 
 namespace sic {
 
@@ -137,8 +137,11 @@ __global__ __launch_bounds__(256) void k_sddmm(const double* __restrict__ Xt, in
 void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b, double* out,
                         hipStream_t s) {
     dim3 grid((unsigned)((n + SJ_TILE - 1) / SJ_TILE), (unsigned)((b + SJ_TILE - 1) / SJ_TILE));
+    prof_begin(KK_SJ, s);
     hipLaunchKernelGGL(k_sj_gemm_f64, grid, dim3(256), 0, s, X, n, m, j0, b, out, 1.0 / (double)m);
     SIC_CHECK_LAUNCH();
+    // algorithmic: X read once (m x n) and S_J written once; 2 n b m flops
+    prof_end(KK_SJ, s, 8.0 * ((double)m * n + (double)n * b), 2.0 * (double)n * b * m);
 }
 
 void launch_transpose(const double* X, int64_t m, int64_t n, double* Xt, hipStream_t s) {
@@ -156,9 +159,11 @@ void launch_diag_s(const double* Xt, int64_t n, int64_t m, double* d, hipStream_
 void launch_sddmm(const double* Xt, int64_t m, const int32_t* rows, const int32_t* cols,
                   int64_t count, double* out, hipStream_t s) {
     if (count <= 0) return;
+    prof_begin(KK_SDDMM, s);
     hipLaunchKernelGGL(k_sddmm, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, s, Xt, m, rows,
                        cols, count, out, 1.0 / (double)m);
     SIC_CHECK_LAUNCH();
+    prof_end(KK_SDDMM, s, 16.0 * (double)m * count + 16.0 * count, 2.0 * (double)m * count);
 }
 
 }  // namespace sic

@@ -152,7 +152,7 @@ void launch_cd_prep(const int64_t* cptr, int b, int64_t ncoord, const int32_t* c
 void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const double* c_S,
                const double* c_A, const double* c_inva, const double* c_wtc, const double* WJJ,
                double lam, int max_sweeps, double tol, double* U, double* delta, double* mu_col,
-               double* ug, double* stats, hipStream_t s);
+               double* ug, unsigned char* markg, double* stats, hipStream_t s);
 
 // ---------------------------------------------------------------- k_dense.hip
 void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,

@@ -20,6 +20,7 @@ struct Options {
 // Scratch of one block update; sized on demand, reused across blocks.
 struct BlockWork {
     DevBuf<double> SJ, WI, AJ, ANEW, WN, WJJ, U, ug;
+    DevBuf<unsigned char> markg;
     DevBuf<int32_t> cols;
     // free lists
     DevBuf<int64_t> colptr;

@@ -461,12 +461,13 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     // (d) coordinate descent
     W.U.reserve((size_t)jp * b);
     W.ug.reserve(jp);
-    W.cdstats.reserve(4);
+    W.markg.reserve(jp);
+    W.cdstats.reserve(8);
     SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
     launch_cd_prep(W.cptr.p, b, nc, W.c_p.p, W.WJJ.p, jp, W.c_ci.p, W.c_a.p, W.c_inva.p, W.c_wtc.p,
                    W.c_wtt.p, W.delta.p, s);
     launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, P.lam,
-              C.opt.cd_max_sweeps, C.opt.cd_tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.cdstats.p, s);
+              C.opt.cd_max_sweeps, C.opt.cd_tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
     double cds[3];
     SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
     // (e) line search
@@ -823,7 +824,8 @@ static void load_coords(Context& C, int jp, int b, const double* wjj, const int6
     W.delta.reserve(ncs); W.mu.reserve(ncs);
     W.U.reserve((size_t)jp * b);
     W.ug.reserve(jp);
-    W.cdstats.reserve(4);
+    W.markg.reserve(jp);
+    W.cdstats.reserve(8);
     SIC_HIP(hipMemcpyAsync(W.WJJ.p, wjj, sizeof(double) * jp * jp, hipMemcpyHostToDevice, s));
     SIC_HIP(hipMemcpyAsync(W.cptr.p, cptr, sizeof(int64_t) * (b + 1), hipMemcpyHostToDevice, s));
     if (nc) {
@@ -844,12 +846,12 @@ int step_cd_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cp
     const int64_t nc = cptr[b];
     SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
     launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, lambda,
-              max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.cdstats.p, s);
+              max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
     if (nc) SIC_HIP(hipMemcpyAsync(delta_out, W.delta.p, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-    double st[3];
-    SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    double st[7];
+    SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     sync(C);
-    if (stats_out) std::copy(st, st + 3, stats_out);
+    if (stats_out) std::copy(st, st + 7, stats_out);
     return SIC_OK;
 }
 

@@ -117,6 +117,10 @@ SIGNATURES = {
     "sic_step_linesearch": (ct.c_int, [_P, ct.c_int, ct.c_int, _dp, _i64p, _i32p, _dp, _dp, _dp,
                                        ct.c_double, _dp, _dp, ct.POINTER(ct.c_int), _dp,
                                        ct.c_int]),
+    "sic_profile_enable": (None, [ct.c_int]),
+    "sic_profile_reset": (None, []),
+    "sic_profile_read": (ct.c_int, [ct.c_int, _i64p, _dp, _dp, _dp]),
+    "sic_profile_kernel_name": (ct.c_char_p, [ct.c_int]),
     "sic_hierarchy": (ct.c_int, [ct.c_int64, _i64p, ct.c_int64, _i64p, _dp, ct.c_int64, _i64p,
                                  _i64p, _i64p, ct.POINTER(ct.c_int)]),
 }
@@ -394,7 +398,7 @@ def step_cd(ctx: Context, wjj, b, cptr, cp, S, A, lam, max_sweeps=20, tol=1e-4):
     A = np.ascontiguousarray(A, dtype=np.float64)
     nc = int(cptr[-1])
     out = np.empty(max(nc, 1))
-    st = np.empty(3)
+    st = np.empty(7)
     _check(lib().sic_step_cd(ctx.h, wjj.shape[0], b, _ptr(wjj, ct.c_double),
                              _ptr(cptr, ct.c_int64), _ptr(cp, ct.c_int32), _ptr(S, ct.c_double),
                              _ptr(A, ct.c_double), float(lam), int(max_sweeps), float(tol),
@@ -433,3 +437,27 @@ def hierarchy(n, supp_keys, free_keys, free_absg):
                                _ptr(g, ct.c_double), f.size, _ptr(rank, ct.c_int64),
                                ct.byref(rlen), _ptr(sizes, ct.c_int64), ct.byref(nl)), "hierarchy")
     return rank[:rlen.value], list(sizes[:nl.value])
+
+
+KERNEL_CLASSES = 9
+
+
+def profile_enable(on=True):
+    lib().sic_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().sic_profile_reset()
+
+
+def profile_read():
+    """{kernel name: dict(launches, ms, bytes, flops)} since the last reset."""
+    out = {}
+    for k in range(KERNEL_CLASSES):
+        n = ct.c_int64()
+        ms, by, fl = ct.c_double(), ct.c_double(), ct.c_double()
+        _check(lib().sic_profile_read(k, ct.byref(n), ct.byref(ms), ct.byref(by), ct.byref(fl)),
+               "profile_read")
+        out[lib().sic_profile_kernel_name(k).decode()] = dict(
+            launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+    return out

@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--cd-max-sweeps", type=int, default=0, help="0: library default")
+    ap.add_argument("--cd-tol", type=float, default=0.0, help="0: library default")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
@@ -139,12 +141,18 @@ def main():
     Xd = torch.from_numpy(X).to("cuda:0")
     torch.cuda.synchronize()
 
-    ctx = sic.Context(block=b, trace_cap=256)
+    solver_opts = dict(block=b)
+    if args.cd_max_sweeps:
+        solver_opts["cd_max_sweeps"] = args.cd_max_sweeps
+    if args.cd_tol:
+        solver_opts["cd_tol"] = args.cd_tol
+    ctx = sic.Context(trace_cap=256, **solver_opts)
     # calibration: solve to KKT <= 1e-6, cycle trace of the tracked objective
     t = time.perf_counter()
     (rp, col, val), info, trace = ctx.solve(Xd, lam, 1e-6)
     t_kkt = time.perf_counter() - t
     F_final = exact_objective(rp, col, val, Xd, lam)
+    sup_kkt = bool(np.array_equal(support_keys(rp, col), gkeys))
     drift = abs(info["objective"] - F_final)
     log(f"calibration: {info['cycles']} cycles, {t_kkt:.2f}s to KKT {info['kkt_max']:.2e}, "
         f"F exact {F_final:.12e} (F* {Fstar:.12e}), tracked drift {drift:.2e}")
@@ -155,7 +163,7 @@ def main():
             break
     # verify c* with the exact objective of the iterate after c* cycles
     while True:
-        ctx_c = sic.Context(block=b, max_cycles=cstar)
+        ctx_c = sic.Context(max_cycles=cstar, **solver_opts)
         (rp, col, val), info_c, _ = ctx_c.solve(Xd, lam, 1e-12)
         gap = (exact_objective(rp, col, val, Xd, lam) - Fstar) / abs(Fstar)
         log(f"c*={cstar}: exact gap {gap:.3e}")
@@ -210,8 +218,10 @@ def main():
         ms_per_step=value * 1e3, higher_is_better=False, scaling="strong", vs_baseline=None,
         dtype="f64", data="synthetic",
         config=dict(workload=name, graph=spec["kind"], n=int(X.shape[1]), m=int(X.shape[0]),
-                    **{"lambda": lam}, block=b, cycles=cstar, x_layout="m x n row-major f64"),
-        gap=gap, F_star=Fstar, support_identical=bool(np.array_equal(keys, gkeys)),
+                    **{"lambda": lam}, block=b, cycles=cstar, x_layout="m x n row-major f64",
+                    cd_max_sweeps=args.cd_max_sweeps or 20, cd_tol=args.cd_tol or 1e-4),
+        gap=gap, F_star=Fstar, support_identical_at_gap=bool(np.array_equal(keys, gkeys)),
+        support_identical_at_kkt=sup_kkt,
         nnz=int(col.size), time_to_kkt_1e6_s=t_kkt, kkt_cycles=info["cycles"],
         kkt_max=info["kkt_max"], roofline=roofline, cpu_baseline=cpu,
         kernels={k: dict(launches=v["launches"], ms=round(v["ms"], 3),

@@ -23,99 +23,215 @@ constexpr int CH_PMAX = CH_NB - CH_T;
 constexpr int CH_PLD = CH_T + 1;  // padded panel row
 
 // In-place lower Cholesky of one nb x nb matrix per workgroup (batch over
-// blockIdx.x, matrices `stride` doubles apart, leading dimension ld), tiled
-// right-looking with 32-wide tiles: factor the diagonal tile in LDS, solve
-// the panel below it with the rows held in registers, then update the
-// trailing lower triangle from the panel staged in LDS.
+// blockIdx.x, matrices `stride` doubles apart, leading dimension ld).
+// The lower triangle is held in registers as 32 x 32 tiles: thread
+// (ti, tj), ti < 16, owns entries (ti, tj) and (ti + 16, tj) of each of the 36
+// lower tiles of a 256 x 256 matrix (144 VGPRs at two waves per SIMD).
+// Per tile column kb:
+//   1. the diagonal tile goes to LDS, where one wave factors it and inverts
+//      the factor (LDS operations of one wave execute in order),
+//   2. each panel tile below is staged in LDS and multiplied by L_kk^{-T},
+//   3. the trailing lower tiles are updated in registers from the panel in LDS.
+// Global memory is touched only by the initial load and the final store.
 // identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
-// out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0.  Only the lower
-// triangle is read and the factor overwrites it.
-__global__ __launch_bounds__(1024) void k_chol(double* __restrict__ M, int64_t stride, int nb,
-                                               int ld, int identity, double* __restrict__ out) {
-    __shared__ double lds[CH_PMAX * CH_PLD];
-    __shared__ double ldiag[CH_T];
-    __shared__ double xbuf[CH_PMAX];
-    double* A = M + (int64_t)blockIdx.x * stride;
-    const int tid = threadIdx.x;
-    const int ti = tid / CH_T, tj = tid % CH_T;
-    double logdet = 0.0;
-    int bad = 0;
-    for (int k0 = 0; k0 < nb && !bad; k0 += CH_T) {
-        const int kw = nb - k0 < CH_T ? nb - k0 : CH_T;
-        double* D = lds;   // diagonal tile, D[i * CH_PLD + j]
-        D[ti * CH_PLD + tj] = (ti < kw && tj < kw && tj <= ti) ? A[(int64_t)(k0 + ti) * ld + k0 + tj] : 0.0;
-        __syncthreads();
-        for (int k = 0; k < kw; ++k) {
-            const double t = D[k * CH_PLD + k];
+// out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0. Only the lower
+// triangle is read; the factor overwrites it and the upper triangle is zeroed.
+__device__ constexpr int tslot(int bi, int bj) { return bi * (bi + 1) / 2 + bj; }
+
+constexpr int CH_THREADS = 512;
+constexpr int CH_NT = CH_NB / CH_T;
+
+struct CholShared {
+    double D[CH_T * CH_PLD];           // diagonal tile, then its factor (lower)
+    double Li[CH_T * CH_PLD];          // inverse of the diagonal factor (lower)
+    double Pn[CH_NT][CH_T * CH_PLD];   // panel tiles of the current tile column
+    int bad;
+    double logdet;
+};
+
+// Tile column KB of the register-resident factorization. Written as a
+// template so that every register tile index is a compile-time constant.
+template <int KB>
+__device__ __forceinline__ void chol_step(double (&reg)[CH_NT * (CH_NT + 1) / 2][2],
+                                          CholShared& sh, int nt, int identity, bool& alive) {
+    constexpr int T = CH_T, NT = CH_NT, PL = CH_PLD, H = T / 2;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int ti = tid / T, tj = tid % T;
+    if (KB >= nt || !alive) return;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = ti + H * h;
+        sh.D[r * PL + tj] = (tj <= r) ? reg[tslot(KB, KB)][h] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double ld_acc = 0.0;
+        int bad = 0;
+        for (int k = 0; k < T; ++k) {
+            const double t = sh.D[k * PL + k];
             const double piv = identity ? 1.0 + t : t;
             if (!(piv > 0.0) || !isfinite(piv)) {
-                bad = 1;   // every thread read the same pivot
+                bad = 1;
                 break;
             }
-            logdet += identity ? log1p(t) : log(t);
+            ld_acc += identity ? log1p(t) : log(t);
             const double lkk = sqrt(piv);
-            if (tid == 0) ldiag[k] = lkk;
-            if (tj == k && ti > k && ti < kw) D[ti * CH_PLD + k] /= lkk;
-            __syncthreads();
-            if (ti > k && tj > k && tj <= ti && ti < kw)
-                D[ti * CH_PLD + tj] -= D[ti * CH_PLD + k] * D[tj * CH_PLD + k];
-            __syncthreads();
-        }
-        if (bad) break;
-        if (ti < kw && tj <= ti)
-            A[(int64_t)(k0 + ti) * ld + k0 + tj] = (tj == ti) ? ldiag[ti] : D[ti * CH_PLD + tj];
-        // panel rows r = p0 + ti + 32 q, column k0 + tj
-        const int p0 = k0 + CH_T;
-        const int pr = nb - p0;
-        if (pr > 0) {
-            double preg[CH_PMAX / CH_T];
-#pragma unroll
-            for (int q = 0; q < CH_PMAX / CH_T; ++q) {
-                const int r = p0 + ti + CH_T * q;
-                preg[q] = (r < nb && tj < kw) ? A[(int64_t)r * ld + k0 + tj] : 0.0;
+            if (lane > k && lane < T) sh.D[lane * PL + k] /= lkk;
+            if (lane == 0) sh.D[k * PL + k] = lkk;
+            for (int idx = lane; idx < T * T; idx += 64) {
+                const int i = idx / T, j = idx - i * T;
+                if (j > k && j <= i) sh.D[i * PL + j] -= sh.D[i * PL + k] * sh.D[j * PL + k];
             }
-            for (int jc = 0; jc < kw; ++jc) {
-                if (tj == jc) {
+        }
+        if (!bad && lane < T) {
+            // Li = D^{-1}: lane j computes column j by forward substitution
+            const int j = lane;
+            for (int i = 0; i < j; ++i) sh.Li[i * PL + j] = 0.0;
+            sh.Li[j * PL + j] = 1.0 / sh.D[j * PL + j];
+            for (int i = j + 1; i < T; ++i) {
+                double sacc = 0.0;
+                for (int q = j; q < i; ++q) sacc += sh.D[i * PL + q] * sh.Li[q * PL + j];
+                sh.Li[i * PL + j] = -sacc / sh.D[i * PL + i];
+            }
+        }
+        if (lane == 0) {
+            sh.logdet += ld_acc;
+            if (bad) sh.bad = 1;
+        }
+    }
+    __syncthreads();
+    alive = !sh.bad;
+    if (!alive) return;
 #pragma unroll
-                    for (int q = 0; q < CH_PMAX / CH_T; ++q) {
-                        preg[q] /= ldiag[jc];
-                        xbuf[ti + CH_T * q] = preg[q];
+    for (int h = 0; h < 2; ++h) {
+        const int r = ti + H * h;
+        reg[tslot(KB, KB)][h] = (tj <= r) ? sh.D[r * PL + tj] : 0.0;
+    }
+    if (KB + 1 >= NT) return;
+    // panel tiles: stage A_(ib,KB), then L_(ib,KB) = A_(ib,KB) L_KB^{-T}
+#pragma unroll
+    for (int ib = KB + 1; ib < NT; ++ib)
+        if (ib < nt)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) sh.Pn[ib][(ti + H * h) * PL + tj] = reg[tslot(ib, KB)][h];
+    __syncthreads();
+#pragma unroll
+    for (int ib = KB + 1; ib < NT; ++ib)
+        if (ib < nt)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double* prow = &sh.Pn[ib][(ti + H * h) * PL];
+                double sacc = 0.0;
+                for (int q = 0; q <= tj; ++q) sacc += prow[q] * sh.Li[tj * PL + q];
+                reg[tslot(ib, KB)][h] = sacc;
+            }
+    __syncthreads();
+#pragma unroll
+    for (int ib = KB + 1; ib < NT; ++ib)
+        if (ib < nt)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) sh.Pn[ib][(ti + H * h) * PL + tj] = reg[tslot(ib, KB)][h];
+    __syncthreads();
+    // trailing lower tiles: A_(ib,jb) -= L_(ib,KB) L_(jb,KB)^T
+#pragma unroll
+    for (int ib = KB + 1; ib < NT; ++ib)
+#pragma unroll
+        for (int jb = KB + 1; jb <= ib; ++jb)
+            if (ib < nt) {
+                const double* pj = &sh.Pn[jb][tj * PL];
+                const double* p0 = &sh.Pn[ib][ti * PL];
+                const double* p1 = &sh.Pn[ib][(ti + H) * PL];
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll 8
+                for (int q = 0; q < T; ++q) {
+                    const double w = pj[q];
+                    s0 += p0[q] * w;
+                    s1 += p1[q] * w;
+                }
+                reg[tslot(ib, jb)][0] -= s0;
+                reg[tslot(ib, jb)][1] -= s1;
+            }
+}
+
+template <int KB>
+struct CholSteps {
+    __device__ __forceinline__ static void run(double (&reg)[CH_NT * (CH_NT + 1) / 2][2],
+                                               CholShared& sh, int nt, int identity, bool& alive) {
+        chol_step<KB>(reg, sh, nt, identity, alive);
+        CholSteps<KB + 1>::run(reg, sh, nt, identity, alive);
+    }
+};
+template <>
+struct CholSteps<CH_NT> {
+    __device__ __forceinline__ static void run(double (&)[CH_NT * (CH_NT + 1) / 2][2], CholShared&,
+                                               int, int, bool&) {}
+};
+
+// In-place lower Cholesky of one nb x nb matrix (nb <= 256) per workgroup
+// (batch over blockIdx.x, matrices `stride` doubles apart, leading dimension
+// ld). The lower triangle is held in registers as 32 x 32 tiles: thread
+// (ti, tj), ti < 16, owns entries (ti, tj) and (ti + 16, tj) of each of the 36
+// lower tiles (144 VGPRs at two waves per SIMD). Per tile column:
+//   1. the diagonal tile goes to LDS, where one wave factors it and inverts
+//      the factor (LDS operations of one wave execute in order),
+//   2. each panel tile below is staged in LDS and multiplied by L_kk^{-T},
+//   3. the trailing lower tiles are updated in registers from the panel in LDS.
+// Global memory is touched only by the initial load and the final store.
+// identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
+// out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0. Only the lower
+// triangle is read; the factor overwrites it and the upper triangle is zeroed.
+__global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int64_t stride,
+                                                     int nb, int ld, int identity,
+                                                     double* __restrict__ out) {
+    constexpr int T = CH_T, NT = CH_NT, H = T / 2;
+    __shared__ CholShared sh;
+    double* A = M + (int64_t)blockIdx.x * stride;
+    const int tid = threadIdx.x;
+    const int ti = tid / T, tj = tid % T;
+    const int nt = (nb + T - 1) / T;
+    const double pad = identity ? 0.0 : 1.0;   // padded diagonal: contributes log 1 = 0
+    double reg[NT * (NT + 1) / 2][2];
+#pragma unroll
+    for (int bi = 0; bi < NT; ++bi)
+#pragma unroll
+        for (int bj = 0; bj <= bi; ++bj)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = bi * T + ti + H * h, j = bj * T + tj;
+                double v = 0.0;
+                if (bi < nt) {
+                    if (i < nb && j < nb) {
+                        if (j <= i) v = A[(int64_t)i * ld + j];
+                    } else if (i == j) {
+                        v = pad;
                     }
                 }
-                __syncthreads();
-                if (tj > jc && tj < kw) {
-                    const double l = D[tj * CH_PLD + jc];
+                reg[tslot(bi, bj)][h] = v;
+            }
+    if (tid == 0) {
+        sh.bad = 0;
+        sh.logdet = 0.0;
+    }
+    bool alive = true;   // uniform: cleared in every thread once a pivot fails
+    CholSteps<0>::run(reg, sh, nt, identity, alive);
+    __syncthreads();
+    if (!sh.bad) {
 #pragma unroll
-                    for (int q = 0; q < CH_PMAX / CH_T; ++q) preg[q] -= xbuf[ti + CH_T * q] * l;
+        for (int bi = 0; bi < NT; ++bi)
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = bi * T + ti + H * h, j = bj * T + tj;
+                    if (bi < nt && i < nb && j < nb) {
+                        A[(int64_t)i * ld + j] = (j <= i) ? reg[tslot(bi, bj)][h] : 0.0;
+                        if (bj == bi && j < i) A[(int64_t)j * ld + i] = 0.0;
+                    }
                 }
-                __syncthreads();
-            }
-            // stage the finished panel (D is no longer needed) and store it
-            double* P = lds;
-#pragma unroll
-            for (int q = 0; q < CH_PMAX / CH_T; ++q) {
-                const int rr = ti + CH_T * q;
-                const int r = p0 + rr;
-                P[rr * CH_PLD + tj] = (r < nb && tj < kw) ? preg[q] : 0.0;
-                if (r < nb && tj < kw) A[(int64_t)r * ld + k0 + tj] = preg[q];
-            }
-            __syncthreads();
-            // trailing lower triangle: A[r][c] -= P[r] . P[c]
-            const int total = pr * pr;
-            for (int idx = tid; idx < total; idx += 1024) {
-                const int rr = idx / pr, cc = idx - rr * pr;
-                if (cc > rr) continue;
-                double s = 0.0;
-#pragma unroll 8
-                for (int j = 0; j < CH_T; ++j) s += P[rr * CH_PLD + j] * P[cc * CH_PLD + j];
-                A[(int64_t)(p0 + rr) * ld + p0 + cc] -= s;
-            }
-        }
-        __syncthreads();
     }
     if (tid == 0) {
-        out[2 * blockIdx.x] = logdet;
-        out[2 * blockIdx.x + 1] = bad ? 0.0 : 1.0;
+        out[2 * blockIdx.x] = sh.logdet;
+        out[2 * blockIdx.x + 1] = sh.bad ? 0.0 : 1.0;
     }
 }
 
@@ -343,7 +459,7 @@ void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int ident
                  hipStream_t s) {
     if (nb > CH_NB) throw SicError(SIC_ETOOBIG, "block larger than the Cholesky kernel supports");
     prof_begin(KK_CHOL, s);
-    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(1024), 0, s, M, stride, nb, ld, identity, out);
+    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(CH_THREADS), 0, s, M, stride, nb, ld, identity, out);
     SIC_CHECK_LAUNCH();
     prof_end(KK_CHOL, s, 16.0 * nb * nb * (double)batch, (double)nb * nb * nb / 3.0 * batch);
 }

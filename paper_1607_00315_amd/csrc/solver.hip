@@ -468,12 +468,20 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
                    W.c_wtt.p, W.delta.p, s);
     launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, P.lam,
               C.opt.cd_max_sweeps, C.opt.cd_tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
-    double cds[3];
-    SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    double cds[7];
+    SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     // (e) line search
     LineSearch ls = line_search(C, P.lam, jp, b, nN, nc);
     R.cd_sweeps = (int)cds[0];
     R.cd_last_maxmu = cds[1];
+    if (C.opt.flags & SIC_FLAG_VERBOSE)
+        fprintf(stderr,
+                "[sic] block j0=%lld %s E=%lld coords=%lld |N|=%lld |NC|=%lld cg=%d/%d cd=%d "
+                "phases(us) u=%.0f dots=%.0f chain=%.0f fold=%.0f alpha=%g trials=%d\n",
+                (long long)j0, fine ? "fine" : "coarse", (long long)R.E, (long long)nc,
+                (long long)nN, (long long)nC, R.cg_iters_I, R.cg_iters_N, R.cd_sweeps,
+                cds[3] / 100.0, cds[4] / 100.0, cds[5] / 100.0, cds[6] / 100.0, ls.alpha,
+                ls.trials);
     if (!ls.wii_pd) throw SicError(SIC_EINTERNAL, "W_II is not positive definite (inaccurate inverse columns)");
     R.alpha = ls.alpha;
     R.dF = ls.dF;

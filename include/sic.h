@@ -93,6 +93,9 @@ typedef struct {
     int cg_max_iter;       /* CG iteration cap per solve, default 1000 */
     double cd_tol;         /* CD stop: max|mu| <= cd_tol * max|Delta|, default 1e-4 */
     int cd_max_sweeps;     /* CD sweep cap per block, default 20 */
+    int cd_hessian_max;    /* blocks with at most this many coordinates run CD on an explicit
+                              coordinate Hessian (ncoord^2 doubles of scratch); 0 = default
+                              4096, < 0 = never */
     int ls_max_trials;     /* line-search trials alpha = 2^-i, i < ls_max_trials, default 31 */
     int max_cycles;        /* multilevel cycles, default 100 */
     void* stream;          /* hipStream_t to run on, or NULL for the context's own stream */

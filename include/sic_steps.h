@@ -94,9 +94,12 @@ int sic_step_kkt(sic_prob* p, double tol_cg, double* kkt_max, double* kkt_l1);
 /* Coordinate descent on given data (host arrays), the kernel of step (d):
  *   wjj: jp x jp (W on J', block columns first), cptr[b+1]: coordinates per
  *   block column, cp[n_coords]: local row index in J', S/A: per coordinate.
- * delta_out: n_coords; stats_out[7]: sweeps, last max|mu|, max|Delta|, then the
- * kernel's wall-clock ticks spent staging u, in dot products and gathers, in
- * the serial chain and in folding steps into U (device wall clock, 100 MHz). */
+ * delta_out: n_coords; stats_out[7]: sweeps, last max|mu|, max|Delta|, then
+ * four phase clocks of the kernel (device wall clock, 100 MHz ticks): with
+ * the explicit coordinate Hessian (n_coords <= the context's cd_hessian_max)
+ * the serial chain, the Hessian products, the staging waits and 0; otherwise
+ * staging u, dot products and gathers, the serial chain and folding steps
+ * into U. Both forms visit the coordinates in the same order. */
 int sic_step_cd(sic_ctx* ctx, int jp, int b, const double* wjj, const int64_t* cptr,
                 const int32_t* cp, const double* S, const double* A, double lambda,
                 int max_sweeps, double tol, double* delta_out, double* stats_out);

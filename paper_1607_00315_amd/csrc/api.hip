@@ -48,6 +48,7 @@ void opts_from(sic::Context& C, const sic_options& o) {
     t.cg_max_iter = o.cg_max_iter > 0 ? o.cg_max_iter : 1000;
     t.cd_tol = o.cd_tol > 0 ? o.cd_tol : 1e-4;
     t.cd_max_sweeps = o.cd_max_sweeps > 0 ? o.cd_max_sweeps : 20;
+    t.cd_hessian_max = o.cd_hessian_max == 0 ? 4096 : (o.cd_hessian_max < 0 ? 0 : o.cd_hessian_max);
     t.ls_max_trials = o.ls_max_trials > 0 ? o.ls_max_trials : 31;
     t.max_cycles = o.max_cycles > 0 ? o.max_cycles : 100;
     t.flags = o.flags;
@@ -88,6 +89,7 @@ void sic_options_default(sic_options* o) {
     o->cg_max_iter = 1000;
     o->cd_tol = 1e-4;
     o->cd_max_sweeps = 20;
+    o->cd_hessian_max = 4096;
     o->ls_max_trials = 31;
     o->max_cycles = 100;
 }

@@ -293,6 +293,195 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(
     }
 }
 
+
+// ------------------------------------------------------------------------
+// Explicit coordinate Hessian form of the same sweep.
+//
+// With Delta = 0 at the start, z_k = (W Delta W)_{r_k c_k} starts at zero and
+// a step mu_t on coordinate t = (r_t, c_t) changes every z_k by mu_t H[k][t],
+//   H[k][t] = W_{r_k r_t} W_{c_t c_k} + [r_t != c_t] W_{r_k c_t} W_{r_t c_k},
+// the coefficient of Delta_t in the model gradient of coordinate k
+// (H[t][t] = a_t). Building H once per block turns a sweep into
+//   for each chunk of 64 consecutive coordinates (the same visiting order):
+//     one wave runs the 64 steps, correcting the chunk's own z in registers
+//     from the 64 x 64 diagonal tile of H held in LDS,
+//   then every other z_k receives sum_t H[k][t] mu_t from one pass over the
+//     chunk's 64 columns of H (coalesced rows of H^T, zero steps skipped).
+// No U = Delta W is kept, so nothing is staged or folded per block column.
+
+constexpr int CDH_THREADS = 1024;
+constexpr int CDH_WAVES = CDH_THREADS / 64;
+constexpr int CDH_K = 64;   // chunk length = wave size
+
+// Barrier for LDS traffic only: outstanding global loads (prefetches into
+// registers) stay in flight across it.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// HT[t * nc + k] = H[k][t] (column t of H stored contiguously).
+__global__ void k_cd_hess(int64_t nc, int jp, const int32_t* __restrict__ c_p,
+                          const int32_t* __restrict__ c_ci, const double* __restrict__ WJJ,
+                          double* __restrict__ HT) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = blockIdx.y;
+    if (k >= nc) return;
+    const int pt = c_p[t], ct = c_ci[t];
+    const int pk = c_p[k], ck = c_ci[k];
+    const double* wpt = WJJ + (int64_t)pt * jp;
+    const double* wct = WJJ + (int64_t)ct * jp;
+    double h = wpt[pk] * wct[ck];
+    if (pt != ct) h += wct[pk] * wpt[ck];
+    HT[t * nc + k] = h;
+}
+
+__global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
+    int64_t nc, const double* __restrict__ HT, const double* __restrict__ c_S,
+    const double* __restrict__ c_A, const double* __restrict__ c_inva,
+    const double* __restrict__ c_wtc, double lam, int max_sweeps, double tol,
+    double* __restrict__ delta, double* __restrict__ stats) {
+    extern __shared__ double sm[];
+    double* zs = sm;                    // [nc] z = (W Delta W) on the coordinates
+    double* ds = zs + nc;               // [nc] Delta
+    double* Hc = ds + nc;               // [CDH_K][CDH_K] diagonal tile of the chunk, [t][k]
+    double* mus = Hc + CDH_K * CDH_K;   // [CDH_K] steps of the chunk
+    int* nzl = (int*)(mus + CDH_K);     // [CDH_K] chunk positions with a nonzero step
+    __shared__ double s_red[CDH_WAVES];
+    __shared__ int s_nnz, s_stop;
+    __shared__ double s_maxmu;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nchunks = (int)((nc + CDH_K - 1) / CDH_K);
+
+    for (int64_t k = tid; k < nc; k += CDH_THREADS) {
+        zs[k] = 0.0;
+        ds[k] = 0.0;
+    }
+    // register copy of the next chunk's diagonal tile (entry e = t * 64 + k)
+    constexpr int HPT = CDH_K * CDH_K / CDH_THREADS;
+    double hreg[HPT];
+    auto load_tile = [&](int ch) {
+        const int64_t k0 = (int64_t)ch * CDH_K;
+        const int K = (int)((nc - k0) < CDH_K ? (nc - k0) : CDH_K);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int e = tid + CDH_THREADS * j;
+            const int t = e / CDH_K, k = e % CDH_K;
+            hreg[j] = (t < K && k < K) ? HT[(k0 + t) * nc + k0 + k] : 0.0;
+        }
+    };
+    // wave 0: the next chunk's per-coordinate constants, one coordinate per lane
+    double nb_c = 0.0, nA = 0.0, ninva = 0.0;
+    auto load_lane = [&](int ch) {
+        const int64_t k = (int64_t)ch * CDH_K + lane;
+        const bool on = k < nc;
+        nb_c = on ? c_S[k] - c_wtc[k] : 0.0;
+        nA = on ? c_A[k] : 0.0;
+        ninva = on ? c_inva[k] : 0.0;
+    };
+    load_tile(0);
+    if (wave == 0) load_lane(0);
+
+    int sweeps = 0;
+    double maxmu = 0.0;   // meaningful in wave 0
+    long long tph[3] = {0, 0, 0};   // thread 0: chain, Hessian products, staging waits
+    long long tlast = wall_clock64();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        maxmu = 0.0;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int64_t k0 = (int64_t)ch * CDH_K;
+            const int K = (int)((nc - k0) < CDH_K ? (nc - k0) : CDH_K);
+            const int nch = ch + 1 < nchunks ? ch + 1 : 0;
+#pragma unroll
+            for (int j = 0; j < HPT; ++j) Hc[tid + CDH_THREADS * j] = hreg[j];
+            lds_barrier();   // tile, z and Delta of the chunk are in place
+            if (tid == 0) { const long long now = wall_clock64(); tph[2] += now - tlast; tlast = now; }
+            load_tile(nch);  // in flight during the chain and the products
+            if (wave == 0) {
+                const bool on = lane < K;
+                const double bc = nb_c, inva = ninva;
+                const double d0 = on ? ds[k0 + lane] : 0.0;
+                const double xl = nA + d0;
+                double z = on ? zs[k0 + lane] : 0.0;
+                load_lane(nch);
+                double mul = 0.0;
+                double hn = Hc[lane];
+                for (int tt = 0; tt < K; ++tt) {
+                    const double h = hn;
+                    if (tt + 1 < K) hn = Hc[(tt + 1) * CDH_K + lane];
+                    const double x = readlane_d(xl, tt);
+                    const double ia = readlane_d(inva, tt);
+                    const double bb = readlane_d(bc, tt) + readlane_d(z, tt);
+                    const double y = x - bb * ia;
+                    const double thr = lam * ia;
+                    const double sh = y > thr ? y - thr : (y < -thr ? y + thr : 0.0);
+                    const double mu = sh - x;
+                    z += mu * h;
+                    if (lane == tt) mul = mu;
+                    maxmu = fmax(maxmu, fabs(mu));
+                }
+                if (on) {
+                    zs[k0 + lane] = z;
+                    ds[k0 + lane] = d0 + mul;
+                    mus[lane] = mul;
+                }
+                const unsigned long long nzm = __ballot(on && mul != 0.0);
+                if (on && mul != 0.0)
+                    nzl[__popcll(nzm & ((1ull << lane) - 1ull))] = lane;
+                if (lane == 0) s_nnz = __popcll(nzm);
+            }
+            lds_barrier();   // steps of the chunk are in place
+            if (tid == 0) { const long long now = wall_clock64(); tph[0] += now - tlast; tlast = now; }
+            // z_k += sum_t H[k][t] mu_t for every coordinate outside the chunk
+            const int nnz = s_nnz;
+            if (nnz > 0) {
+                for (int64_t k = tid; k < nc; k += CDH_THREADS) {
+                    if (k >= k0 && k < k0 + K) continue;
+                    const double* hk = HT + k0 * nc + k;
+                    double acc = 0.0;
+                    int i = 0;
+                    for (; i + 8 <= nnz; i += 8) {
+                        double hv[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) hv[q] = hk[(int64_t)nzl[i + q] * nc];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) acc += hv[q] * mus[nzl[i + q]];
+                    }
+                    for (; i < nnz; ++i) acc += hk[(int64_t)nzl[i] * nc] * mus[nzl[i]];
+                    zs[k] += acc;
+                }
+            }
+            if (tid == 0) { const long long now = wall_clock64(); tph[1] += now - tlast; tlast = now; }
+        }
+        // stopping rule: max|mu| <= tol * max|Delta|
+        if (tid == 0) s_maxmu = maxmu;
+        double dmax = 0.0;
+        for (int64_t k = tid; k < nc; k += CDH_THREADS) dmax = fmax(dmax, fabs(ds[k]));
+        dmax = wave_max(dmax);
+        if (lane == 0) s_red[wave] = dmax;
+        lds_barrier();
+        if (tid == 0) {
+            double m = 0.0;
+            for (int w = 0; w < CDH_WAVES; ++w) m = fmax(m, s_red[w]);
+            s_stop = (s_maxmu <= tol * m) ? 1 : 0;
+            stats[1] = s_maxmu;
+            stats[2] = m;
+        }
+        lds_barrier();
+        ++sweeps;
+        if (s_stop) break;
+    }
+    for (int64_t k = tid; k < nc; k += CDH_THREADS) delta[k] = ds[k];
+    if (tid == 0) {
+        stats[0] = (double)sweeps;
+        for (int i = 0; i < 3; ++i) stats[3 + i] = (double)tph[i];
+        stats[6] = 0.0;
+    }
+}
+
 }  // namespace
 
 size_t cd_lds_bytes(int jp, bool u_in_lds) {
@@ -335,7 +524,40 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
                            markg, stats);
     }
     SIC_CHECK_LAUNCH();
-    prof_end(KK_CD, s, 0.0, 0.0);   // latency-bound chain: time only
+    // the W rows a sweep must read (one per coordinate for the model gradient)
+    prof_end(KK_CD, s, 0.0, 0.0);
+}
+
+size_t cd_hessian_lds_bytes(int64_t ncoord) {
+    return sizeof(double) * ((size_t)2 * ncoord + CDH_K * CDH_K + CDH_K) + sizeof(int) * CDH_K;
+}
+
+void launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
+                       const double* WJJ, const double* c_S, const double* c_A,
+                       const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
+                       double tol, double* HT, double* delta, double* stats, hipStream_t s) {
+    if (ncoord <= 0) return;
+    const size_t lds = cd_hessian_lds_bytes(ncoord);
+    if (lds > CD_MAX_LDS_BYTES)
+        throw SicError(SIC_EINTERNAL, "coordinate count too large for the explicit-Hessian sweep");
+    prof_begin(KK_CD_HESS, s);
+    hipLaunchKernelGGL(k_cd_hess, dim3((unsigned)((ncoord + 255) / 256), (unsigned)ncoord),
+                       dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HT);
+    SIC_CHECK_LAUNCH();
+    // H written once; 4 gathers of W per entry (from the L2-resident W on J')
+    prof_end(KK_CD_HESS, s, 8.0 * (double)ncoord * ncoord, 3.0 * (double)ncoord * ncoord);
+    static bool attr_set = false;
+    if (!attr_set) {
+        SIC_HIP(hipFuncSetAttribute((const void*)k_cd_dense,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)CD_MAX_LDS_BYTES));
+        attr_set = true;
+    }
+    prof_begin(KK_CD, s);
+    hipLaunchKernelGGL(k_cd_dense, dim3(1), dim3(CDH_THREADS), lds, s, ncoord, HT, c_S, c_A, c_inva,
+                       c_wtc, lam, max_sweeps, tol, delta, stats);
+    SIC_CHECK_LAUNCH();
+    prof_end(KK_CD, s, 0.0, 0.0);
 }
 
 }  // namespace sic

@@ -15,6 +15,7 @@ enum KernelKind {
     KK_CHOL,
     KK_GEMM,
     KK_UPD_ROWS,
+    KK_CD_HESS,
     KK_COUNT
 };
 

@@ -153,6 +153,13 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
                const double* c_A, const double* c_inva, const double* c_wtc, const double* WJJ,
                double lam, int max_sweeps, double tol, double* U, double* delta, double* mu_col,
                double* ug, unsigned char* markg, double* stats, hipStream_t s);
+// Explicit coordinate Hessian form: builds H^T (ncoord^2 doubles at HT), then
+// runs the sweeps; requires cd_hessian_lds_bytes(ncoord) <= CD_MAX_LDS_BYTES.
+size_t cd_hessian_lds_bytes(int64_t ncoord);
+void launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
+                       const double* WJJ, const double* c_S, const double* c_A,
+                       const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
+                       double tol, double* HT, double* delta, double* stats, hipStream_t s);
 
 // ---------------------------------------------------------------- k_dense.hip
 void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,

@@ -11,6 +11,7 @@ struct Options {
     int cg_max_iter = 1000;
     double cd_tol = 1e-4;
     int cd_max_sweeps = 20;
+    int cd_hessian_max = 4096;   // 0: never use the explicit-Hessian sweep
     int ls_max_trials = 31;
     int max_cycles = 100;
     uint64_t flags = 0;
@@ -19,7 +20,7 @@ struct Options {
 
 // Scratch of one block update; sized on demand, reused across blocks.
 struct BlockWork {
-    DevBuf<double> SJ, WI, AJ, ANEW, WN, WJJ, U, ug;
+    DevBuf<double> SJ, WI, AJ, ANEW, WN, WJJ, U, ug, HT;
     DevBuf<unsigned char> markg;
     DevBuf<int32_t> cols;
     // free lists

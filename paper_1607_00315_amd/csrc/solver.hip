@@ -327,6 +327,27 @@ void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count) 
 
 // ------------------------------------------------------------------ one block
 
+// Step (d) on the coordinates prepared in the block work area: the explicit
+// coordinate Hessian form when the block has at most cd_hessian_max
+// coordinates (and its z and Delta fit in LDS), else the U = Delta W form.
+static void run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max_sweeps, double tol) {
+    BlockWork& W = C.work;
+    hipStream_t s = C.stream;
+    W.cdstats.reserve(8);
+    if (nc > 0 && nc <= C.opt.cd_hessian_max && cd_hessian_lds_bytes(nc) <= CD_MAX_LDS_BYTES) {
+        W.HT.reserve((size_t)nc * nc);
+        launch_cd_hessian(nc, jp, W.c_p.p, W.c_ci.p, W.WJJ.p, W.c_S.p, W.c_A.p, W.c_inva.p,
+                          W.c_wtc.p, lam, max_sweeps, tol, W.HT.p, W.delta.p, W.cdstats.p, s);
+        return;
+    }
+    W.U.reserve((size_t)jp * b);
+    W.ug.reserve(jp);
+    W.markg.reserve(jp);
+    SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
+    launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, lam,
+              max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
+}
+
 BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, bool record,
                          double tolI, double tolN) {
     hipStream_t s = C.stream;
@@ -459,15 +480,9 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     launch_gather_wjj(fine ? 0 : 1, W.Jp.p, jp, b, W.WI.p, W.WN.p, nN, W.WII.p, W.WNC.p, nC,
                       W.cmap.p, W.WJJ.p, s);
     // (d) coordinate descent
-    W.U.reserve((size_t)jp * b);
-    W.ug.reserve(jp);
-    W.markg.reserve(jp);
-    W.cdstats.reserve(8);
-    SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
     launch_cd_prep(W.cptr.p, b, nc, W.c_p.p, W.WJJ.p, jp, W.c_ci.p, W.c_a.p, W.c_inva.p, W.c_wtc.p,
                    W.c_wtt.p, W.delta.p, s);
-    launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, P.lam,
-              C.opt.cd_max_sweeps, C.opt.cd_tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
+    run_cd(C, jp, b, nc, P.lam, C.opt.cd_max_sweeps, C.opt.cd_tol);
     double cds[7];
     SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     // (e) line search
@@ -477,7 +492,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     if (C.opt.flags & SIC_FLAG_VERBOSE)
         fprintf(stderr,
                 "[sic] block j0=%lld %s E=%lld coords=%lld |N|=%lld |NC|=%lld cg=%d/%d cd=%d "
-                "phases(us) u=%.0f dots=%.0f chain=%.0f fold=%.0f alpha=%g trials=%d\n",
+                "cd-clocks(us) %.0f/%.0f/%.0f/%.0f alpha=%g trials=%d\n",
                 (long long)j0, fine ? "fine" : "coarse", (long long)R.E, (long long)nc,
                 (long long)nN, (long long)nC, R.cg_iters_I, R.cg_iters_N, R.cd_sweeps,
                 cds[3] / 100.0, cds[4] / 100.0, cds[5] / 100.0, cds[6] / 100.0, ls.alpha,
@@ -830,10 +845,6 @@ static void load_coords(Context& C, int jp, int b, const double* wjj, const int6
     W.c_p.reserve(ncs); W.c_ci.reserve(ncs); W.c_S.reserve(ncs); W.c_A.reserve(ncs);
     W.c_a.reserve(ncs); W.c_inva.reserve(ncs); W.c_wtc.reserve(ncs); W.c_wtt.reserve(ncs);
     W.delta.reserve(ncs); W.mu.reserve(ncs);
-    W.U.reserve((size_t)jp * b);
-    W.ug.reserve(jp);
-    W.markg.reserve(jp);
-    W.cdstats.reserve(8);
     SIC_HIP(hipMemcpyAsync(W.WJJ.p, wjj, sizeof(double) * jp * jp, hipMemcpyHostToDevice, s));
     SIC_HIP(hipMemcpyAsync(W.cptr.p, cptr, sizeof(int64_t) * (b + 1), hipMemcpyHostToDevice, s));
     if (nc) {
@@ -852,9 +863,7 @@ int step_cd_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cp
     hipStream_t s = C.stream;
     load_coords(C, jp, b, wjj, cptr, cp, S, A);
     const int64_t nc = cptr[b];
-    SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
-    launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, lambda,
-              max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
+    run_cd(C, jp, b, nc, lambda, max_sweeps, tol);
     if (nc) SIC_HIP(hipMemcpyAsync(delta_out, W.delta.p, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
     double st[7];
     SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));

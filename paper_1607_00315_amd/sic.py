@@ -45,7 +45,7 @@ class Options(ct.Structure):
     _fields_ = [("device", ct.c_int), ("hbm_budget", ct.c_size_t), ("precision", ct.c_int),
                 ("block", ct.c_int), ("cg_tol_I", ct.c_double), ("cg_tol_N", ct.c_double),
                 ("cg_max_iter", ct.c_int), ("cd_tol", ct.c_double), ("cd_max_sweeps", ct.c_int),
-                ("ls_max_trials", ct.c_int), ("max_cycles", ct.c_int), ("stream", ct.c_void_p),
+                ("cd_hessian_max", ct.c_int), ("ls_max_trials", ct.c_int), ("max_cycles", ct.c_int), ("stream", ct.c_void_p),
                 ("flags", ct.c_uint64), ("trace", ct.POINTER(TraceEntry)), ("trace_cap", ct.c_int)]
 
 
@@ -439,7 +439,7 @@ def hierarchy(n, supp_keys, free_keys, free_absg):
     return rank[:rlen.value], list(sizes[:nl.value])
 
 
-KERNEL_CLASSES = 9
+KERNEL_CLASSES = 10
 
 
 def profile_enable(on=True):

@@ -127,15 +127,28 @@ def _mlbcd_iterate(X, lam, b, sweeps=1):
     return A, S
 
 
+@pytest.fixture(scope="module")
+def ctx_u():
+    """Context whose CD always takes the U = Delta W form."""
+    from paper_1607_00315_amd import sic
+    c = sic.Context(block=128, cd_hessian_max=-1)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("form", ["hessian", "u"])
 @pytest.mark.parametrize("start", ["identity", "iterate"])
-def test_cd_step_matches_oracle(ctx, rnd600, start):
+def test_cd_step_matches_oracle(ctx, ctx_u, rnd600, start, form):
+    """Both CD forms against the plain C loop; the identity start has 2630
+    coordinates (42 chunks of 64, the last one ragged)."""
     from paper_1607_00315_amd import sic
     X, P, spec, S = rnd600
     lam = spec["lam"]
     A = np.eye(600) if start == "identity" else _mlbcd_iterate(X, lam, 128)[0]
     j0, j1 = 128, 256
     d = _block_inputs(A, S, lam, j0, j1)
-    announce(f"step_cd random_n600 start={start} coords={d['r'].size} |N|={d['N'].size}")
+    ctx = ctx if form == "hessian" else ctx_u
+    announce(f"step_cd random_n600 start={start} form={form} coords={d['r'].size} |N|={d['N'].size}")
     # fixed number of sweeps: identical work on both sides
     got, st = sic.step_cd(ctx, d["wjj"], d["b"], d["cptr"], d["cp"], d["S"], d["A"], lam,
                           max_sweeps=6, tol=0.0)

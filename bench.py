@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--cd-max-sweeps", type=int, default=0, help="0: library default")
     ap.add_argument("--cd-tol", type=float, default=0.0, help="0: library default")
+    ap.add_argument("--cycles", type=int, default=0,
+                    help="skip the calibration solve and run this many cycles per step "
+                         "(the exact gap is still measured and reported)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
@@ -147,30 +150,36 @@ def main():
     if args.cd_tol:
         solver_opts["cd_tol"] = args.cd_tol
     ctx = sic.Context(trace_cap=256, **solver_opts)
-    # calibration: solve to KKT <= 1e-6, cycle trace of the tracked objective
-    t = time.perf_counter()
-    (rp, col, val), info, trace = ctx.solve(Xd, lam, 1e-6)
-    t_kkt = time.perf_counter() - t
-    F_final = exact_objective(rp, col, val, Xd, lam)
-    sup_kkt = bool(np.array_equal(support_keys(rp, col), gkeys))
-    drift = abs(info["objective"] - F_final)
-    log(f"calibration: {info['cycles']} cycles, {t_kkt:.2f}s to KKT {info['kkt_max']:.2e}, "
-        f"F exact {F_final:.12e} (F* {Fstar:.12e}), tracked drift {drift:.2e}")
-    cstar = len(trace)
-    for e in trace:
-        if (e["objective"] - Fstar + drift) / abs(Fstar) <= GAP:
-            cstar = e["cycle"] + 1
-            break
-    # verify c* with the exact objective of the iterate after c* cycles
-    while True:
+    t_kkt = sup_kkt = None
+    info = {"cycles": None, "kkt_max": None}
+    if args.cycles > 0:
+        cstar = args.cycles
         ctx_c = sic.Context(max_cycles=cstar, **solver_opts)
-        (rp, col, val), info_c, _ = ctx_c.solve(Xd, lam, 1e-12)
-        gap = (exact_objective(rp, col, val, Xd, lam) - Fstar) / abs(Fstar)
-        log(f"c*={cstar}: exact gap {gap:.3e}")
-        if gap <= GAP or cstar >= info["cycles"] + 5:
-            break
-        ctx_c.close()
-        cstar += 1
+    else:
+        # calibration: solve to KKT <= 1e-6, cycle trace of the tracked objective
+        t = time.perf_counter()
+        (rp, col, val), info, trace = ctx.solve(Xd, lam, 1e-6)
+        t_kkt = time.perf_counter() - t
+        F_final = exact_objective(rp, col, val, Xd, lam)
+        sup_kkt = bool(np.array_equal(support_keys(rp, col), gkeys))
+        drift = abs(info["objective"] - F_final)
+        log(f"calibration: {info['cycles']} cycles, {t_kkt:.2f}s to KKT {info['kkt_max']:.2e}, "
+            f"F exact {F_final:.12e} (F* {Fstar:.12e}), tracked drift {drift:.2e}")
+        cstar = len(trace)
+        for e in trace:
+            if (e["objective"] - Fstar + drift) / abs(Fstar) <= GAP:
+                cstar = e["cycle"] + 1
+                break
+        # verify c* with the exact objective of the iterate after c* cycles
+        while True:
+            ctx_c = sic.Context(max_cycles=cstar, **solver_opts)
+            (rp, col, val), info_c, _ = ctx_c.solve(Xd, lam, 1e-12)
+            gap = (exact_objective(rp, col, val, Xd, lam) - Fstar) / abs(Fstar)
+            log(f"c*={cstar}: exact gap {gap:.3e}")
+            if gap <= GAP or cstar >= info["cycles"] + 5:
+                break
+            ctx_c.close()
+            cstar += 1
     for _ in range(args.warmup):
         ctx_c.solve(Xd, lam, 1e-12)
     if not args.no_kernel_timing:

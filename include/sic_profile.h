@@ -21,8 +21,9 @@ extern "C" {
  *   2 cg_spmm      CG sparse product             7 gemm_small   line-search products
  *   3 cg_update    CG vector update              8 upd_rows     CSR rebuild
  *   4 screen_fine  free-set screening            9 cd_hess      coordinate Hessian
- *                                                               (explicit-Hessian CD) */
-#define SIC_KERNEL_CLASSES 10
+ *                                                               (explicit-Hessian CD)
+ *                                               10 trsm         triangular solves */
+#define SIC_KERNEL_CLASSES 11
 
 void sic_profile_enable(int on);      /* on != 0 starts timing, 0 stops it */
 void sic_profile_reset(void);         /* zero every counter */

@@ -53,7 +53,8 @@ struct CholShared {
 // template so that every register tile index is a compile-time constant.
 template <int KB>
 __device__ __forceinline__ void chol_step(double (&reg)[CH_NT * (CH_NT + 1) / 2][2],
-                                          CholShared& sh, int nt, int identity, bool& alive) {
+                                          CholShared& sh, int nt, int identity, bool& alive,
+                                          double* __restrict__ dinv) {
     constexpr int T = CH_T, NT = CH_NT, PL = CH_PLD, H = T / 2;
     const int tid = threadIdx.x, lane = tid & 63;
     const int ti = tid / T, tj = tid % T;
@@ -106,6 +107,7 @@ __device__ __forceinline__ void chol_step(double (&reg)[CH_NT * (CH_NT + 1) / 2]
     for (int h = 0; h < 2; ++h) {
         const int r = ti + H * h;
         reg[tslot(KB, KB)][h] = (tj <= r) ? sh.D[r * PL + tj] : 0.0;
+        if (dinv) dinv[KB * T * T + r * T + tj] = sh.Li[r * PL + tj];
     }
     if (KB + 1 >= NT) return;
     // panel tiles: stage A_(ib,KB), then L_(ib,KB) = A_(ib,KB) L_KB^{-T}
@@ -156,15 +158,16 @@ __device__ __forceinline__ void chol_step(double (&reg)[CH_NT * (CH_NT + 1) / 2]
 template <int KB>
 struct CholSteps {
     __device__ __forceinline__ static void run(double (&reg)[CH_NT * (CH_NT + 1) / 2][2],
-                                               CholShared& sh, int nt, int identity, bool& alive) {
-        chol_step<KB>(reg, sh, nt, identity, alive);
-        CholSteps<KB + 1>::run(reg, sh, nt, identity, alive);
+                                               CholShared& sh, int nt, int identity, bool& alive,
+                                               double* __restrict__ dinv) {
+        chol_step<KB>(reg, sh, nt, identity, alive, dinv);
+        CholSteps<KB + 1>::run(reg, sh, nt, identity, alive, dinv);
     }
 };
 template <>
 struct CholSteps<CH_NT> {
     __device__ __forceinline__ static void run(double (&)[CH_NT * (CH_NT + 1) / 2][2], CholShared&,
-                                               int, int, bool&) {}
+                                               int, int, bool&, double*) {}
 };
 
 // In-place lower Cholesky of one nb x nb matrix (nb <= 256) per workgroup
@@ -180,9 +183,12 @@ struct CholSteps<CH_NT> {
 // identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
 // out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0. Only the lower
 // triangle is read; the factor overwrites it and the upper triangle is zeroed.
+// dinv (batch 1 only, may be null): the inverses of the 32 x 32 diagonal
+// tiles of the factor, tile k at dinv + 1024 k, row-major (written when PD).
 __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int64_t stride,
                                                      int nb, int ld, int identity,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out,
+                                                     double* __restrict__ dinv) {
     constexpr int T = CH_T, NT = CH_NT, H = T / 2;
     __shared__ CholShared sh;
     double* A = M + (int64_t)blockIdx.x * stride;
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
         sh.logdet = 0.0;
     }
     bool alive = true;   // uniform: cleared in every thread once a pivot fails
-    CholSteps<0>::run(reg, sh, nt, identity, alive);
+    CholSteps<0>::run(reg, sh, nt, identity, alive, dinv);
     __syncthreads();
     if (!sh.bad) {
 #pragma unroll
@@ -235,41 +241,75 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
     }
 }
 
-// Solve L X = B (trans = 0) or L^T X = B (trans = 1) in place, L nb x nb lower
-// (leading dimension ldl), B nb x ncols row-major (leading dimension ldb).
-// One thread per right-hand side; four partial sums break the FMA chain.
-__global__ void k_trsm_lower(const double* __restrict__ L, int nb, int ldl, double* __restrict__ B,
-                             int ncols, int ldb, int trans) {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ncols) return;
-    if (!trans) {
-        for (int i = 0; i < nb; ++i) {
-            double s0 = B[(int64_t)i * ldb + col], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            const double* li = L + (int64_t)i * ldl;
-            int k = 0;
-            for (; k + 3 < i; k += 4) {
-                s0 -= li[k] * B[(int64_t)k * ldb + col];
-                s1 -= li[k + 1] * B[(int64_t)(k + 1) * ldb + col];
-                s2 -= li[k + 2] * B[(int64_t)(k + 2) * ldb + col];
-                s3 -= li[k + 3] * B[(int64_t)(k + 3) * ldb + col];
+// Solve L X = B (trans = 0) or L^T X = B (trans = 1) in place, with L the
+// nb x nb lower Cholesky factor written by k_chol (leading dimension ldl) and
+// dinv the inverses of its 32 x 32 diagonal tiles; B is nb x ncols row-major
+// (leading dimension ldb). Blocked substitution over 32-row blocks: block i
+// of X is dinv_i (B_i - sum_{j<i} L_ij X_j) (forward) or
+// dinv_i^T (B_i - sum_{j>i} L_ji^T X_j) (backward). One workgroup solves
+// TS_COLS right-hand sides, held in LDS; thread (r, c) owns row r of the
+// current block in column c.
+constexpr int TS_COLS = 8;
+constexpr int TS_T = 32;
+constexpr int TS_THREADS = TS_COLS * TS_T;
+
+__global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __restrict__ L, int nb,
+                                                             int ldl, const double* __restrict__ dinv,
+                                                             double* __restrict__ B, int ncols,
+                                                             int ldb, int trans) {
+    __shared__ double Xs[CH_NB][TS_COLS];
+    __shared__ double As[TS_T][TS_COLS];
+    const int tid = threadIdx.x;
+    const int r = tid / TS_COLS, c = tid % TS_COLS;
+    const int col = blockIdx.x * TS_COLS + c;
+    const bool con = col < ncols;
+    const int nt = (nb + TS_T - 1) / TS_T;
+    for (int k = r; k < nt * TS_T; k += TS_T)
+        Xs[k][c] = (con && k < nb) ? B[(int64_t)k * ldb + col] : 0.0;
+    __syncthreads();
+    for (int step = 0; step < nt; ++step) {
+        const int i = trans ? nt - 1 - step : step;
+        const int row = i * TS_T + r;
+        double acc = 0.0;
+        if (row < nb) {
+            double a0 = Xs[row][c], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            if (!trans) {
+                const double* lr = L + (int64_t)row * ldl;
+                const int kend = i * TS_T;
+                int k = 0;
+                for (; k + 4 <= kend; k += 4) {
+                    a0 -= lr[k] * Xs[k][c];
+                    a1 -= lr[k + 1] * Xs[k + 1][c];
+                    a2 -= lr[k + 2] * Xs[k + 2][c];
+                    a3 -= lr[k + 3] * Xs[k + 3][c];
+                }
+                for (; k < kend; ++k) a0 -= lr[k] * Xs[k][c];
+            } else {
+                int k = (i + 1) * TS_T;
+                for (; k + 4 <= nb; k += 4) {
+                    a0 -= L[(int64_t)k * ldl + row] * Xs[k][c];
+                    a1 -= L[(int64_t)(k + 1) * ldl + row] * Xs[k + 1][c];
+                    a2 -= L[(int64_t)(k + 2) * ldl + row] * Xs[k + 2][c];
+                    a3 -= L[(int64_t)(k + 3) * ldl + row] * Xs[k + 3][c];
+                }
+                for (; k < nb; ++k) a0 -= L[(int64_t)k * ldl + row] * Xs[k][c];
             }
-            for (; k < i; ++k) s0 -= li[k] * B[(int64_t)k * ldb + col];
-            B[(int64_t)i * ldb + col] = ((s0 + s1) + (s2 + s3)) / li[i];
+            acc = (a0 + a1) + (a2 + a3);
         }
-    } else {
-        for (int i = nb - 1; i >= 0; --i) {
-            double s0 = B[(int64_t)i * ldb + col], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int k = i + 1;
-            for (; k + 3 < nb; k += 4) {
-                s0 -= L[(int64_t)k * ldl + i] * B[(int64_t)k * ldb + col];
-                s1 -= L[(int64_t)(k + 1) * ldl + i] * B[(int64_t)(k + 1) * ldb + col];
-                s2 -= L[(int64_t)(k + 2) * ldl + i] * B[(int64_t)(k + 2) * ldb + col];
-                s3 -= L[(int64_t)(k + 3) * ldl + i] * B[(int64_t)(k + 3) * ldb + col];
-            }
-            for (; k < nb; ++k) s0 -= L[(int64_t)k * ldl + i] * B[(int64_t)k * ldb + col];
-            B[(int64_t)i * ldb + col] = ((s0 + s1) + (s2 + s3)) / L[(int64_t)i * ldl + i];
+        As[r][c] = acc;
+        __syncthreads();
+        const double* di = dinv + (int64_t)i * TS_T * TS_T;
+        double x = 0.0;
+        if (!trans) {
+            for (int q = 0; q <= r; ++q) x += di[r * TS_T + q] * As[q][c];
+        } else {
+            for (int q = r; q < TS_T; ++q) x += di[q * TS_T + r] * As[q][c];
         }
+        if (row < nb) Xs[row][c] = x;
+        __syncthreads();
     }
+    if (con)
+        for (int k = r; k < nb; k += TS_T) B[(int64_t)k * ldb + col] = Xs[k][c];
 }
 
 // C = alpha * op(A) op(B) + beta * C; op(X) = X or X^T; row-major with leading dims.
@@ -456,20 +496,27 @@ void launch_identity_minus(const double* K, int b, double* out, hipStream_t s) {
 }
 
 void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,
-                 hipStream_t s) {
+                 hipStream_t s, double* dinv) {
     if (nb > CH_NB) throw SicError(SIC_ETOOBIG, "block larger than the Cholesky kernel supports");
+    if (dinv && batch != 1) throw SicError(SIC_EINTERNAL, "diagonal-tile inverses need batch 1");
     prof_begin(KK_CHOL, s);
-    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(CH_THREADS), 0, s, M, stride, nb, ld, identity, out);
+    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(CH_THREADS), 0, s, M, stride, nb, ld, identity, out,
+                       dinv);
     SIC_CHECK_LAUNCH();
     prof_end(KK_CHOL, s, 16.0 * nb * nb * (double)batch, (double)nb * nb * nb / 3.0 * batch);
 }
 
-void launch_trsm_lower(const double* L, int nb, int ldl, double* B, int ncols, int ldb, int trans,
-                       hipStream_t s) {
+void launch_trsm_lower(const double* L, int nb, int ldl, const double* dinv, double* B, int ncols,
+                       int ldb, int trans, hipStream_t s) {
     if (ncols <= 0 || nb <= 0) return;
-    hipLaunchKernelGGL(k_trsm_lower, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, s, L, nb, ldl,
-                       B, ncols, ldb, trans);
+    if (nb > CH_NB) throw SicError(SIC_ETOOBIG, "block larger than the triangular solve supports");
+    prof_begin(KK_TRSM, s);
+    hipLaunchKernelGGL(k_trsm_blocked, dim3((unsigned)((ncols + TS_COLS - 1) / TS_COLS)),
+                       dim3(TS_THREADS), 0, s, L, nb, ldl, dinv, B, ncols, ldb, trans);
     SIC_CHECK_LAUNCH();
+    // the triangle of L once per workgroup (from L2), B read and written once
+    prof_end(KK_TRSM, s, 8.0 * (double)nb * nb / 2.0 + 16.0 * (double)nb * ncols,
+             (double)nb * nb * ncols);
 }
 
 void launch_gemm_small(int M, int N, int K, double alpha, const double* A, int lda, int ta,

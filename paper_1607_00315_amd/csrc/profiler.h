@@ -16,6 +16,7 @@ enum KernelKind {
     KK_GEMM,
     KK_UPD_ROWS,
     KK_CD_HESS,
+    KK_TRSM,
     KK_COUNT
 };
 

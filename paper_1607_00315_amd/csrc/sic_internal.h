@@ -162,11 +162,13 @@ void launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t
                        double tol, double* HT, double* delta, double* stats, hipStream_t s);
 
 // ---------------------------------------------------------------- k_dense.hip
+// dinv (batch 1 only, may be null) receives the inverses of the factor's
+// 32 x 32 diagonal tiles (8 x 1024 doubles), which launch_trsm_lower consumes.
 void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,
-                 hipStream_t s);
+                 hipStream_t s, double* dinv = nullptr);
 void launch_zero_upper(double* M, int nb, int ld, hipStream_t s);
-void launch_trsm_lower(const double* L, int nb, int ldl, double* B, int ncols, int ldb, int trans,
-                       hipStream_t s);
+void launch_trsm_lower(const double* L, int nb, int ldl, const double* dinv, double* B, int ncols,
+                       int ldb, int trans, hipStream_t s);
 void launch_gemm_small(int M, int N, int K, double alpha, const double* A, int lda, int ta,
                        const double* B, int ldb, int tb, double beta, double* C, int ldc,
                        hipStream_t s);

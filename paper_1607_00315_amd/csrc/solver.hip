@@ -61,6 +61,7 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN) {
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
     const size_t bb = (size_t)b * b;
+    W.Dinv.reserve(8 * 1024);
     W.Rb.reserve(bb); W.D11.reserve(bb); W.Mo.reserve(bb); W.Pm.reserve(bb);
     W.T1.reserve(bb); W.D1.reserve(bb); W.X.reserve(bb); W.XtX.reserve(bb);
     W.RPR.reserve(bb); W.E1.reserve(bb); W.E2.reserve(bb);
@@ -71,13 +72,13 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN) {
     W.lin.reserve(4);
     // R R^T = W_II
     launch_copy_block(W.WJJ.p, jp, b, W.Rb.p, s);
-    launch_chol(W.Rb.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s);
+    launch_chol(W.Rb.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s, W.Dinv.p);
     launch_zero_upper(W.Rb.p, b, b, s);
     launch_ls_terms(W.cptr.p, W.c_p.p, W.delta.p, W.WJJ.p, jp, b, (int)nN, W.D11.p, W.Mo.p, W.Y.p,
                     W.Pm.p, s);
     // X = R^{-1} (M^T R) = K1^T
     launch_gemm_small(b, b, b, 1.0, W.Mo.p, b, 1, W.Rb.p, b, 0, 0.0, W.X.p, b, s);
-    launch_trsm_lower(W.Rb.p, b, b, W.X.p, b, b, 0, s);
+    launch_trsm_lower(W.Rb.p, b, b, W.Dinv.p, W.X.p, b, b, 0, s);
     // D1 = R^T Delta_II R
     launch_gemm_small(b, b, b, 1.0, W.D11.p, b, 0, W.Rb.p, b, 0, 0.0, W.T1.p, b, s);
     launch_gemm_small(b, b, b, 1.0, W.Rb.p, b, 1, W.T1.p, b, 0, 0.0, W.D1.p, b, s);
@@ -416,17 +417,17 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
             R.cg_res_N = cg.max_rel_res;
         }
         const size_t bb = (size_t)b * b;
-        W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb);
+        W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb); W.Dinv.reserve(8 * 1024);
         W.err.reserve(1);
         W.chol_out.reserve(16);
         SIC_HIP(hipMemsetAsync(W.err.p, 0, sizeof(int32_t), s));
         launch_a2_k(A, j0, b, W.WNC.p, nC, W.cmap.p, W.Kb.p, W.err.p, s);
         launch_dense_aii(A, j0, b, W.AII.p, s);
-        launch_chol(W.AII.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s);
+        launch_chol(W.AII.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s, W.Dinv.p);
         launch_zero_upper(W.AII.p, b, b, s);
         launch_identity_minus(W.Kb.p, b, W.WII.p, s);
-        launch_trsm_lower(W.AII.p, b, b, W.WII.p, b, b, 0, s);
-        launch_trsm_lower(W.AII.p, b, b, W.WII.p, b, b, 1, s);
+        launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 0, s);
+        launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 1, s);
         double h[2];
         int32_t herr = 0;
         SIC_HIP(hipMemcpyAsync(h, W.chol_out.p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));

@@ -439,7 +439,7 @@ def hierarchy(n, supp_keys, free_keys, free_absg):
     return rank[:rlen.value], list(sizes[:nl.value])
 
 
-KERNEL_CLASSES = 10
+KERNEL_CLASSES = 11
 
 
 def profile_enable(on=True):

@@ -18,9 +18,6 @@ namespace sic {
 namespace {
 
 constexpr int CH_NB = 256;        // largest block handled by the Cholesky kernel
-constexpr int CH_T = 32;          // tile width
-constexpr int CH_PMAX = CH_NB - CH_T;
-constexpr int CH_PLD = CH_T + 1;  // padded panel row
 
 // In-place lower Cholesky of one nb x nb matrix per workgroup (batch over
 // blockIdx.x, matrices `stride` doubles apart, leading dimension ld).
@@ -36,204 +33,199 @@ constexpr int CH_PLD = CH_T + 1;  // padded panel row
 // identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
 // out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0. Only the lower
 // triangle is read; the factor overwrites it and the upper triangle is zeroed.
-__device__ constexpr int tslot(int bi, int bj) { return bi * (bi + 1) / 2 + bj; }
+typedef double chol_d4 __attribute__((ext_vector_type(4)));
 
+constexpr int CB = 16;                  // block size of the factorization
+constexpr int CB_N = CH_NB / CB;        // block rows of the largest matrix
 constexpr int CH_THREADS = 512;
-constexpr int CH_NT = CH_NB / CH_T;
+constexpr int CH_WAVES = CH_THREADS / 64;
+constexpr int CB_PLD = CB + 1;          // padded LDS row (17 doubles)
+constexpr int CB_RLD = CB + 2;          // padded row of a staged L block (18 doubles, 16-byte aligned)
 
 struct CholShared {
-    double D[CH_T * CH_PLD];           // diagonal tile, then its factor (lower)
-    double Li[CH_T * CH_PLD];          // inverse of the diagonal factor (lower)
-    double Pn[CH_NT][CH_T * CH_PLD];   // panel tiles of the current tile column
+    double Rk[CB_N][CB * CB_RLD];       // row block kb of L (the blocks left of the diagonal)
+    double Pn[CB_N][CB * CB_PLD];       // updated blocks of column kb, accumulator layout
+    double Part[CH_WAVES][4 * 64];      // partial sums when a block's K range is split
+    double Lik[CB * CB_PLD];            // inverse of the diagonal factor (lower)
     int bad;
     double logdet;
 };
 
-// Tile column KB of the register-resident factorization. Written as a
-// template so that every register tile index is a compile-time constant.
-template <int KB>
-__device__ __forceinline__ void chol_step(double (&reg)[CH_NT * (CH_NT + 1) / 2][2],
-                                          CholShared& sh, int nt, int identity, bool& alive,
-                                          double* __restrict__ dinv) {
-    constexpr int T = CH_T, NT = CH_NT, PL = CH_PLD, H = T / 2;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int ti = tid / T, tj = tid % T;
-    if (KB >= nt || !alive) return;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int r = ti + H * h;
-        sh.D[r * PL + tj] = (tj <= r) ? reg[tslot(KB, KB)][h] : 0.0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        double ld_acc = 0.0;
-        int bad = 0;
-        for (int k = 0; k < T; ++k) {
-            const double t = sh.D[k * PL + k];
-            const double piv = identity ? 1.0 + t : t;
-            if (!(piv > 0.0) || !isfinite(piv)) {
-                bad = 1;
-                break;
-            }
-            ld_acc += identity ? log1p(t) : log(t);
-            const double lkk = sqrt(piv);
-            if (lane > k && lane < T) sh.D[lane * PL + k] /= lkk;
-            if (lane == 0) sh.D[k * PL + k] = lkk;
-            for (int idx = lane; idx < T * T; idx += 64) {
-                const int i = idx / T, j = idx - i * T;
-                if (j > k && j <= i) sh.D[i * PL + j] -= sh.D[i * PL + k] * sh.D[j * PL + k];
-            }
-        }
-        if (!bad && lane < T) {
-            // Li = D^{-1}: lane j computes column j by forward substitution
-            const int j = lane;
-            for (int i = 0; i < j; ++i) sh.Li[i * PL + j] = 0.0;
-            sh.Li[j * PL + j] = 1.0 / sh.D[j * PL + j];
-            for (int i = j + 1; i < T; ++i) {
-                double sacc = 0.0;
-                for (int q = j; q < i; ++q) sacc += sh.D[i * PL + q] * sh.Li[q * PL + j];
-                sh.Li[i * PL + j] = -sacc / sh.D[i * PL + i];
-            }
-        }
-        if (lane == 0) {
-            sh.logdet += ld_acc;
-            if (bad) sh.bad = 1;
-        }
-    }
-    __syncthreads();
-    alive = !sh.bad;
-    if (!alive) return;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int r = ti + H * h;
-        reg[tslot(KB, KB)][h] = (tj <= r) ? sh.D[r * PL + tj] : 0.0;
-        if (dinv) dinv[KB * T * T + r * T + tj] = sh.Li[r * PL + tj];
-    }
-    if (KB + 1 >= NT) return;
-    // panel tiles: stage A_(ib,KB), then L_(ib,KB) = A_(ib,KB) L_KB^{-T}
-#pragma unroll
-    for (int ib = KB + 1; ib < NT; ++ib)
-        if (ib < nt)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) sh.Pn[ib][(ti + H * h) * PL + tj] = reg[tslot(ib, KB)][h];
-    __syncthreads();
-#pragma unroll
-    for (int ib = KB + 1; ib < NT; ++ib)
-        if (ib < nt)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const double* prow = &sh.Pn[ib][(ti + H * h) * PL];
-                double sacc = 0.0;
-                for (int q = 0; q <= tj; ++q) sacc += prow[q] * sh.Li[tj * PL + q];
-                reg[tslot(ib, KB)][h] = sacc;
-            }
-    __syncthreads();
-#pragma unroll
-    for (int ib = KB + 1; ib < NT; ++ib)
-        if (ib < nt)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) sh.Pn[ib][(ti + H * h) * PL + tj] = reg[tslot(ib, KB)][h];
-    __syncthreads();
-    // trailing lower tiles: A_(ib,jb) -= L_(ib,KB) L_(jb,KB)^T
-#pragma unroll
-    for (int ib = KB + 1; ib < NT; ++ib)
-#pragma unroll
-        for (int jb = KB + 1; jb <= ib; ++jb)
-            if (ib < nt) {
-                const double* pj = &sh.Pn[jb][tj * PL];
-                const double* p0 = &sh.Pn[ib][ti * PL];
-                const double* p1 = &sh.Pn[ib][(ti + H) * PL];
-                double s0 = 0.0, s1 = 0.0;
-#pragma unroll 8
-                for (int q = 0; q < T; ++q) {
-                    const double w = pj[q];
-                    s0 += p0[q] * w;
-                    s1 += p1[q] * w;
-                }
-                reg[tslot(ib, jb)][0] -= s0;
-                reg[tslot(ib, jb)][1] -= s1;
-            }
+__device__ inline double chol_readlane(double v, int l) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-
-template <int KB>
-struct CholSteps {
-    __device__ __forceinline__ static void run(double (&reg)[CH_NT * (CH_NT + 1) / 2][2],
-                                               CholShared& sh, int nt, int identity, bool& alive,
-                                               double* __restrict__ dinv) {
-        chol_step<KB>(reg, sh, nt, identity, alive, dinv);
-        CholSteps<KB + 1>::run(reg, sh, nt, identity, alive, dinv);
-    }
-};
-template <>
-struct CholSteps<CH_NT> {
-    __device__ __forceinline__ static void run(double (&)[CH_NT * (CH_NT + 1) / 2][2], CholShared&,
-                                               int, int, bool&, double*) {}
-};
 
 // In-place lower Cholesky of one nb x nb matrix (nb <= 256) per workgroup
 // (batch over blockIdx.x, matrices `stride` doubles apart, leading dimension
-// ld). The lower triangle is held in registers as 32 x 32 tiles: thread
-// (ti, tj), ti < 16, owns entries (ti, tj) and (ti + 16, tj) of each of the 36
-// lower tiles (144 VGPRs at two waves per SIMD). Per tile column:
-//   1. the diagonal tile goes to LDS, where one wave factors it and inverts
-//      the factor (LDS operations of one wave execute in order),
-//   2. each panel tile below is staged in LDS and multiplied by L_kk^{-T},
-//   3. the trailing lower tiles are updated in registers from the panel in LDS.
-// Global memory is touched only by the initial load and the final store.
+// ld), left-looking over 16-column block columns; the factor is written in
+// place and re-read from there (the matrix stays in L2). For block column kb:
+//   1. row block kb of L (left of the diagonal) is staged in LDS;
+//   2. C_I = A_{I,kb} - sum_j L_{I,j} L_{kb,j}^T for every block row I >= kb on
+//      FP64 MFMA (16x16x4); when few block rows remain, their K ranges are
+//      split over the waves and the partial sums added in a fixed order;
+//   3. one wave factors C_kk and inverts the factor in registers (rows in
+//      lanes 0..15, the pivot row broadcast with readlane);
+//   4. each panel block becomes L_I = C_I L_kk^{-T} (4 MFMAs) and is stored.
 // identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
 // out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0. Only the lower
-// triangle is read; the factor overwrites it and the upper triangle is zeroed.
-// dinv (batch 1 only, may be null): the inverses of the 32 x 32 diagonal
-// tiles of the factor, tile k at dinv + 1024 k, row-major (written when PD).
+// triangle is read; the factor overwrites it (partly, when not PD) and the
+// upper triangle of the diagonal blocks is zeroed (the blocks above them are
+// left untouched). dinv (batch 1 only, may be null): the inverses of the
+// 16 x 16 diagonal blocks of the factor, block k at dinv + 256 k, row-major.
 __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int64_t stride,
                                                      int nb, int ld, int identity,
                                                      double* __restrict__ out,
                                                      double* __restrict__ dinv) {
-    constexpr int T = CH_T, NT = CH_NT, H = T / 2;
     __shared__ CholShared sh;
     double* A = M + (int64_t)blockIdx.x * stride;
     const int tid = threadIdx.x;
-    const int ti = tid / T, tj = tid % T;
-    const int nt = (nb + T - 1) / T;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lr = lane >> 4, lc = lane & 15;
+    const int nt = (nb + CB - 1) / CB;
     const double pad = identity ? 0.0 : 1.0;   // padded diagonal: contributes log 1 = 0
-    double reg[NT * (NT + 1) / 2][2];
-#pragma unroll
-    for (int bi = 0; bi < NT; ++bi)
-#pragma unroll
-        for (int bj = 0; bj <= bi; ++bj)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int i = bi * T + ti + H * h, j = bj * T + tj;
-                double v = 0.0;
-                if (bi < nt) {
-                    if (i < nb && j < nb) {
-                        if (j <= i) v = A[(int64_t)i * ld + j];
-                    } else if (i == j) {
-                        v = pad;
-                    }
-                }
-                reg[tslot(bi, bj)][h] = v;
-            }
     if (tid == 0) {
         sh.bad = 0;
         sh.logdet = 0.0;
     }
-    bool alive = true;   // uniform: cleared in every thread once a pivot fails
-    CholSteps<0>::run(reg, sh, nt, identity, alive, dinv);
-    __syncthreads();
-    if (!sh.bad) {
+    for (int kb = 0; kb < nt; ++kb) {
+        const int r0 = kb * CB;
+        // (1) stage L_{kb, 0:kb}: Rk[j][r][c] = L[r0 + r][j*16 + c]
+        for (int e = tid; e < kb * CB * CB; e += CH_THREADS) {
+            const int j = e / (CB * CB), rc = e - j * CB * CB;
+            const int r = rc / CB, c = rc - r * CB;
+            const int row = r0 + r;
+            sh.Rk[j][r * CB_RLD + c] = row < nb ? A[(int64_t)row * ld + j * CB + c] : 0.0;
+        }
+        __syncthreads();
+        // (2) C_I for I = kb .. nt-1; ws waves share one block row when there are few
+        const int nout = nt - kb;
+        const int ws = nout >= CH_WAVES ? 1 : CH_WAVES / nout;
+        const int groups = CH_WAVES / ws;
+        const int slice = wave % ws;
+        const int jlo = slice * kb / ws, jhi = (slice + 1) * kb / ws;
+        for (int bi = wave / ws; bi < nout; bi += groups) {
+            const int I = kb + bi;
+            chol_d4 acc;
 #pragma unroll
-        for (int bi = 0; bi < NT; ++bi)
-#pragma unroll
-            for (int bj = 0; bj <= bi; ++bj)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int i = bi * T + ti + H * h, j = bj * T + tj;
-                    if (bi < nt && i < nb && j < nb) {
-                        A[(int64_t)i * ld + j] = (j <= i) ? reg[tslot(bi, bj)][h] : 0.0;
-                        if (bj == bi && j < i) A[(int64_t)j * ld + i] = 0.0;
+            for (int v = 0; v < 4; ++v) {
+                const int row = I * CB + lr + 4 * v, col = r0 + lc;
+                double val = 0.0;
+                if (slice == 0) {
+                    if (row < nb && col < nb) {
+                        if (col <= row) val = A[(int64_t)row * ld + col];
+                    } else if (row == col) {
+                        val = pad;
                     }
                 }
+                acc[v] = val;
+            }
+            const int arow = I * CB + lc;   // A operand: row lc of L_{I,j}, columns 4 lr .. 4 lr + 3
+            for (int j = jlo; j < jhi; ++j) {
+                double a[4], bv[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    a[t] = arow < nb ? -A[(int64_t)arow * ld + j * CB + 4 * lr + t] : 0.0;
+                    bv[t] = sh.Rk[j][lc * CB_RLD + 4 * lr + t];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv[t], acc, 0, 0, 0);
+            }
+            if (ws > 1) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sh.Part[wave][v * 64 + lane] = acc[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sh.Pn[I][(lr + 4 * v) * CB_PLD + lc] = acc[v];
+            }
+        }
+        __syncthreads();
+        if (ws > 1 && slice == 0 && wave / ws < nout) {
+            const int I = kb + wave / ws;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double sacc = 0.0;
+                for (int q = 0; q < ws; ++q) sacc += sh.Part[wave + q][v * 64 + lane];
+                sh.Pn[I][(lr + 4 * v) * CB_PLD + lc] = sacc;
+            }
+        }
+        __syncthreads();
+        // (3) factor and invert the diagonal block
+        if (wave == 0) {
+            const bool on = lane < CB;
+            double rw[CB];
+#pragma unroll
+            for (int j = 0; j < CB; ++j) rw[j] = on ? sh.Pn[kb][lane * CB_PLD + j] : 0.0;
+            double tsave = 1.0;
+            int bad = 0;
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                const double t = chol_readlane(rw[k], k);
+                const double piv = identity ? 1.0 + t : t;
+                if (!(piv > 0.0) || !isfinite(piv)) bad = 1;
+                const double lkk = sqrt(piv);
+                const double ikk = 1.0 / lkk;
+                if (lane == k) tsave = t;
+                rw[k] = (lane == k) ? lkk : rw[k] * ikk;   // lanes > k: L_ik
+#pragma unroll
+                for (int j = k + 1; j < CB; ++j) rw[j] -= rw[k] * chol_readlane(rw[k], j);
+            }
+            // rows of the inverse factor: right-looking forward substitution
+            double li[CB];
+#pragma unroll
+            for (int j = 0; j < CB; ++j) li[j] = (lane == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                const double ikk = 1.0 / chol_readlane(rw[k], k);
+                const double f = (lane > k) ? rw[k] : 0.0;
+#pragma unroll
+                for (int j = 0; j <= k; ++j) {
+                    if (lane == k) li[j] *= ikk;             // row k of the inverse is final
+                    li[j] -= f * chol_readlane(li[j], k);    // rows below: subtract L_ik (row k)
+                }
+            }
+            double lg = (on && !bad) ? (identity ? log1p(tsave) : log(tsave)) : 0.0;
+            for (int off = 32; off > 0; off >>= 1) lg += __shfl_xor(lg, off, 64);
+            if (on) {
+                const int row = r0 + lane;
+#pragma unroll
+                for (int j = 0; j < CB; ++j) {
+                    const double lv = (j <= lane) ? rw[j] : 0.0;
+                    const double iv = (j <= lane) ? li[j] : 0.0;
+                    sh.Lik[lane * CB_PLD + j] = iv;
+                    if (row < nb && r0 + j < nb) A[(int64_t)row * ld + r0 + j] = lv;
+                    if (dinv && !bad) dinv[kb * CB * CB + lane * CB + j] = iv;
+                }
+            }
+            if (lane == 0) {
+                sh.logdet += lg;
+                if (bad) sh.bad = 1;
+            }
+        }
+        __syncthreads();
+        if (sh.bad) break;
+        // (4) panel blocks L_I = C_I L_kk^{-T}
+        for (int I = kb + 1 + wave; I < nt; I += CH_WAVES) {
+            chol_d4 r = {0.0, 0.0, 0.0, 0.0};
+            double a[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = sh.Pn[I][lc * CB_PLD + 4 * lr + t];
+                bv[t] = sh.Lik[lc * CB_PLD + 4 * lr + t];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) r = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv[t], r, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = I * CB + lr + 4 * v, col = r0 + lc;
+                if (row < nb && col < nb) A[(int64_t)row * ld + col] = r[v];
+            }
+        }
+        __syncthreads();   // the new block column of L is visible to the next step
     }
     if (tid == 0) {
         out[2 * blockIdx.x] = sh.logdet;
@@ -243,14 +235,14 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
 
 // Solve L X = B (trans = 0) or L^T X = B (trans = 1) in place, with L the
 // nb x nb lower Cholesky factor written by k_chol (leading dimension ldl) and
-// dinv the inverses of its 32 x 32 diagonal tiles; B is nb x ncols row-major
-// (leading dimension ldb). Blocked substitution over 32-row blocks: block i
+// dinv the inverses of its 16 x 16 diagonal blocks; B is nb x ncols row-major
+// (leading dimension ldb). Blocked substitution over 16-row blocks: block i
 // of X is dinv_i (B_i - sum_{j<i} L_ij X_j) (forward) or
 // dinv_i^T (B_i - sum_{j>i} L_ji^T X_j) (backward). One workgroup solves
 // TS_COLS right-hand sides, held in LDS; thread (r, c) owns row r of the
 // current block in column c.
-constexpr int TS_COLS = 8;
-constexpr int TS_T = 32;
+constexpr int TS_COLS = 16;
+constexpr int TS_T = CB;   // the factor's diagonal-block size (dinv layout)
 constexpr int TS_THREADS = TS_COLS * TS_T;
 
 __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __restrict__ L, int nb,

@@ -163,7 +163,7 @@ void launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t
 
 // ---------------------------------------------------------------- k_dense.hip
 // dinv (batch 1 only, may be null) receives the inverses of the factor's
-// 32 x 32 diagonal tiles (8 x 1024 doubles), which launch_trsm_lower consumes.
+// 16 x 16 diagonal blocks (16 x 256 doubles), which launch_trsm_lower consumes.
 void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,
                  hipStream_t s, double* dinv = nullptr);
 void launch_zero_upper(double* M, int nb, int ld, hipStream_t s);

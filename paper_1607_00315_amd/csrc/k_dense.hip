@@ -40,7 +40,8 @@ constexpr int CB_N = CH_NB / CB;        // block rows of the largest matrix
 constexpr int CH_THREADS = 512;
 constexpr int CH_WAVES = CH_THREADS / 64;
 constexpr int CB_PLD = CB + 1;          // padded LDS row (17 doubles)
-constexpr int CB_RLD = CB + 2;          // padded row of a staged L block (18 doubles, 16-byte aligned)
+
+constexpr int CB_RLD = CB + 2;          // padded row of a staged L block (18 doubles)
 
 struct CholShared {
     double Rk[CB_N][CB * CB_RLD];       // row block kb of L (the blocks left of the diagonal)
@@ -50,6 +51,22 @@ struct CholShared {
     int bad;
     double logdet;
 };
+
+// Barrier for LDS traffic only: outstanding global stores and loads stay in
+// flight across it.
+__device__ inline void chol_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// p[idx] when cond, else dflt, with the load itself unconditional (index 0
+// when !cond, which must be a valid element): a predicated load would become
+// a branch that waits for its data before the next load is issued.
+__device__ inline double load_or(const double* __restrict__ p, int64_t idx, bool cond, double dflt) {
+    const double v = p[cond ? idx : 0];
+    return cond ? v : dflt;
+}
 
 __device__ inline double chol_readlane(double v, int l) {
     const long long bits = __double_as_longlong(v);
@@ -62,19 +79,24 @@ __device__ inline double chol_readlane(double v, int l) {
 // (batch over blockIdx.x, matrices `stride` doubles apart, leading dimension
 // ld), left-looking over 16-column block columns; the factor is written in
 // place and re-read from there (the matrix stays in L2). For block column kb:
-//   1. row block kb of L (left of the diagonal) is staged in LDS;
-//   2. C_I = A_{I,kb} - sum_j L_{I,j} L_{kb,j}^T for every block row I >= kb on
-//      FP64 MFMA (16x16x4); when few block rows remain, their K ranges are
+//   1. row block kb of L is staged in LDS; C_I = A_{I,kb} - sum_j L_{I,j}
+//      L_{kb,j}^T for every block row I >= kb on FP64 MFMA (16x16x4), the
+//      L_{I,j} operands read from the stored factor, all of a step's loads
+//      in flight at once; when few block rows remain, their K ranges are
 //      split over the waves and the partial sums added in a fixed order;
-//   3. one wave factors C_kk and inverts the factor in registers (rows in
+//   2. one wave factors C_kk and inverts the factor in registers (rows in
 //      lanes 0..15, the pivot row broadcast with readlane);
-//   4. each panel block becomes L_I = C_I L_kk^{-T} (4 MFMAs) and is stored.
+//   3. each panel block becomes L_I = C_I L_kk^{-T} (4 MFMAs) and is stored.
+// Only the panel stores are re-read inside the kernel, so only the barrier
+// that ends a block column waits for global stores.
 // identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
 // out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0. Only the lower
-// triangle is read; the factor overwrites it (partly, when not PD) and the
-// upper triangle of the diagonal blocks is zeroed (the blocks above them are
-// left untouched). dinv (batch 1 only, may be null): the inverses of the
-// 16 x 16 diagonal blocks of the factor, block k at dinv + 256 k, row-major.
+// triangle is read; the factor overwrites it (partly, when not PD), the upper
+// triangle of the diagonal blocks is zeroed and the blocks above them receive
+// the transpose of the factor (the kernel's own operand copy; callers that
+// need a clean lower factor zero them). dinv (batch 1 only, may be null): the
+// inverses of the 16 x 16 diagonal blocks of the factor, block k at
+// dinv + 256 k, row-major.
 __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int64_t stride,
                                                      int nb, int ld, int identity,
                                                      double* __restrict__ out,
@@ -93,57 +115,85 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
     }
     for (int kb = 0; kb < nt; ++kb) {
         const int r0 = kb * CB;
-        // (1) stage L_{kb, 0:kb}: Rk[j][r][c] = L[r0 + r][j*16 + c]
-        for (int e = tid; e < kb * CB * CB; e += CH_THREADS) {
-            const int j = e / (CB * CB), rc = e - j * CB * CB;
-            const int r = rc / CB, c = rc - r * CB;
-            const int row = r0 + r;
-            sh.Rk[j][r * CB_RLD + c] = row < nb ? A[(int64_t)row * ld + j * CB + c] : 0.0;
-        }
-        __syncthreads();
-        // (2) C_I for I = kb .. nt-1; ws waves share one block row when there are few
+        // (1) C_I for I = kb .. nt-1. With nout >= 8 block rows, wave w takes rows
+        // kb + w and kb + w + 8 (then kb <= 7); with fewer, ws waves split the K
+        // range of one row (then at most 11 block columns per wave). Every load
+        // of the step is issued before the staging barrier: the initial block
+        // values and the L_{I,j} operands, 16 jobs of one block column each.
         const int nout = nt - kb;
         const int ws = nout >= CH_WAVES ? 1 : CH_WAVES / nout;
         const int groups = CH_WAVES / ws;
         const int slice = wave % ws;
         const int jlo = slice * kb / ws, jhi = (slice + 1) * kb / ws;
-        for (int bi = wave / ws; bi < nout; bi += groups) {
-            const int I = kb + bi;
-            chol_d4 acc;
+        const int I0 = kb + wave / ws, I1 = I0 + groups;
+        const int nbw = I0 >= nt ? 0 : (ws == 1 && I1 < nt ? 2 : 1);
+        chol_d4 acc0, acc1;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = I * CB + lr + 4 * v, col = r0 + lc;
-                double val = 0.0;
-                if (slice == 0) {
-                    if (row < nb && col < nb) {
-                        if (col <= row) val = A[(int64_t)row * ld + col];
-                    } else if (row == col) {
-                        val = pad;
-                    }
-                }
-                acc[v] = val;
-            }
-            const int arow = I * CB + lc;   // A operand: row lc of L_{I,j}, columns 4 lr .. 4 lr + 3
-            for (int j = jlo; j < jhi; ++j) {
-                double a[4], bv[4];
+        for (int v = 0; v < 4; ++v) {
+            const int col = r0 + lc;
+            double v0 = 0.0, v1 = 0.0;
+            const int row0 = I0 * CB + lr + 4 * v, row1 = I1 * CB + lr + 4 * v;
+            const bool in0 = slice == 0 && nbw >= 1 && row0 < nb && col < nb && col <= row0;
+            const bool in1 = slice == 0 && nbw == 2 && row1 < nb && col < nb;
+            v0 = load_or(A, (int64_t)row0 * ld + col, in0, 0.0);
+            v1 = load_or(A, (int64_t)row1 * ld + col, in1, 0.0);
+            if (slice == 0 && nbw >= 1 && !(row0 < nb && col < nb) && row0 == col) v0 = pad;
+            if (slice == 0 && nbw == 2 && !(row1 < nb && col < nb) && row1 == col) v1 = pad;
+            acc0[v] = v0;
+            acc1[v] = v1;
+        }
+        constexpr int JOBS = 16;
+        double a[JOBS][4];
+#pragma unroll
+        for (int x = 0; x < JOBS; ++x) {
+            const int q = nbw == 2 ? (x >> 3) : 0;
+            const int j = jlo + (nbw == 2 ? (x & 7) : x);
+            const bool valid = nbw >= 1 && j < jhi;
+            // L_{I,j}[lc][4 lr + t], read from its transpose in the upper triangle so
+            // that 16 consecutive lanes read one contiguous row segment
+            const int acol = (q ? I1 : I0) * CB + lc;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                a[x][t] = -load_or(A, (int64_t)(j * CB + 4 * lr + t) * ld + acol, valid && acol < nb,
+                                   0.0);
+        }
+        // stage L_{kb, 0:kb}: Rk[j][r][c] = L[r0 + r][j*16 + c]
+        for (int e = tid; e < kb * CB * CB; e += CH_THREADS) {
+            const int j = e / (CB * CB), rc = e - j * CB * CB;
+            const int r = rc / CB, c = rc - r * CB;
+            const int row = r0 + r;
+            sh.Rk[j][r * CB_RLD + c] = load_or(A, (int64_t)row * ld + j * CB + c, row < nb, 0.0);
+        }
+        chol_lds_barrier();
+#pragma unroll
+        for (int x = 0; x < JOBS; ++x) {
+            const int q = nbw == 2 ? (x >> 3) : 0;
+            const int j = jlo + (nbw == 2 ? (x & 7) : x);
+            if (nbw >= 1 && j < jhi) {
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    a[t] = arow < nb ? -A[(int64_t)arow * ld + j * CB + 4 * lr + t] : 0.0;
-                    bv[t] = sh.Rk[j][lc * CB_RLD + 4 * lr + t];
+                    const double bv = sh.Rk[j][lc * CB_RLD + 4 * lr + t];
+                    if (q)
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][t], bv, acc1, 0, 0, 0);
+                    else
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][t], bv, acc0, 0, 0, 0);
                 }
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv[t], acc, 0, 0, 0);
-            }
-            if (ws > 1) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sh.Part[wave][v * 64 + lane] = acc[v];
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sh.Pn[I][(lr + 4 * v) * CB_PLD + lc] = acc[v];
             }
         }
-        __syncthreads();
+        if (nbw >= 1) {
+            if (ws > 1) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sh.Part[wave][v * 64 + lane] = acc0[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sh.Pn[I0][(lr + 4 * v) * CB_PLD + lc] = acc0[v];
+            }
+        }
+        if (nbw == 2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sh.Pn[I1][(lr + 4 * v) * CB_PLD + lc] = acc1[v];
+        }
+        chol_lds_barrier();
         if (ws > 1 && slice == 0 && wave / ws < nout) {
             const int I = kb + wave / ws;
 #pragma unroll
@@ -153,14 +203,18 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
                 sh.Pn[I][(lr + 4 * v) * CB_PLD + lc] = sacc;
             }
         }
-        __syncthreads();
+        chol_lds_barrier();
         // (3) factor and invert the diagonal block
         if (wave == 0) {
             const bool on = lane < CB;
             double rw[CB];
 #pragma unroll
-            for (int j = 0; j < CB; ++j) rw[j] = on ? sh.Pn[kb][lane * CB_PLD + j] : 0.0;
+            for (int j = 0; j < CB; ++j) {
+                const double v = sh.Pn[kb][(on ? lane : 0) * CB_PLD + j];
+                rw[j] = on ? v : 0.0;
+            }
             double tsave = 1.0;
+            double ikks[CB];   // 1 / L_kk (uniform)
             int bad = 0;
 #pragma unroll
             for (int k = 0; k < CB; ++k) {
@@ -169,6 +223,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
                 if (!(piv > 0.0) || !isfinite(piv)) bad = 1;
                 const double lkk = sqrt(piv);
                 const double ikk = 1.0 / lkk;
+                ikks[k] = ikk;
                 if (lane == k) tsave = t;
                 rw[k] = (lane == k) ? lkk : rw[k] * ikk;   // lanes > k: L_ik
 #pragma unroll
@@ -180,7 +235,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
             for (int j = 0; j < CB; ++j) li[j] = (lane == j) ? 1.0 : 0.0;
 #pragma unroll
             for (int k = 0; k < CB; ++k) {
-                const double ikk = 1.0 / chol_readlane(rw[k], k);
+                const double ikk = ikks[k];
                 const double f = (lane > k) ? rw[k] : 0.0;
 #pragma unroll
                 for (int j = 0; j <= k; ++j) {
@@ -206,7 +261,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
                 if (bad) sh.bad = 1;
             }
         }
-        __syncthreads();
+        chol_lds_barrier();   // the factor's global copy is not re-read in this kernel
         if (sh.bad) break;
         // (4) panel blocks L_I = C_I L_kk^{-T}
         for (int I = kb + 1 + wave; I < nt; I += CH_WAVES) {
@@ -222,7 +277,10 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = I * CB + lr + 4 * v, col = r0 + lc;
-                if (row < nb && col < nb) A[(int64_t)row * ld + col] = r[v];
+                if (row < nb && col < nb) {
+                    A[(int64_t)row * ld + col] = r[v];
+                    A[(int64_t)col * ld + row] = r[v];   // transposed copy for later steps
+                }
             }
         }
         __syncthreads();   // the new block column of L is visible to the next step

@@ -337,6 +337,34 @@ __global__ void k_cd_hess(int64_t nc, int jp, const int32_t* __restrict__ c_p,
     HT[t * nc + k] = h;
 }
 
+// p[idx] when cond, else dflt, with the load itself unconditional (index 0
+// when !cond, which must be a valid element): a predicated load would become
+// a branch that waits for its data before the next load is issued.
+__device__ inline double load_or(const double* __restrict__ p, int64_t idx, bool cond, double dflt) {
+    const double v = p[cond ? idx : 0];
+    return cond ? v : dflt;
+}
+
+constexpr int CDH_RMAX = 4;    // coordinate rows per thread in the Hessian products (4096 / 1024)
+constexpr int CDH_PAD = 16;    // the nonzero-step list is zero padded to a multiple of this
+
+// One coordinate step of the chain, on lane data broadcast from lane tt:
+// y = x - (S - W_rc + z)/a = p - z/a, soft(y) = y - clamp(y, -lam/a, lam/a),
+// mu = soft(y) - x; every lane then adds mu H[k][tt] to its own z.
+__device__ __forceinline__ void cd_step(int tt, double p, double ia, double thr, double xl, double h,
+                                        int lane, double& z, double& mul, double& maxmu) {
+    const double zt = readlane_d(z, tt);
+    const double pt = readlane_d(p, tt), iat = readlane_d(ia, tt);
+    const double tht = readlane_d(thr, tt), xt = readlane_d(xl, tt);
+    const double y = pt - zt * iat;
+    const double c = fmax(fmin(y, tht), -tht);
+    const double mu = (y - c) - xt;
+    z += mu * h;
+    if (lane == tt) mul = mu;
+    maxmu = fmax(maxmu, fabs(mu));
+}
+
+template <int ROWS>   // coordinate rows per thread: ceil(nc / 1024)
 __global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
     int64_t nc, const double* __restrict__ HT, const double* __restrict__ c_S,
     const double* __restrict__ c_A, const double* __restrict__ c_inva,
@@ -346,8 +374,8 @@ __global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
     double* zs = sm;                    // [nc] z = (W Delta W) on the coordinates
     double* ds = zs + nc;               // [nc] Delta
     double* Hc = ds + nc;               // [CDH_K][CDH_K] diagonal tile of the chunk, [t][k]
-    double* mus = Hc + CDH_K * CDH_K;   // [CDH_K] steps of the chunk
-    int* nzl = (int*)(mus + CDH_K);     // [CDH_K] chunk positions with a nonzero step
+    double* nzm = Hc + CDH_K * CDH_K;   // [CDH_K] nonzero steps of the chunk (zero padded)
+    int* nzl = (int*)(nzm + CDH_K);     // [CDH_K] their chunk positions
     __shared__ double s_red[CDH_WAVES];
     __shared__ int s_nnz, s_stop;
     __shared__ double s_maxmu;
@@ -370,17 +398,18 @@ __global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
         for (int j = 0; j < HPT; ++j) {
             const int e = tid + CDH_THREADS * j;
             const int t = e / CDH_K, k = e % CDH_K;
-            hreg[j] = (t < K && k < K) ? HT[(k0 + t) * nc + k0 + k] : 0.0;
+            hreg[j] = load_or(HT, (k0 + t) * nc + k0 + k, t < K && k < K, 0.0);
         }
     };
     // wave 0: the next chunk's per-coordinate constants, one coordinate per lane
-    double nb_c = 0.0, nA = 0.0, ninva = 0.0;
+    double nS = 0.0, nW = 0.0, nA = 0.0, ninva = 0.0;
     auto load_lane = [&](int ch) {
         const int64_t k = (int64_t)ch * CDH_K + lane;
         const bool on = k < nc;
-        nb_c = on ? c_S[k] - c_wtc[k] : 0.0;
-        nA = on ? c_A[k] : 0.0;
-        ninva = on ? c_inva[k] : 0.0;
+        nS = load_or(c_S, k, on, 0.0);
+        nW = load_or(c_wtc, k, on, 0.0);
+        nA = load_or(c_A, k, on, 0.0);
+        ninva = load_or(c_inva, k, on, 0.0);
     };
     load_tile(0);
     if (wave == 0) load_lane(0);
@@ -401,58 +430,80 @@ __global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
             if (tid == 0) { const long long now = wall_clock64(); tph[2] += now - tlast; tlast = now; }
             load_tile(nch);  // in flight during the chain and the products
             if (wave == 0) {
+                // lanes >= K carry zeros: their steps are exactly 0 and change nothing
                 const bool on = lane < K;
-                const double bc = nb_c, inva = ninva;
-                const double d0 = on ? ds[k0 + lane] : 0.0;
-                const double xl = nA + d0;
-                double z = on ? zs[k0 + lane] : 0.0;
+                const int kl = on ? (int)k0 + lane : (int)k0;
+                const double ia = on ? ninva : 0.0;
+                const double d0 = on ? ds[kl] : 0.0;
+                const double xl = on ? nA + d0 : 0.0;
+                const double p = on ? xl - (nS - nW) * ia : 0.0;
+                const double thr = lam * ia;
+                double z = on ? zs[kl] : 0.0;
                 load_lane(nch);
                 double mul = 0.0;
-                double hn = Hc[lane];
-                for (int tt = 0; tt < K; ++tt) {
-                    const double h = hn;
-                    if (tt + 1 < K) hn = Hc[(tt + 1) * CDH_K + lane];
-                    const double x = readlane_d(xl, tt);
-                    const double ia = readlane_d(inva, tt);
-                    const double bb = readlane_d(bc, tt) + readlane_d(z, tt);
-                    const double y = x - bb * ia;
-                    const double thr = lam * ia;
-                    const double sh = y > thr ? y - thr : (y < -thr ? y + thr : 0.0);
-                    const double mu = sh - x;
-                    z += mu * h;
-                    if (lane == tt) mul = mu;
-                    maxmu = fmax(maxmu, fabs(mu));
+                const int K4 = (K + 3) & ~3;
+                for (int tt = 0; tt < K4; tt += 4) {
+                    const double h0 = Hc[tt * CDH_K + lane], h1 = Hc[(tt + 1) * CDH_K + lane];
+                    const double h2 = Hc[(tt + 2) * CDH_K + lane], h3 = Hc[(tt + 3) * CDH_K + lane];
+                    cd_step(tt, p, ia, thr, xl, h0, lane, z, mul, maxmu);
+                    cd_step(tt + 1, p, ia, thr, xl, h1, lane, z, mul, maxmu);
+                    cd_step(tt + 2, p, ia, thr, xl, h2, lane, z, mul, maxmu);
+                    cd_step(tt + 3, p, ia, thr, xl, h3, lane, z, mul, maxmu);
                 }
                 if (on) {
-                    zs[k0 + lane] = z;
-                    ds[k0 + lane] = d0 + mul;
-                    mus[lane] = mul;
+                    zs[kl] = z;
+                    ds[kl] = d0 + mul;
                 }
-                const unsigned long long nzm = __ballot(on && mul != 0.0);
-                if (on && mul != 0.0)
-                    nzl[__popcll(nzm & ((1ull << lane) - 1ull))] = lane;
-                if (lane == 0) s_nnz = __popcll(nzm);
+                // compacted nonzero steps, zero padded to a multiple of the batch
+                const bool nzs = on && mul != 0.0;
+                const unsigned long long nzm_bits = __ballot(nzs);
+                const int nnz = __popcll(nzm_bits);
+                if (nzs) {
+                    const int pos = __popcll(nzm_bits & ((1ull << lane) - 1ull));
+                    nzl[pos] = lane;
+                    nzm[pos] = mul;
+                }
+                const int npad = (nnz + CDH_PAD - 1) / CDH_PAD * CDH_PAD;
+                if (lane >= nnz && lane < npad) {
+                    nzl[lane] = 0;
+                    nzm[lane] = 0.0;
+                }
+                if (lane == 0) s_nnz = nnz;
             }
             lds_barrier();   // steps of the chunk are in place
             if (tid == 0) { const long long now = wall_clock64(); tph[0] += now - tlast; tlast = now; }
-            // z_k += sum_t H[k][t] mu_t for every coordinate outside the chunk
+            // z_k += sum_t H[k][t] mu_t for every coordinate outside the chunk; a
+            // thread's rows k = tid + 1024 r load their batches together
             const int nnz = s_nnz;
             if (nnz > 0) {
-                for (int64_t k = tid; k < nc; k += CDH_THREADS) {
-                    if (k >= k0 && k < k0 + K) continue;
-                    const double* hk = HT + k0 * nc + k;
-                    double acc = 0.0;
-                    int i = 0;
-                    for (; i + 8 <= nnz; i += 8) {
-                        double hv[8];
+                constexpr int BATCH = ROWS == 1 ? 16 : (ROWS == 2 ? 8 : 4);   // 16 loads in flight
+                const int npad = (nnz + CDH_PAD - 1) / CDH_PAD * CDH_PAD;
+                const double* hcol = HT + k0 * nc;
+                double acc[ROWS];
+                bool rv[ROWS];
+                int64_t rk[ROWS];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) hv[q] = hk[(int64_t)nzl[i + q] * nc];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) acc += hv[q] * mus[nzl[i + q]];
-                    }
-                    for (; i < nnz; ++i) acc += hk[(int64_t)nzl[i] * nc] * mus[nzl[i]];
-                    zs[k] += acc;
+                for (int r = 0; r < ROWS; ++r) {
+                    const int64_t k = tid + (int64_t)CDH_THREADS * r;
+                    rv[r] = k < nc && !(k >= k0 && k < k0 + K);
+                    rk[r] = rv[r] ? k : 0;
+                    acc[r] = 0.0;
                 }
+                for (int i = 0; i < npad; i += BATCH) {
+                    double hv[ROWS][BATCH];
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                        for (int q = 0; q < BATCH; ++q)
+                            hv[r][q] = hcol[(int64_t)nzl[i + q] * nc + rk[r]];
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                        for (int q = 0; q < BATCH; ++q) acc[r] += hv[r][q] * nzm[i + q];
+                }
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r)
+                    if (rv[r]) zs[rk[r]] += acc[r];
             }
             if (tid == 0) { const long long now = wall_clock64(); tph[1] += now - tlast; tlast = now; }
         }
@@ -475,6 +526,291 @@ __global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
         if (s_stop) break;
     }
     for (int64_t k = tid; k < nc; k += CDH_THREADS) delta[k] = ds[k];
+    if (tid == 0) {
+        stats[0] = (double)sweeps;
+        for (int i = 0; i < 3; ++i) stats[3 + i] = (double)tph[i];
+        stats[6] = 0.0;
+    }
+}
+
+
+// ------------------------------------------------------------------------
+// Pipelined explicit-Hessian sweep (blocks whose z, Delta and four 64 x 64
+// tiles fit in LDS). Chunk intervals g = 0, 1, ... (chunk i = g mod C):
+//   wave 0     applies the previous chunk's steps to the rows of chunk i from
+//              the prefetched tile H[chunk i][chunk i-1], then runs the
+//              chain of chunk i on the tile H[chunk i][chunk i] and publishes
+//              its nonzero steps;
+//   waves 1-15 apply the previous chunk's steps to every row outside chunks
+//              i-1 and i (streaming those columns of H^T) and prefetch the
+//              two tiles of the next interval.
+// One barrier per chunk; tiles and step lists are double buffered. The rows
+// of chunk i receive every step before its chain: steps of chunk i-1 from
+// wave 0, older ones from the workers' earlier intervals.
+constexpr int CDP_THREADS = 1024;
+constexpr int CDP_WORKERS = CDP_THREADS - 64;
+constexpr int CDP_TILE = CDH_K * CDH_K;
+constexpr int CDP_TPT = (2 * CDP_TILE + CDP_WORKERS - 1) / CDP_WORKERS;   // tile loads per worker
+
+__device__ __forceinline__ double cd_soft(double y, double t) {
+    return y > t ? y - t : (y < -t ? y + t : 0.0);
+}
+
+template <int ROWS>   // worker rows per thread: ceil(nc / 960)
+__global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
+    int64_t nc, const double* __restrict__ HT, const double* __restrict__ c_S,
+    const double* __restrict__ c_A, const double* __restrict__ c_inva,
+    const double* __restrict__ c_wtc, double lam, int max_sweeps, double tol,
+    double* __restrict__ delta, double* __restrict__ stats) {
+    extern __shared__ double sm[];
+    double* zs = sm;                          // [nc]
+    double* ds = zs + nc;                     // [nc]
+    double* Dt = ds + nc;                     // [2][64 x 64] H[chunk i][chunk i], [t][k]
+    double* St = Dt + 2 * CDP_TILE;           // [2][64 x 64] H[chunk i][chunk i-1], [t][k]
+    double* cst = St + 2 * CDP_TILE;          // [3][64] chain constants p, 1/a, x
+    double* mud = cst + 3 * CDH_K;            // [2][64] steps of the chunk, dense (0 when none)
+    double* nzm = mud + 2 * CDH_K;            // [2][64] nonzero steps (zero padded)
+    int* nzl = (int*)(nzm + 2 * CDH_K);       // [2][64] their chunk positions
+    __shared__ int s_nnz[2];
+    __shared__ int s_stop;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int C = (int)((nc + CDH_K - 1) / CDH_K);
+    auto klen = [&](int c) {
+        const int64_t r = nc - (int64_t)c * CDH_K;
+        return (int)(r < CDH_K ? r : CDH_K);
+    };
+    // worker: load the tiles of chunk ci (and its predecessor cp) into registers
+    double treg[CDP_TPT];
+    auto load_tiles = [&](int ci, int cp) {
+        const int64_t ki = (int64_t)ci * CDH_K, kp = (int64_t)cp * CDH_K;
+        const int Ki = klen(ci), Kp = klen(cp);
+#pragma unroll
+        for (int r = 0; r < CDP_TPT; ++r) {
+            const int e = (tid - 64) + CDP_WORKERS * r;
+            const int which = e / CDP_TILE, f = e % CDP_TILE;
+            const int t = f / CDH_K, k = f % CDH_K;
+            const bool dtile = which == 0;
+            const bool ok = e < 2 * CDP_TILE && k < Ki && (dtile ? t < Ki : t < Kp);
+            const int64_t col = (dtile ? ki : kp) + t;
+            treg[r] = load_or(HT, col * nc + ki + k, ok, 0.0);
+        }
+    };
+    auto store_tiles = [&](int b) {
+#pragma unroll
+        for (int r = 0; r < CDP_TPT; ++r) {
+            const int e = (tid - 64) + CDP_WORKERS * r;
+            if (e < 2 * CDP_TILE) {
+                const int which = e / CDP_TILE, f = e % CDP_TILE;
+                (which == 0 ? Dt : St)[b * CDP_TILE + f] = treg[r];
+            }
+        }
+    };
+
+    for (int64_t k = tid; k < nc; k += CDP_THREADS) {
+        zs[k] = 0.0;
+        ds[k] = 0.0;
+    }
+    if (wave > 0) {
+        load_tiles(0, C - 1);
+        store_tiles(0);
+    }
+    // wave 0: the next chunk's per-coordinate constants, one coordinate per lane
+    double nIa = 0.0, nA = 0.0, nS = 0.0, nW = 0.0;
+    auto load_consts = [&](int c) {
+        const int64_t k = (int64_t)c * CDH_K + lane;
+        const bool on = k < nc;
+        nIa = load_or(c_inva, k, on, 0.0);
+        nA = load_or(c_A, k, on, 0.0);
+        nS = load_or(c_S, k, on, 0.0);
+        nW = load_or(c_wtc, k, on, 0.0);
+    };
+    if (wave == 0) load_consts(0);
+    if (tid == 0) {
+        s_nnz[0] = 0;
+        s_nnz[1] = 0;
+        s_stop = 0;
+    }
+    lds_barrier();
+
+    int sweeps = 0;
+    double maxmu = 0.0;   // wave 0
+    long long tph[3] = {0, 0, 0};   // thread 0: step application, chain, barrier wait
+    long long tlast = wall_clock64();
+    int64_t g = 0;
+    bool done = false;
+    for (int sweep = 0; sweep < max_sweeps && !done; ++sweep) {
+        for (int i = 0; i < C; ++i, ++g) {
+            const int b = (int)(g & 1), pb = 1 - b;   // this interval's buffers / previous steps
+            const int cp = (i + C - 1) % C;            // previous chunk
+            const int64_t k0 = (int64_t)i * CDH_K, kp0 = (int64_t)cp * CDH_K;
+            const int K = klen(i);
+            const bool have_prev = g > 0 && C > 1;
+            if (wave == 0) {
+                if (i == 0) maxmu = 0.0;
+                const bool on = lane < K;
+                const int kl = on ? (int)k0 + lane : (int)k0;
+                double z = on ? zs[kl] : 0.0;
+                // steps of the previous chunk onto the rows of this one
+                if (have_prev && s_nnz[pb] > 0) {
+                    const double* st = St + b * CDP_TILE;
+                    const double* pm = mud + pb * CDH_K;
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+                    for (int t = 0; t < CDH_K; t += 4) {
+                        a0 += st[t * CDH_K + lane] * pm[t];
+                        a1 += st[(t + 1) * CDH_K + lane] * pm[t + 1];
+                        a2 += st[(t + 2) * CDH_K + lane] * pm[t + 2];
+                        a3 += st[(t + 3) * CDH_K + lane] * pm[t + 3];
+                    }
+                    z += on ? (a0 + a1) + (a2 + a3) : 0.0;
+                }
+                if (tid == 0) { const long long now = wall_clock64(); tph[0] += now - tlast; tlast = now; }
+                // chain constants of this chunk, broadcast from LDS inside the chain
+                const double ia = on ? nIa : 0.0;
+                const double d0 = on ? ds[kl] : 0.0;
+                const double xl = on ? nA + d0 : 0.0;
+                const double pv = on ? xl - (nS - nW) * ia : 0.0;
+                load_consts((i + 1) % C);
+                cst[lane] = pv;
+                cst[CDH_K + lane] = ia;
+                cst[2 * CDH_K + lane] = xl;
+                const double* dt = Dt + b * CDP_TILE;
+                double mul = 0.0;
+                const int K4 = (K + 3) & ~3;
+                // group of four steps; the next group's LDS data is read one group ahead
+                double hN[4], pN[4], iN[4], xN[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    hN[u] = dt[u * CDH_K + lane];
+                    pN[u] = cst[u];
+                    iN[u] = cst[CDH_K + u];
+                    xN[u] = cst[2 * CDH_K + u];
+                }
+                for (int tt = 0; tt < K4; tt += 4) {
+                    double hC[4], pC[4], iC[4], xC[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        hC[u] = hN[u];
+                        pC[u] = pN[u];
+                        iC[u] = iN[u];
+                        xC[u] = xN[u];
+                    }
+                    const int tn = tt + 4 < CDH_K ? tt + 4 : CDH_K - 4;   // in range; unused past K4
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        hN[u] = dt[(tn + u) * CDH_K + lane];
+                        pN[u] = cst[tn + u];
+                        iN[u] = cst[CDH_K + tn + u];
+                        xN[u] = cst[2 * CDH_K + tn + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int t = tt + u;
+                        const double zt = readlane_d(z, t);
+                        const double y = pC[u] - zt * iC[u];
+                        const double mu = cd_soft(y, lam * iC[u]) - xC[u];
+                        z += mu * hC[u];
+                        if (lane == t) mul = mu;
+                        maxmu = fmax(maxmu, fabs(mu));
+                    }
+                }
+                if (on) {
+                    zs[kl] = z;
+                    ds[kl] = d0 + mul;
+                }
+                mud[b * CDH_K + lane] = mul;   // lanes >= K hold 0
+                const bool nzs = on && mul != 0.0;
+                const unsigned long long bits = __ballot(nzs);
+                const int nnz = __popcll(bits);
+                double* om = nzm + b * CDH_K;
+                int* ol = nzl + b * CDH_K;
+                if (nzs) {
+                    const int pos = __popcll(bits & ((1ull << lane) - 1ull));
+                    ol[pos] = lane;
+                    om[pos] = mul;
+                }
+                const int npad = (nnz + CDH_PAD - 1) / CDH_PAD * CDH_PAD;
+                if (lane >= nnz && lane < npad) {
+                    ol[lane] = 0;
+                    om[lane] = 0.0;
+                }
+                if (lane == 0) s_nnz[b] = nnz;
+                if (i == C - 1) {
+                    // stopping rule of the sweep: max|mu| <= tol * max|Delta|
+                    double dm = 0.0;
+                    for (int64_t k = lane; k < nc; k += 64) dm = fmax(dm, fabs(ds[k]));
+                    dm = wave_max(dm);
+                    if (lane == 0) {
+                        s_stop = (maxmu <= tol * dm) ? 1 : 0;
+                        stats[1] = maxmu;
+                        stats[2] = dm;
+                    }
+                }
+                if (tid == 0) { const long long now = wall_clock64(); tph[1] += now - tlast; tlast = now; }
+            } else {
+                // steps of the previous chunk onto every row outside chunks cp and i
+                if (have_prev && C > 2) {
+                    const int np = (s_nnz[pb] + CDH_PAD - 1) / CDH_PAD * CDH_PAD;
+                    const double* pm = nzm + pb * CDH_K;
+                    const int* pl = nzl + pb * CDH_K;
+                    const double* hcol = HT + kp0 * nc;
+                    double acc[ROWS];
+                    bool rv[ROWS];
+                    int rk[ROWS];
+                    // worker w takes the w-th row outside the (64-aligned) chunks cp and i
+                    const int64_t ea = kp0 < k0 ? kp0 : k0, eb = kp0 < k0 ? k0 : kp0;
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) {
+                        int64_t k = (tid - 64) + (int64_t)CDP_WORKERS * r;
+                        if (k >= ea) k += CDH_K;
+                        if (k >= eb) k += CDH_K;
+                        rv[r] = k < nc;
+                        rk[r] = rv[r] ? (int)k : 0;
+                        acc[r] = 0.0;
+                    }
+                    // the column index is the same in every lane: a scalar base address
+                    // plus a 32-bit row offset per load
+                    constexpr int BATCH = 16 / ROWS;
+#pragma unroll 1
+                    for (int q0 = 0; q0 < np; q0 += BATCH) {
+                        double hv[ROWS][BATCH];
+#pragma unroll
+                        for (int q = 0; q < BATCH; ++q) {
+                            const int t = __builtin_amdgcn_readfirstlane(pl[q0 + q]);
+                            const double* colp = hcol + (int64_t)t * nc;
+#pragma unroll
+                            for (int r = 0; r < ROWS; ++r) hv[r][q] = colp[rk[r]];
+                        }
+#pragma unroll
+                        for (int q = 0; q < BATCH; ++q) {
+                            const double m = pm[q0 + q];
+#pragma unroll
+                            for (int r = 0; r < ROWS; ++r) acc[r] += hv[r][q] * m;
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r)
+                        if (rv[r]) zs[rk[r]] += acc[r];
+                }
+                // next interval's tiles (chunk i+1 and its predecessor i); their latency
+                // hides behind the chain
+                load_tiles((i + 1) % C, i);
+                store_tiles(pb);
+            }
+            lds_barrier();
+            if (tid == 0) { const long long now = wall_clock64(); tph[2] += now - tlast; tlast = now; }
+            if (i == C - 1) {
+                ++sweeps;
+                if (s_stop) {
+                    done = true;
+                    break;
+                }
+            }
+        }
+    }
+    for (int64_t k = tid; k < nc; k += CDP_THREADS) delta[k] = ds[k];
     if (tid == 0) {
         stats[0] = (double)sweeps;
         for (int i = 0; i < 3; ++i) stats[3 + i] = (double)tph[i];
@@ -528,17 +864,24 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
     prof_end(KK_CD, s, 0.0, 0.0);
 }
 
+int64_t cd_hessian_limit() { return (int64_t)CDH_RMAX * CDH_THREADS; }
+
+size_t cd_pipe_lds_bytes(int64_t ncoord) {
+    return sizeof(double) * ((size_t)2 * ncoord + 4 * CDP_TILE + 3 * CDH_K + 4 * CDH_K) +
+           sizeof(int) * 2 * CDH_K;
+}
+
 size_t cd_hessian_lds_bytes(int64_t ncoord) {
     return sizeof(double) * ((size_t)2 * ncoord + CDH_K * CDH_K + CDH_K) + sizeof(int) * CDH_K;
 }
 
-void launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
-                       const double* WJJ, const double* c_S, const double* c_A,
-                       const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
-                       double tol, double* HT, double* delta, double* stats, hipStream_t s) {
-    if (ncoord <= 0) return;
+int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
+                          const double* WJJ, const double* c_S, const double* c_A,
+                          const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
+                          double tol, double* HT, double* delta, double* stats, hipStream_t s) {
+    if (ncoord <= 0) return -1;
     const size_t lds = cd_hessian_lds_bytes(ncoord);
-    if (lds > CD_MAX_LDS_BYTES)
+    if (ncoord > cd_hessian_limit() || lds > CD_MAX_LDS_BYTES)
         throw SicError(SIC_EINTERNAL, "coordinate count too large for the explicit-Hessian sweep");
     prof_begin(KK_CD_HESS, s);
     hipLaunchKernelGGL(k_cd_hess, dim3((unsigned)((ncoord + 255) / 256), (unsigned)ncoord),
@@ -546,18 +889,47 @@ void launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t
     SIC_CHECK_LAUNCH();
     // H written once; 4 gathers of W per entry (from the L2-resident W on J')
     prof_end(KK_CD_HESS, s, 8.0 * (double)ncoord * ncoord, 3.0 * (double)ncoord * ncoord);
-    static bool attr_set = false;
-    if (!attr_set) {
-        SIC_HIP(hipFuncSetAttribute((const void*)k_cd_dense,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)CD_MAX_LDS_BYTES));
-        attr_set = true;
+    const int rows = (int)((ncoord + CDH_THREADS - 1) / CDH_THREADS);
+    auto launch = [&](auto kern) {
+        static bool attr_set[CDH_RMAX + 1] = {};
+        if (!attr_set[rows]) {
+            SIC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)CD_MAX_LDS_BYTES));
+            attr_set[rows] = true;
+        }
+        prof_begin(KK_CD, s);
+        hipLaunchKernelGGL(kern, dim3(1), dim3(CDH_THREADS), lds, s, ncoord, HT, c_S, c_A, c_inva,
+                           c_wtc, lam, max_sweeps, tol, delta, stats);
+        SIC_CHECK_LAUNCH();
+    };
+    const size_t lds_pipe = cd_pipe_lds_bytes(ncoord);
+    // rows the workers cover: all but two chunks (all but one or none for C <= 2)
+    const int prow = (int)((std::max<int64_t>(ncoord - 2 * CDH_K, 1) + CDP_WORKERS - 1) / CDP_WORKERS);
+    auto launch_pipe = [&](auto kern) {
+        static bool attr = false;
+        if (!attr) {
+            SIC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)CD_MAX_LDS_BYTES));
+            attr = true;
+        }
+        prof_begin(KK_CD, s);
+        hipLaunchKernelGGL(kern, dim3(1), dim3(CDP_THREADS), lds_pipe, s, ncoord, HT, c_S, c_A,
+                           c_inva, c_wtc, lam, max_sweeps, tol, delta, stats);
+        SIC_CHECK_LAUNCH();
+    };
+    if (lds_pipe <= CD_MAX_LDS_BYTES && prow <= 2) {
+        if (prow == 1) launch_pipe(k_cd_pipe<1>); else launch_pipe(k_cd_pipe<2>);
+    } else {
+        switch (rows) {
+            case 1: launch(k_cd_dense<1>); break;
+            case 2: launch(k_cd_dense<2>); break;
+            case 3: launch(k_cd_dense<3>); break;
+            default: launch(k_cd_dense<4>); break;
+        }
     }
-    prof_begin(KK_CD, s);
-    hipLaunchKernelGGL(k_cd_dense, dim3(1), dim3(CDH_THREADS), lds, s, ncoord, HT, c_S, c_A, c_inva,
-                       c_wtc, lam, max_sweeps, tol, delta, stats);
-    SIC_CHECK_LAUNCH();
-    prof_end(KK_CD, s, 0.0, 0.0);
+    // one sweep streams every column of H once (8 ncoord^2 bytes, 2 ncoord^2 flops); the
+    // caller scales the record by the sweep count once it is known
+    return prof_end(KK_CD, s, 8.0 * (double)ncoord * ncoord, 2.0 * (double)ncoord * ncoord);
 }
 
 }  // namespace sic

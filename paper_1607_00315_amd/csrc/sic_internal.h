@@ -155,11 +155,14 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
                double* ug, unsigned char* markg, double* stats, hipStream_t s);
 // Explicit coordinate Hessian form: builds H^T (ncoord^2 doubles at HT), then
 // runs the sweeps; requires cd_hessian_lds_bytes(ncoord) <= CD_MAX_LDS_BYTES.
+int64_t cd_hessian_limit();   // largest coordinate count the explicit-Hessian sweep takes
 size_t cd_hessian_lds_bytes(int64_t ncoord);
-void launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
-                       const double* WJJ, const double* c_S, const double* c_A,
-                       const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
-                       double tol, double* HT, double* delta, double* stats, hipStream_t s);
+// Returns the profiler record of the sweep kernel (bytes and flops of one sweep),
+// to be scaled by the sweep count, or -1.
+int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
+                          const double* WJJ, const double* c_S, const double* c_A,
+                          const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
+                          double tol, double* HT, double* delta, double* stats, hipStream_t s);
 
 // ---------------------------------------------------------------- k_dense.hip
 // dinv (batch 1 only, may be null) receives the inverses of the factor's

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "profiler.h"
 #include "solver.h"
 
 namespace sic {
@@ -331,15 +332,18 @@ void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count) 
 // Step (d) on the coordinates prepared in the block work area: the explicit
 // coordinate Hessian form when the block has at most cd_hessian_max
 // coordinates (and its z and Delta fit in LDS), else the U = Delta W form.
-static void run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max_sweeps, double tol) {
+// Returns the profiler record to scale by the sweep count (or -1).
+static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max_sweeps,
+                      double tol) {
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
     W.cdstats.reserve(8);
-    if (nc > 0 && nc <= C.opt.cd_hessian_max && cd_hessian_lds_bytes(nc) <= CD_MAX_LDS_BYTES) {
+    if (nc > 0 && nc <= C.opt.cd_hessian_max && nc <= cd_hessian_limit() &&
+        cd_hessian_lds_bytes(nc) <= CD_MAX_LDS_BYTES) {
         W.HT.reserve((size_t)nc * nc);
-        launch_cd_hessian(nc, jp, W.c_p.p, W.c_ci.p, W.WJJ.p, W.c_S.p, W.c_A.p, W.c_inva.p,
-                          W.c_wtc.p, lam, max_sweeps, tol, W.HT.p, W.delta.p, W.cdstats.p, s);
-        return;
+        return launch_cd_hessian(nc, jp, W.c_p.p, W.c_ci.p, W.WJJ.p, W.c_S.p, W.c_A.p,
+                                 W.c_inva.p, W.c_wtc.p, lam, max_sweeps, tol, W.HT.p, W.delta.p,
+                                 W.cdstats.p, s);
     }
     W.U.reserve((size_t)jp * b);
     W.ug.reserve(jp);
@@ -347,6 +351,7 @@ static void run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max_sw
     SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
     launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, lam,
               max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
+    return -1;
 }
 
 BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, bool record,
@@ -483,13 +488,14 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     // (d) coordinate descent
     launch_cd_prep(W.cptr.p, b, nc, W.c_p.p, W.WJJ.p, jp, W.c_ci.p, W.c_a.p, W.c_inva.p, W.c_wtc.p,
                    W.c_wtt.p, W.delta.p, s);
-    run_cd(C, jp, b, nc, P.lam, C.opt.cd_max_sweeps, C.opt.cd_tol);
+    const int64_t cd_rec = run_cd(C, jp, b, nc, P.lam, C.opt.cd_max_sweeps, C.opt.cd_tol);
     double cds[7];
     SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     // (e) line search
     LineSearch ls = line_search(C, P.lam, jp, b, nN, nc);
     R.cd_sweeps = (int)cds[0];
     R.cd_last_maxmu = cds[1];
+    prof_scale(cd_rec, cds[0]);
     if (C.opt.flags & SIC_FLAG_VERBOSE)
         fprintf(stderr,
                 "[sic] block j0=%lld %s E=%lld coords=%lld |N|=%lld |NC|=%lld cg=%d/%d cd=%d "
@@ -864,11 +870,12 @@ int step_cd_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cp
     hipStream_t s = C.stream;
     load_coords(C, jp, b, wjj, cptr, cp, S, A);
     const int64_t nc = cptr[b];
-    run_cd(C, jp, b, nc, lambda, max_sweeps, tol);
+    const int64_t cd_rec = run_cd(C, jp, b, nc, lambda, max_sweeps, tol);
     if (nc) SIC_HIP(hipMemcpyAsync(delta_out, W.delta.p, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
     double st[7];
     SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     sync(C);
+    prof_scale(cd_rec, st[0]);
     if (stats_out) std::copy(st, st + 7, stats_out);
     return SIC_OK;
 }

@@ -567,8 +567,7 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
     double* ds = zs + nc;                     // [nc]
     double* Dt = ds + nc;                     // [2][64 x 64] H[chunk i][chunk i], [t][k]
     double* St = Dt + 2 * CDP_TILE;           // [2][64 x 64] H[chunk i][chunk i-1], [t][k]
-    double* cst = St + 2 * CDP_TILE;          // [3][64] chain constants p, 1/a, x
-    double* mud = cst + 3 * CDH_K;            // [2][64] steps of the chunk, dense (0 when none)
+    double* mud = St + 2 * CDP_TILE;          // [2][64] steps of the chunk, dense (0 when none)
     double* nzm = mud + 2 * CDH_K;            // [2][64] nonzero steps (zero padded)
     int* nzl = (int*)(nzm + 2 * CDH_K);       // [2][64] their chunk positions
     __shared__ int s_nnz[2];
@@ -626,7 +625,11 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
         nS = load_or(c_S, k, on, 0.0);
         nW = load_or(c_wtc, k, on, 0.0);
     };
-    if (wave == 0) load_consts(0);
+    if (wave == 0) {
+        load_consts(0);
+        // the chain is the critical path: let its wave win issue arbitration on its SIMD
+        __builtin_amdgcn_s_setprio(3);
+    }
     if (tid == 0) {
         s_nnz[0] = 0;
         s_nnz[1] = 0;
@@ -656,15 +659,19 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                 if (have_prev && s_nnz[pb] > 0) {
                     const double* st = St + b * CDP_TILE;
                     const double* pm = mud + pb * CDH_K;
-                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 4
-                    for (int t = 0; t < CDH_K; t += 4) {
-                        a0 += st[t * CDH_K + lane] * pm[t];
-                        a1 += st[(t + 1) * CDH_K + lane] * pm[t + 1];
-                        a2 += st[(t + 2) * CDH_K + lane] * pm[t + 2];
-                        a3 += st[(t + 3) * CDH_K + lane] * pm[t + 3];
+                    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+                    for (int t = 0; t < CDH_K; t += 8) {
+                        double sv[8], mv[8];   // all eight reads in flight before the fmas
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            sv[u] = st[(t + u) * CDH_K + lane];
+                            mv[u] = pm[t + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) a[u & 3] += sv[u] * mv[u];
                     }
-                    z += on ? (a0 + a1) + (a2 + a3) : 0.0;
+                    z += on ? (a[0] + a[1]) + (a[2] + a[3]) : 0.0;
                 }
                 if (tid == 0) { const long long now = wall_clock64(); tph[0] += now - tlast; tlast = now; }
                 // chain constants of this chunk, broadcast from LDS inside the chain
@@ -673,44 +680,33 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                 const double xl = on ? nA + d0 : 0.0;
                 const double pv = on ? xl - (nS - nW) * ia : 0.0;
                 load_consts((i + 1) % C);
-                cst[lane] = pv;
-                cst[CDH_K + lane] = ia;
-                cst[2 * CDH_K + lane] = xl;
                 const double* dt = Dt + b * CDP_TILE;
                 double mul = 0.0;
                 const int K4 = (K + 3) & ~3;
-                // group of four steps; the next group's LDS data is read one group ahead
-                double hN[4], pN[4], iN[4], xN[4];
+                // The chain, one coordinate per step in the stored order. With
+                // q = p - x, a = q - lam/a - z/a and b = q + lam/a - z/a, the step
+                // mu = soft(p - z/a, lam/a) - x is the median of a, -x and b
+                // (a <= b), three dependent operations after the broadcast of z_t.
+                const double qlo = pv - xl - lam * ia, qhi = pv - xl + lam * ia, nx = -xl;
+                double hN[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    hN[u] = dt[u * CDH_K + lane];
-                    pN[u] = cst[u];
-                    iN[u] = cst[CDH_K + u];
-                    xN[u] = cst[2 * CDH_K + u];
-                }
+                for (int u = 0; u < 4; ++u) hN[u] = dt[u * CDH_K + lane];
                 for (int tt = 0; tt < K4; tt += 4) {
-                    double hC[4], pC[4], iC[4], xC[4];
+                    double hC[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        hC[u] = hN[u];
-                        pC[u] = pN[u];
-                        iC[u] = iN[u];
-                        xC[u] = xN[u];
-                    }
+                    for (int u = 0; u < 4; ++u) hC[u] = hN[u];
                     const int tn = tt + 4 < CDH_K ? tt + 4 : CDH_K - 4;   // in range; unused past K4
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        hN[u] = dt[(tn + u) * CDH_K + lane];
-                        pN[u] = cst[tn + u];
-                        iN[u] = cst[CDH_K + tn + u];
-                        xN[u] = cst[2 * CDH_K + tn + u];
-                    }
+                    for (int u = 0; u < 4; ++u) hN[u] = dt[(tn + u) * CDH_K + lane];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int t = tt + u;
+                        const double iat = readlane_d(ia, t);
+                        const double lo = readlane_d(qlo, t), hi = readlane_d(qhi, t);
+                        const double nxt = readlane_d(nx, t);
                         const double zt = readlane_d(z, t);
-                        const double y = pC[u] - zt * iC[u];
-                        const double mu = cd_soft(y, lam * iC[u]) - xC[u];
+                        const double av = lo - zt * iat, bv = hi - zt * iat;
+                        const double mu = fmax(av, fmin(bv, nxt));
                         z += mu * hC[u];
                         if (lane == t) mul = mu;
                         maxmu = fmax(maxmu, fabs(mu));
@@ -867,7 +863,7 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
 int64_t cd_hessian_limit() { return (int64_t)CDH_RMAX * CDH_THREADS; }
 
 size_t cd_pipe_lds_bytes(int64_t ncoord) {
-    return sizeof(double) * ((size_t)2 * ncoord + 4 * CDP_TILE + 3 * CDH_K + 4 * CDH_K) +
+    return sizeof(double) * ((size_t)2 * ncoord + 4 * CDP_TILE + 4 * CDH_K) +
            sizeof(int) * 2 * CDH_K;
 }
 

@@ -302,58 +302,70 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
 constexpr int TS_COLS = 16;
 constexpr int TS_T = CB;   // the factor's diagonal-block size (dinv layout)
 constexpr int TS_THREADS = TS_COLS * TS_T;
+static_assert(TS_THREADS == TS_T * TS_T, "one diagonal-block entry per thread");
 
 __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __restrict__ L, int nb,
                                                              int ldl, const double* __restrict__ dinv,
                                                              double* __restrict__ B, int ncols,
                                                              int ldb, int trans) {
+    constexpr int LPT = (TS_T * CH_NB + TS_THREADS - 1) / TS_THREADS;   // staged L per thread
     __shared__ double Xs[CH_NB][TS_COLS];
+    __shared__ double Ls[TS_T * CH_NB];   // the L entries of the current step (see below)
     __shared__ double As[TS_T][TS_COLS];
+    __shared__ double Ds[TS_T * TS_T];    // inverse of the step's diagonal block
     const int tid = threadIdx.x;
     const int r = tid / TS_COLS, c = tid % TS_COLS;
     const int col = blockIdx.x * TS_COLS + c;
     const bool con = col < ncols;
     const int nt = (nb + TS_T - 1) / TS_T;
     for (int k = r; k < nt * TS_T; k += TS_T)
-        Xs[k][c] = (con && k < nb) ? B[(int64_t)k * ldb + col] : 0.0;
-    __syncthreads();
+        Xs[k][c] = load_or(B, (int64_t)k * ldb + col, con && k < nb, 0.0);
     for (int step = 0; step < nt; ++step) {
         const int i = trans ? nt - 1 - step : step;
-        const int row = i * TS_T + r;
-        double acc = 0.0;
-        if (row < nb) {
-            double a0 = Xs[row][c], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            if (!trans) {
-                const double* lr = L + (int64_t)row * ldl;
-                const int kend = i * TS_T;
-                int k = 0;
-                for (; k + 4 <= kend; k += 4) {
-                    a0 -= lr[k] * Xs[k][c];
-                    a1 -= lr[k + 1] * Xs[k + 1][c];
-                    a2 -= lr[k + 2] * Xs[k + 2][c];
-                    a3 -= lr[k + 3] * Xs[k + 3][c];
-                }
-                for (; k < kend; ++k) a0 -= lr[k] * Xs[k][c];
-            } else {
-                int k = (i + 1) * TS_T;
-                for (; k + 4 <= nb; k += 4) {
-                    a0 -= L[(int64_t)k * ldl + row] * Xs[k][c];
-                    a1 -= L[(int64_t)(k + 1) * ldl + row] * Xs[k + 1][c];
-                    a2 -= L[(int64_t)(k + 2) * ldl + row] * Xs[k + 2][c];
-                    a3 -= L[(int64_t)(k + 3) * ldl + row] * Xs[k + 3][c];
-                }
-                for (; k < nb; ++k) a0 -= L[(int64_t)k * ldl + row] * Xs[k][c];
-            }
-            acc = (a0 + a1) + (a2 + a3);
+        // stage, with every load in flight at once:
+        //   forward:  Ls[q * 16 + rr] = L[i*16 + rr][q]           for q <  i*16
+        //   backward: Ls[q * 16 + rr] = L[(i+1)*16 + q][i*16 + rr] for q <  nb - (i+1)*16
+        const int kcnt = trans ? nb - (i + 1) * TS_T : i * TS_T;
+        double lreg[LPT];
+#pragma unroll
+        for (int u = 0; u < LPT; ++u) {
+            const int e = tid + TS_THREADS * u;
+            const int q = e / TS_T, rr = e % TS_T;
+            const int row = trans ? (i + 1) * TS_T + q : i * TS_T + rr;
+            const int lc = trans ? i * TS_T + rr : q;
+            const bool ok = q < kcnt && row < nb && lc < nb;
+            lreg[u] = load_or(L, (int64_t)row * ldl + lc, ok, 0.0);
         }
-        As[r][c] = acc;
+        const double dv = dinv[(int64_t)i * TS_T * TS_T + tid];   // TS_THREADS == TS_T * TS_T
+#pragma unroll
+        for (int u = 0; u < LPT; ++u) {
+            const int e = tid + TS_THREADS * u;
+            if (e < TS_T * CH_NB) Ls[e] = lreg[u];
+        }
+        Ds[tid] = dv;
         __syncthreads();
-        const double* di = dinv + (int64_t)i * TS_T * TS_T;
+        const int row = i * TS_T + r;
+        const int k0 = trans ? (i + 1) * TS_T : 0;
+        double a[4] = {Xs[row][c], 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 8 <= kcnt; q += 8) {
+            double lv[8], xv[8];   // eight LDS reads in flight before the fmas
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                lv[u] = Ls[(q + u) * TS_T + r];
+                xv[u] = Xs[k0 + q + u][c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u & 3] -= lv[u] * xv[u];
+        }
+        for (; q < kcnt; ++q) a[0] -= Ls[q * TS_T + r] * Xs[k0 + q][c];
+        As[r][c] = row < nb ? (a[0] + a[1]) + (a[2] + a[3]) : 0.0;
+        __syncthreads();
         double x = 0.0;
         if (!trans) {
-            for (int q = 0; q <= r; ++q) x += di[r * TS_T + q] * As[q][c];
+            for (int qq = 0; qq <= r; ++qq) x += Ds[r * TS_T + qq] * As[qq][c];
         } else {
-            for (int q = r; q < TS_T; ++q) x += di[q * TS_T + r] * As[q][c];
+            for (int qq = r; qq < TS_T; ++qq) x += Ds[qq * TS_T + r] * As[qq][c];
         }
         if (row < nb) Xs[row][c] = x;
         __syncthreads();
@@ -362,39 +374,70 @@ __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __res
         for (int k = r; k < nb; k += TS_T) B[(int64_t)k * ldb + col] = Xs[k][c];
 }
 
-// C = alpha * op(A) op(B) + beta * C; op(X) = X or X^T; row-major with leading dims.
-// 16 x 16 output tile per 256-thread workgroup, 16-deep LDS stages.
-__global__ __launch_bounds__(256) void k_gemm_small(int M, int N, int K, double alpha,
-                                                    const double* __restrict__ A, int lda, int ta,
-                                                    const double* __restrict__ B, int ldb, int tb,
-                                                    double beta, double* __restrict__ C, int ldc) {
-    __shared__ double sa[16][17], sb[16][17];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
-    double acc = 0.0;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        {   // sa[ty][tx] = op(A)[blockIdx.y*16 + ty][k0 + tx]
-            const int r = blockIdx.y * 16 + ty, k = k0 + tx;
-            double v = 0.0;
-            if (r < M && k < K) v = ta ? A[(int64_t)k * lda + r] : A[(int64_t)r * lda + k];
-            sa[ty][tx] = v;
+// C = alpha * op(A) op(B) + beta * C on FP64 MFMA (16x16x4): one workgroup of
+// four waves per 32 x 32 tile of C (each wave one 16 x 16 accumulator), K
+// staged through LDS 16 at a time with the next stage's loads in flight
+// during the current stage's products. op(X) = X or X^T; row-major with
+// leading dimensions.
+typedef double gemm_d4 __attribute__((ext_vector_type(4)));
+constexpr int GM_TILE = 32, GM_KC = 16, GM_PAD = 4;
+
+__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double alpha,
+                                                   const double* __restrict__ A, int lda, int ta,
+                                                   const double* __restrict__ B, int ldb, int tb,
+                                                   double beta, double* __restrict__ C, int ldc) {
+    __shared__ double sA[GM_KC][GM_TILE + GM_PAD];   // sA[k][i] = op(A)[i0 + i][k0 + k]
+    __shared__ double sB[GM_KC][GM_TILE + GM_PAD];   // sB[k][j] = op(B)[k0 + k][j0 + j]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int i0 = blockIdx.y * GM_TILE, j0 = blockIdx.x * GM_TILE;
+    const int lr = tid >> 4;          // 0..15 (k within the stage)
+    const int lc = (tid & 15) * 2;    // 0..30 (i or j within the tile)
+    gemm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    double va[2], vb[2];
+    auto load_stage = [&](int k0) {
+        const int k = k0 + lr;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i = i0 + lc + q, j = j0 + lc + q;
+            const int64_t ia = ta ? (int64_t)k * lda + i : (int64_t)i * lda + k;
+            const int64_t ib = tb ? (int64_t)j * ldb + k : (int64_t)k * ldb + j;
+            va[q] = load_or(A, ia, i < M && k < K, 0.0);
+            vb[q] = load_or(B, ib, j < N && k < K, 0.0);
         }
-        {   // sb[ty][tx] = op(B)[k0 + ty][blockIdx.x*16 + tx]
-            const int k = k0 + ty, c = blockIdx.x * 16 + tx;
-            double v = 0.0;
-            if (k < K && c < N) v = tb ? B[(int64_t)c * ldb + k] : B[(int64_t)k * ldb + c];
-            sb[ty][tx] = v;
+    };
+    load_stage(0);
+    for (int k0 = 0; k0 < K; k0 += GM_KC) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            sA[lr][lc + q] = va[q];
+            sB[lr][lc + q] = vb[q];
         }
         __syncthreads();
+        load_stage(k0 + GM_KC);   // beyond K: guarded loads of element 0
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) acc += sa[ty][kk] * sb[kk][tx];
+        for (int kk = 0; kk < GM_KC; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const double av = sA[kr][wr * 16 + (lane & 15)];
+            const double bv = sB[kr][wc * 16 + (lane & 15)];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
         __syncthreads();
     }
-    if (i < M && j < N) {
-        const int64_t o = (int64_t)i * ldc + j;
-        C[o] = alpha * acc + (beta != 0.0 ? beta * C[o] : 0.0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 16 + (lane >> 4) + 4 * v;
+        const int j = j0 + wc * 16 + (lane & 15);
+        if (i < M && j < N) {
+            const int64_t o = (int64_t)i * ldc + j;
+            const double prev = beta != 0.0 ? C[o] : 0.0;
+            C[o] = alpha * acc[v] + beta * prev;
+        }
     }
 }
+
 
 // Copy the leading nb x nb block of a (ld) matrix into a packed nb x nb buffer.
 __global__ void k_copy_block(const double* __restrict__ src, int ld, int nb, double* __restrict__ dst) {
@@ -573,9 +616,9 @@ void launch_gemm_small(int M, int N, int K, double alpha, const double* A, int l
                        const double* B, int ldb, int tb, double beta, double* C, int ldc,
                        hipStream_t s) {
     if (M <= 0 || N <= 0) return;
-    dim3 grid((unsigned)((N + 15) / 16), (unsigned)((M + 15) / 16));
+    dim3 grid((unsigned)((N + GM_TILE - 1) / GM_TILE), (unsigned)((M + GM_TILE - 1) / GM_TILE));
     prof_begin(KK_GEMM, s);
-    hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb,
+    hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb,
                        beta, C, ldc);
     SIC_CHECK_LAUNCH();
     prof_end(KK_GEMM, s, 8.0 * ((double)M * K + (double)K * N + 2.0 * M * N), 2.0 * (double)M * N * K);

@@ -79,6 +79,21 @@ __global__ void k_upd_rows(int pass, int64_t n, int64_t j0, int b,
         }
         ++count;
     };
+    // the dense row over the block columns, 16 loads in flight at a time
+    // (unconditional loads of a clamped index, then a select)
+    auto emit_dense = [&]() {
+        for (int q0 = 0; q0 < b; q0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int q = q0 + u < b ? q0 + u : b - 1;
+                v[u] = arow[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (q0 + u < b && v[u] != 0.0) emit(j0 + q0 + u, v[u]);
+        }
+    };
     if (r >= j0 && r < j1) {
         const int ci = (int)(r - j0);
         const int64_t t0 = cptr[ci], t1 = cptr[ci + 1];
@@ -89,10 +104,7 @@ __global__ void k_upd_rows(int pass, int64_t n, int64_t j0, int b,
             const double v = ANEW[g * b + ci];
             if (v != 0.0) emit(g, v);
         }
-        for (int q = 0; q < b; ++q) {
-            const double v = arow[q];
-            if (v != 0.0) emit(j0 + q, v);
-        }
+        emit_dense();
         for (; t < t1; ++t) {
             const int64_t g = Jp[c_p[t]];
             if (g < j1) continue;
@@ -112,10 +124,7 @@ __global__ void k_upd_rows(int pass, int64_t n, int64_t j0, int b,
             const int64_t lo = lower_bound_col(col, e0, e1, j0);
             const int64_t hi = lower_bound_col(col, lo, e1, j1);
             for (int64_t e = e0; e < lo; ++e) emit(col[e], val[e]);
-            for (int q = 0; q < b; ++q) {
-                const double v = arow[q];
-                if (v != 0.0) emit(j0 + q, v);
-            }
+            emit_dense();
             for (int64_t e = hi; e < e1; ++e) emit(col[e], val[e]);
         }
     }

@@ -68,11 +68,13 @@ def support_keys(rowptr, col):
 def cpu_baseline(name, X, lam, golden, budget_s):
     """The oracle as it stands, timed on this host on a bounded sample.
 
-    Sample: the oracle's first proximal-Newton iterations on the same
-    workload, run until ``budget_s`` seconds have passed (at least one).
-    Its time to the 1e-6 gap is extrapolated from the oracle's recorded
-    history (the same iterations on the machine that wrote the stored
-    expected values), scaled by the measured/recorded time of the sample.
+    Sample: the oracle on the same workload up to the first iteration
+    boundary past ``budget_s`` seconds (with the default, its set-up and its
+    first proximal-Newton iteration: ~15-20 s of float64 work on a 16-core
+    host). Its time to the 1e-6 gap is
+    extrapolated from the oracle's recorded history (the same iterations on
+    the machine that wrote the stored expected values), scaled by the
+    measured/recorded time of the sample.
     """
     from oracle import core, quic_plain
     try:
@@ -109,7 +111,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid_n10000_m5000")
-    ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-sample-seconds", type=float, default=5.0,
+                    help="oracle sample: up to the first iteration boundary past this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--cd-max-sweeps", type=int, default=0, help="0: library default")

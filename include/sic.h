@@ -96,6 +96,9 @@ typedef struct {
     int cd_hessian_max;    /* blocks with at most this many coordinates run CD on an explicit
                               coordinate Hessian (ncoord^2 doubles of scratch); 0 = default
                               4096, < 0 = never */
+    int pcd_min_coords;    /* blocks with at least this many coordinates take the Newton
+                              direction by PCD-CG (Section 6.1.1) instead of the sequential
+                              coordinate chain; 0 = default 4097, < 0 = never */
     int ls_max_trials;     /* line-search trials alpha = 2^-i, i < ls_max_trials, default 31 */
     int max_cycles;        /* multilevel cycles, default 100 */
     void* stream;          /* hipStream_t to run on, or NULL for the context's own stream */

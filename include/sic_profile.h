@@ -22,8 +22,9 @@ extern "C" {
  *   3 cg_update    CG vector update              8 upd_rows     CSR rebuild
  *   4 screen_fine  free-set screening            9 cd_hess      coordinate Hessian
  *                                                               (explicit-Hessian CD)
- *                                               10 trsm         triangular solves */
-#define SIC_KERNEL_CLASSES 11
+ *                                               10 trsm         triangular solves
+ *                                               11 pcd          PCD-CG Newton direction */
+#define SIC_KERNEL_CLASSES 12
 
 void sic_profile_enable(int on);      /* on != 0 starts timing, 0 stops it */
 void sic_profile_reset(void);         /* zero every counter */

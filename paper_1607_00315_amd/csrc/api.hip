@@ -49,6 +49,7 @@ void opts_from(sic::Context& C, const sic_options& o) {
     t.cd_tol = o.cd_tol > 0 ? o.cd_tol : 1e-4;
     t.cd_max_sweeps = o.cd_max_sweeps > 0 ? o.cd_max_sweeps : 20;
     t.cd_hessian_max = o.cd_hessian_max == 0 ? 4096 : (o.cd_hessian_max < 0 ? 0 : o.cd_hessian_max);
+    t.pcd_min_coords = o.pcd_min_coords == 0 ? 4097 : (o.pcd_min_coords < 0 ? 0 : o.pcd_min_coords);
     t.ls_max_trials = o.ls_max_trials > 0 ? o.ls_max_trials : 31;
     t.max_cycles = o.max_cycles > 0 ? o.max_cycles : 100;
     t.flags = o.flags;
@@ -56,6 +57,7 @@ void opts_from(sic::Context& C, const sic_options& o) {
     C.trace = o.trace;
     C.trace_cap = o.trace ? o.trace_cap : 0;
     C.budget = o.hbm_budget;
+    C.acct->budget = o.hbm_budget;
 }
 
 void check_block(int b) {
@@ -70,6 +72,40 @@ struct StepBufs {
 };
 
 }  // namespace
+
+namespace sic {
+
+void context_init(Context& C, const sic_options& o) {
+    check_block(o.block > 0 ? o.block : 256);
+    C.device = o.device;
+    SIC_HIP(hipSetDevice(o.device));
+    int lds = 0;
+    SIC_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, o.device));
+    CD_MAX_LDS_BYTES = lds > 4096 ? (size_t)lds - 2048 : 0;
+    if (o.stream) {
+        C.stream = (hipStream_t)o.stream;
+        C.own_stream = false;
+    } else {
+        SIC_HIP(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
+        C.own_stream = true;
+    }
+    SIC_HIP(hipHostMalloc((void**)&C.h_i64, 64 * sizeof(int64_t), hipHostMallocDefault));
+    SIC_HIP(hipHostMalloc((void**)&C.h_f64, 64 * sizeof(double), hipHostMallocDefault));
+    opts_from(C, o);
+}
+
+void context_release(Context& C) {
+    (void)hipSetDevice(C.device);
+    if (C.stream) (void)hipStreamSynchronize(C.stream);
+    if (C.own_stream && C.stream) (void)hipStreamDestroy(C.stream);
+    if (C.h_i64) (void)hipHostFree(C.h_i64);
+    if (C.h_f64) (void)hipHostFree(C.h_f64);
+    C.stream = nullptr;
+    C.h_i64 = nullptr;
+    C.h_f64 = nullptr;
+}
+
+}  // namespace sic
 
 namespace sic {
 // implemented in solver.hip through these two helpers
@@ -90,6 +126,7 @@ void sic_options_default(sic_options* o) {
     o->cd_tol = 1e-4;
     o->cd_max_sweeps = 20;
     o->cd_hessian_max = 4096;
+    o->pcd_min_coords = 4097;
     o->ls_max_trials = 31;
     o->max_cycles = 100;
 }
@@ -119,25 +156,8 @@ int sic_create(sic_ctx** out, const sic_options* opt) {
         sic_options o;
         sic_options_default(&o);
         if (opt) o = *opt;
-        check_block(o.block > 0 ? o.block : 256);
         auto ctx = std::make_unique<sic_ctx>();
-        sic::Context& C = ctx->c;
-        C.device = o.device;
-        SIC_HIP(hipSetDevice(o.device));
-        int lds = 0;
-        SIC_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, o.device));
-        sic::CD_MAX_LDS_BYTES = lds > 4096 ? (size_t)lds - 2048 : 0;
-        if (o.stream) {
-            C.stream = (hipStream_t)o.stream;
-            C.own_stream = false;
-        } else {
-            SIC_HIP(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
-            C.own_stream = true;
-        }
-        SIC_HIP(hipHostMalloc((void**)&C.h_i64, 64 * sizeof(int64_t), hipHostMallocDefault));
-        SIC_HIP(hipHostMalloc((void**)&C.h_f64, 64 * sizeof(double), hipHostMallocDefault));
-        opts_from(C, o);
-        sic::g_dev_budget = C.budget;
+        sic::context_init(ctx->c, o);
         *out = ctx.release();
         return SIC_OK;
     });
@@ -145,12 +165,7 @@ int sic_create(sic_ctx** out, const sic_options* opt) {
 
 void sic_destroy(sic_ctx* ctx) {
     if (!ctx) return;
-    sic::Context& C = ctx->c;
-    (void)hipSetDevice(C.device);
-    if (C.stream) (void)hipStreamSynchronize(C.stream);
-    if (C.own_stream && C.stream) (void)hipStreamDestroy(C.stream);
-    if (C.h_i64) (void)hipHostFree(C.h_i64);
-    if (C.h_f64) (void)hipHostFree(C.h_f64);
+    sic::context_release(ctx->c);
     delete ctx;
 }
 
@@ -173,8 +188,8 @@ int sic_solve(sic_ctx* ctx, const double* X, int64_t n, int64_t m, double lambda
     }
     return guard([&]() {
         sic::Context& C = ctx->c;
+        sic::AccountScope scope(C.acct);
         SIC_HIP(hipSetDevice(C.device));
-        sic::g_dev_budget = C.budget;
         sic::Problem P;
         sic::problem_init(C, P, X, SIC_X_F64, n, m, lambda);
         const int st = sic::solve_problem(C, P, tol, info);
@@ -190,44 +205,20 @@ int sic_solve_batch(sic_ctx* ctx, int count, const sic_problem* probs, sic_csr* 
     int slot = 0;
     for (int k = 0; k < count; ++k) {
         const sic_problem& q = probs[k];
-        const int nl = q.n_lambda > 0 ? q.n_lambda : 1;
+        const int nl = sic::request_results(q);
+        sic_info* inf = info ? info + slot : nullptr;
+        if (inf) std::memset(inf, 0, sizeof(sic_info) * nl);
+        for (int l = 0; l < nl; ++l) std::memset(&A_out[slot + l], 0, sizeof(sic_csr));
         int st = guard([&]() {
-            if (!q.X || q.n < 1 || q.m < 1 || !(q.tol > 0.0)) throw sic::SicError(SIC_EINVAL, "bad problem");
             sic::Context& C = ctx->c;
+            sic::AccountScope scope(C.acct);
             SIC_HIP(hipSetDevice(C.device));
             sic::Problem P;
-            const double lam0 = q.n_lambda > 0 ? q.lambda_path[0] : q.lambda;
-            if (!(lam0 >= 0.0)) throw sic::SicError(SIC_EINVAL, "negative lambda");
-            sic::problem_init(C, P, q.X, q.x_dtype, q.n, q.m, lam0);
-            if (q.A0) {
-                sic::set_A_host(C, P, q.A0);
-                P.F = NAN;
-            }
-            int worst = SIC_OK;
-            for (int l = 0; l < nl; ++l) {
-                const double lam = q.n_lambda > 0 ? q.lambda_path[l] : q.lambda;
-                if (!(lam >= 0.0) || (lam == 0.0 && q.m <= q.n))
-                    throw sic::SicError(SIC_EINVAL, "bad lambda in path");
-                if (l > 0) {
-                    // warm start: the tracked objective follows the change of lambda
-                    sic_csr tmp;
-                    sic::get_A_host(C, P, &tmp);
-                    double l1 = 0.0;
-                    for (int64_t e = 0; e < tmp.nnz; ++e) l1 += std::fabs(tmp.val[e]);
-                    sic_csr_free(&tmp);
-                    P.F += (lam - P.lam) * l1;
-                    P.lam = lam;
-                }
-                sic_info* inf = info ? &info[slot + l] : nullptr;
-                const int st1 = sic::solve_problem(C, P, q.tol, inf);
-                sic::get_A_host(C, P, &A_out[slot + l]);
-                if (st1 != SIC_OK && worst == SIC_OK) worst = st1;
-            }
-            return worst;
+            return sic::solve_request(C, P, q, A_out + slot, inf);
         });
-        if (st != SIC_OK && info)
+        if (st != SIC_OK && inf)
             for (int l = 0; l < nl; ++l)
-                if (info[slot + l].status == SIC_OK) info[slot + l].status = st;
+                if (inf[l].status == SIC_OK) inf[l].status = st;
         if (st != SIC_OK && first_bad == SIC_OK) first_bad = st;
         slot += nl;
     }
@@ -242,6 +233,7 @@ int sic_prob_create(sic_ctx* ctx, const double* X, int64_t n, int64_t m, double 
     *out = nullptr;
     return guard([&]() {
         sic::Context& C = ctx->c;
+        sic::AccountScope scope(C.acct);
         SIC_HIP(hipSetDevice(C.device));
         auto p = std::make_unique<sic_prob>();
         p->ctx = ctx;
@@ -260,6 +252,7 @@ void sic_prob_destroy(sic_prob* p) {
 int sic_prob_set_A(sic_prob* p, const sic_csr* A, double objective) {
     if (!p || !A) return SIC_EINVAL;
     return guard([&]() {
+        sic::AccountScope scope(p->ctx->c.acct);
         sic::set_A_host(p->ctx->c, p->P, A);
         p->P.F = objective;
         return SIC_OK;
@@ -269,6 +262,7 @@ int sic_prob_set_A(sic_prob* p, const sic_csr* A, double objective) {
 int sic_prob_get_A(sic_prob* p, sic_csr* out) {
     if (!p || !out) return SIC_EINVAL;
     return guard([&]() {
+        sic::AccountScope scope(p->ctx->c.acct);
         sic::get_A_host(p->ctx->c, p->P, out);
         return SIC_OK;
     });
@@ -280,6 +274,7 @@ int sic_step_cov_block(sic_prob* p, int64_t j0, int b, double* out) {
     if (!p || !out || j0 < 0 || b < 1 || j0 + b > p->P.n) return SIC_EINVAL;
     return guard([&]() {
         sic::Context& C = p->ctx->c;
+        sic::AccountScope scope(C.acct);
         C.work.SJ.reserve((size_t)p->P.n * b);
         sic::launch_sj_gemm_f64(p->P.X.p, p->P.n, p->P.m, j0, b, C.work.SJ.p, C.stream);
         SIC_HIP(hipMemcpyAsync(out, C.work.SJ.p, sizeof(double) * p->P.n * b,
@@ -297,6 +292,7 @@ int sic_step_cov_pairs(sic_prob* p, const int32_t* rows, const int32_t* cols, in
     if (count == 0) return SIC_OK;
     return guard([&]() {
         sic::Context& C = p->ctx->c;
+        sic::AccountScope scope(C.acct);
         sic::DevBuf<int32_t> r, c;
         sic::DevBuf<double> o;
         r.reserve(count); c.reserve(count); o.reserve(count);
@@ -316,6 +312,7 @@ int sic_step_inverse_columns(sic_prob* p, const int32_t* cols, int k, double tol
         if (cols[j] < 0 || cols[j] >= p->P.n) return SIC_EINVAL;
     return guard([&]() {
         sic::Context& C = p->ctx->c;
+        sic::AccountScope scope(C.acct);
         const int64_t n = p->P.n;
         sic::DevBuf<int32_t> dc;
         sic::DevBuf<double> W;
@@ -334,6 +331,7 @@ int sic_step_inverse_columns(sic_prob* p, const int32_t* cols, int k, double tol
 int sic_step_set_level(sic_prob* p, const int64_t* keys, int64_t count) {
     if (!p || count < 0 || (count > 0 && !keys)) return SIC_EINVAL;
     return guard([&]() {
+        sic::AccountScope scope(p->ctx->c.acct);
         sic::set_level_keys(p->ctx->c, p->P, keys, count);
         return SIC_OK;
     });
@@ -360,6 +358,7 @@ int sic_step_block(sic_prob* p, int64_t j0, int b, int level, double tol_I, doub
     if (!p || j0 < 0 || b < 1 || b > 256 || j0 + b > p->P.n || level < 0) return SIC_EINVAL;
     return guard([&]() {
         sic::Context& C = p->ctx->c;
+        sic::AccountScope scope(C.acct);
         const double tI = tol_I > 0 ? tol_I : C.opt.cg_tol_I;
         const double tN = tol_N > 0 ? tol_N : C.opt.cg_tol_N;
         sic::BlockResult R = sic::block_update(C, p->P, j0, b, level == 0, false, tI, tN);
@@ -373,6 +372,7 @@ int sic_step_last_block(sic_prob* p, int64_t* colptr, int32_t* rows, double* g, 
     if (!p) return SIC_EINVAL;
     return guard([&]() {
         sic::Context& C = p->ctx->c;
+        sic::AccountScope scope(C.acct);
         sic::BlockWork& W = C.work;
         const sic::BlockResult& R = C.last;
         hipStream_t s = C.stream;
@@ -405,6 +405,7 @@ int sic_step_sweep(sic_prob* p, int level, double tol_I, double tol_N, double* k
     if (!p || level < 0) return SIC_EINVAL;
     return guard([&]() {
         sic::Context& C = p->ctx->c;
+        sic::AccountScope scope(C.acct);
         const double tI = tol_I > 0 ? tol_I : C.opt.cg_tol_I;
         const double tN = tol_N > 0 ? tol_N : C.opt.cg_tol_N;
         sic::SweepResult S = sic::sweep(C, p->P, level == 0, tI, tN);
@@ -417,6 +418,7 @@ int sic_step_sweep(sic_prob* p, int level, double tol_I, double tol_N, double* k
 int sic_step_kkt(sic_prob* p, double tol_cg, double* kkt_max, double* kkt_l1) {
     if (!p || !(tol_cg > 0.0)) return SIC_EINVAL;
     return guard([&]() {
+        sic::AccountScope scope(p->ctx->c.acct);
         double l1 = 0.0;
         const double m = sic::exact_kkt(p->ctx->c, p->P, tol_cg, &l1);
         if (kkt_max) *kkt_max = m;
@@ -452,6 +454,7 @@ int sic_step_cd(sic_ctx* ctx, int jp, int b, const double* wjj, const int64_t* c
     for (int64_t t = 0; t < nc; ++t)
         if (cp[t] < 0 || cp[t] >= jp) return SIC_EINVAL;
     return guard([&]() {
+        sic::AccountScope scope(ctx->c.acct);
         return sic::step_cd_impl(ctx->c, jp, b, wjj, cptr, cp, S, A, lambda, max_sweeps, tol,
                                  delta_out, stats_out);
     });
@@ -469,6 +472,7 @@ int sic_step_linesearch(sic_ctx* ctx, int jp, int b, const double* wjj, const in
     for (int64_t t = 0; t < nc; ++t)
         if (cp[t] < 0 || cp[t] >= jp) return SIC_EINVAL;
     return guard([&]() {
+        sic::AccountScope scope(ctx->c.acct);
         return sic::step_ls_impl(ctx->c, jp, b, wjj, cptr, cp, S, A, delta, lambda, alpha, dF,
                                  trials, logdet_out, n_alpha);
     });

@@ -24,6 +24,8 @@
 // around it is spread over 8 waves.
 #include "profiler.h"
 
+#include <mutex>
+
 namespace sic {
 
 namespace {
@@ -816,6 +818,18 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
 
 }  // namespace
 
+// Raises a kernel's dynamic-LDS limit to the device maximum, once per kernel
+// (host threads of the serving loop may launch concurrently).
+static void allow_dynamic_lds(const void* kern) {
+    static std::mutex mu;
+    static std::vector<const void*> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (std::find(done.begin(), done.end(), kern) != done.end()) return;
+    SIC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)CD_MAX_LDS_BYTES));
+    done.push_back(kern);
+}
+
 size_t cd_lds_bytes(int jp, bool u_in_lds) {
     const size_t fixed = (size_t)6 * CD_CHUNK + CD_CHUNK / 2 + (size_t)CD_CHUNK * CD_WPAD +
                          (size_t)CD_COLCAP + CD_COLCAP / 2 + CD_MAXB;
@@ -840,13 +854,7 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
     const bool in_lds = lds_full <= CD_MAX_LDS_BYTES;
     const size_t lds = cd_lds_bytes(jp, in_lds);
     if (in_lds) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            SIC_HIP(hipFuncSetAttribute((const void*)k_cd<true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)CD_MAX_LDS_BYTES));
-            attr_set = true;
-        }
+        allow_dynamic_lds((const void*)k_cd<true>);
         hipLaunchKernelGGL(k_cd<true>, dim3(1), dim3(CD_THREADS), lds, s, jp, b, cptr, c_p, c_S,
                            c_A, c_inva, c_wtc, WJJ, lam, max_sweeps, tol, U, delta, mu_col, ug,
                            markg, stats);
@@ -887,12 +895,7 @@ int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int3
     prof_end(KK_CD_HESS, s, 8.0 * (double)ncoord * ncoord, 3.0 * (double)ncoord * ncoord);
     const int rows = (int)((ncoord + CDH_THREADS - 1) / CDH_THREADS);
     auto launch = [&](auto kern) {
-        static bool attr_set[CDH_RMAX + 1] = {};
-        if (!attr_set[rows]) {
-            SIC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)CD_MAX_LDS_BYTES));
-            attr_set[rows] = true;
-        }
+        allow_dynamic_lds((const void*)kern);
         prof_begin(KK_CD, s);
         hipLaunchKernelGGL(kern, dim3(1), dim3(CDH_THREADS), lds, s, ncoord, HT, c_S, c_A, c_inva,
                            c_wtc, lam, max_sweeps, tol, delta, stats);
@@ -902,12 +905,7 @@ int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int3
     // rows the workers cover: all but two chunks (all but one or none for C <= 2)
     const int prow = (int)((std::max<int64_t>(ncoord - 2 * CDH_K, 1) + CDP_WORKERS - 1) / CDP_WORKERS);
     auto launch_pipe = [&](auto kern) {
-        static bool attr = false;
-        if (!attr) {
-            SIC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)CD_MAX_LDS_BYTES));
-            attr = true;
-        }
+        allow_dynamic_lds((const void*)kern);
         prof_begin(KK_CD, s);
         hipLaunchKernelGGL(kern, dim3(1), dim3(CDP_THREADS), lds_pipe, s, ncoord, HT, c_S, c_A,
                            c_inva, c_wtc, lam, max_sweeps, tol, delta, stats);

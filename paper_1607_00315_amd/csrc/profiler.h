@@ -17,6 +17,7 @@ enum KernelKind {
     KK_UPD_ROWS,
     KK_CD_HESS,
     KK_TRSM,
+    KK_PCD,
     KK_COUNT
 };
 

@@ -26,7 +26,9 @@ struct Profiler {
     hipEvent_t open[KK_COUNT] = {};
 };
 
-Profiler g;
+// Per host thread: a solve is timed on the thread that runs it, and the
+// serving loop's worker threads never contend for it.
+thread_local Profiler g;
 
 hipEvent_t take_event() {
     if (!g.free_events.empty()) {
@@ -63,7 +65,7 @@ void resolve() {
 const char* kernel_kind_name(int kind) {
     static const char* names[KK_COUNT] = {"sj_gemm_f64", "sddmm", "cg_spmm", "cg_update",
                                           "screen_fine", "cd", "chol", "gemm_small", "upd_rows", "cd_hess",
-                                          "trsm"};
+                                          "trsm", "pcd"};
     return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";
 }
 

@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -33,9 +35,24 @@ struct SicError : std::runtime_error {
 
 #define SIC_CHECK_LAUNCH() SIC_HIP(hipGetLastError())
 
-// Bytes of device memory allocated through DevBuf (for the HBM budget).
-extern size_t g_dev_bytes;
-extern size_t g_dev_budget;
+// Device bytes held by one owner (a context or a serving slot), with an
+// optional cap. Every DevBuf charges the account that was current on its
+// thread when it allocated, and keeps it alive until it frees.
+struct MemAccount {
+    std::atomic<size_t> bytes{0};
+    std::atomic<size_t> budget{0};   // 0: no cap
+};
+// The account of the calling thread (a process-wide uncapped one by default).
+const std::shared_ptr<MemAccount>& current_account();
+// Makes `a` the calling thread's account for the lifetime of the scope.
+struct AccountScope {
+    explicit AccountScope(const std::shared_ptr<MemAccount>& a);
+    ~AccountScope();
+    AccountScope(const AccountScope&) = delete;
+    AccountScope& operator=(const AccountScope&) = delete;
+  private:
+    std::shared_ptr<MemAccount> prev_;
+};
 // Largest dynamic LDS a workgroup may use on the current device.
 extern size_t CD_MAX_LDS_BYTES;
 
@@ -44,6 +61,7 @@ template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t cap = 0;
+    std::shared_ptr<MemAccount> acct;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -51,16 +69,19 @@ struct DevBuf {
     void release() {
         if (p) {
             (void)hipFree(p);
-            g_dev_bytes -= cap * sizeof(T);
+            acct->bytes -= cap * sizeof(T);
         }
         p = nullptr;
         cap = 0;
+        acct.reset();
     }
     void reserve(size_t count) {
         if (count <= cap && p) return;
         release();
         size_t bytes = (count ? count : 1) * sizeof(T);
-        if (g_dev_budget && g_dev_bytes + bytes > g_dev_budget)
+        const std::shared_ptr<MemAccount>& a = current_account();
+        const size_t cap_bytes = a->budget.load();
+        if (cap_bytes && a->bytes.load() + bytes > cap_bytes)
             throw SicError(SIC_ENOMEM, "HBM budget exceeded by a " + std::to_string(bytes) +
                                            "-byte buffer");
         hipError_t e = hipMalloc(&p, bytes);
@@ -70,7 +91,8 @@ struct DevBuf {
             throw SicError(SIC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
         }
         cap = count ? count : 1;
-        g_dev_bytes += cap * sizeof(T);
+        acct = a;
+        acct->bytes += cap * sizeof(T);
     }
 };
 
@@ -163,6 +185,22 @@ int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int3
                           const double* WJJ, const double* c_S, const double* c_A,
                           const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
                           double tol, double* HT, double* delta, double* stats, hipStream_t s);
+
+// ---------------------------------------------------------------- k_pcd.hip
+struct PcdWork {
+    DevBuf<double> z, Y, pdiag, part, sc;
+    DevBuf<double> d[2], p[2], zp[2];
+    DevBuf<int32_t> dg;
+};
+// Newton direction by PCD-CG on the free coordinates (delta: in, zero; out,
+// the direction). Returns the profiler record (bytes and flops of one
+// iteration, to be scaled by the iteration count in stats[0]) or -1. Reads the
+// stop flag through the pinned double h_flag every four iterations.
+int64_t launch_pcd(int64_t nc, int jp, int b, const int64_t* cptr, const int32_t* c_p,
+                   const int32_t* c_ci, const double* c_S, const double* c_A,
+                   const double* c_wtc, const double* c_inva, const double* WJJ, double lam,
+                   int max_iter, double tol, double* delta, PcdWork& wk, double* stats,
+                   double* h_flag, hipStream_t s);
 
 // ---------------------------------------------------------------- k_dense.hip
 // dinv (batch 1 only, may be null) receives the inverses of the factor's

@@ -12,6 +12,7 @@ struct Options {
     double cd_tol = 1e-4;
     int cd_max_sweeps = 20;
     int cd_hessian_max = 4096;   // 0: never use the explicit-Hessian sweep
+    int pcd_min_coords = 4097;   // blocks with at least this many coordinates use PCD-CG; 0: never
     int ls_max_trials = 31;
     int max_cycles = 100;
     uint64_t flags = 0;
@@ -22,6 +23,7 @@ struct Options {
 struct BlockWork {
     DevBuf<double> SJ, WI, AJ, ANEW, WN, WJJ, U, ug, HT;
     DevBuf<unsigned char> markg;
+    DevBuf<char> xstage;   // reduced-precision X before its conversion
     DevBuf<int32_t> cols;
     // free lists
     DevBuf<int64_t> colptr;
@@ -42,6 +44,7 @@ struct BlockWork {
     // CSR rebuild
     DevBuf<int32_t> rcount;
     CGWork cg;
+    PcdWork pcd;
     int64_t n_init = 0;   // n for which flag/map arrays are initialised
     int b_init = 0;
 };
@@ -86,6 +89,7 @@ struct Context {
     bool own_stream = false;
     Options opt;
     size_t budget = 0;
+    std::shared_ptr<MemAccount> acct = std::make_shared<MemAccount>();
     BlockWork work;
     sic_trace_entry* trace = nullptr;
     int trace_cap = 0;
@@ -94,6 +98,13 @@ struct Context {
     double* h_f64 = nullptr;
     BlockResult last;
 };
+
+// context set-up (stream, pinned staging, options) and release; the context's
+// device workspace is freed with the Context itself
+void context_init(Context& C, const sic_options& o);
+void context_release(Context& C);
+// frees the block workspace (the next block update allocates it again)
+void release_workspace(Context& C);
 
 // problem setup / transfer
 void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n, int64_t m,
@@ -117,6 +128,11 @@ void hierarchy_host(int64_t n, const std::vector<int64_t>& supp,
                     std::vector<int64_t>& ranking, std::vector<int64_t>& sizes);
 std::vector<int64_t> support_keys(Context& C, Problem& P);
 int solve_problem(Context& C, Problem& P, double tol, sic_info* info);
+// One request of sic_solve_batch (or of the serving loop): set-up, optional
+// warm start, then the lambda path (or the single lambda). Results go to
+// A_out[0 .. results) and info[0 .. results); returns the first bad status.
+int solve_request(Context& C, Problem& P, const sic_problem& q, sic_csr* A_out, sic_info* info);
+int request_results(const sic_problem& q);
 double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1);
 
 }  // namespace sic

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <numeric>
 
 #include "profiler.h"
@@ -17,9 +18,24 @@
 
 namespace sic {
 
-size_t g_dev_bytes = 0;
-size_t g_dev_budget = 0;
 size_t CD_MAX_LDS_BYTES = 65536;
+
+namespace {
+std::shared_ptr<MemAccount>& default_account() {
+    static std::shared_ptr<MemAccount> a = std::make_shared<MemAccount>();
+    return a;
+}
+thread_local std::shared_ptr<MemAccount> t_account;
+}  // namespace
+
+const std::shared_ptr<MemAccount>& current_account() {
+    return t_account ? t_account : default_account();
+}
+
+AccountScope::AccountScope(const std::shared_ptr<MemAccount>& a) : prev_(t_account) {
+    t_account = a;
+}
+AccountScope::~AccountScope() { t_account = prev_; }
 
 namespace {
 
@@ -189,7 +205,7 @@ void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n,
         SIC_HIP(hipMemcpyAsync(P.X.p, X, count * esz,
                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     } else {
-        DevBuf<char> tmp;
+        DevBuf<char>& tmp = C.work.xstage;   // kept: no free (and no device sync) per problem
         tmp.reserve(count * esz);
         SIC_HIP(hipMemcpyAsync(tmp.p, X, count * esz,
                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
@@ -338,6 +354,10 @@ static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
     W.cdstats.reserve(8);
+    if (nc > 0 && C.opt.pcd_min_coords > 0 && nc >= C.opt.pcd_min_coords)
+        return launch_pcd(nc, jp, b, W.cptr.p, W.c_p.p, W.c_ci.p, W.c_S.p, W.c_A.p, W.c_wtc.p,
+                          W.c_inva.p, W.WJJ.p, lam, 10 * max_sweeps, tol, W.delta.p,
+                          W.pcd, W.cdstats.p, C.h_f64 + 32, s);
     if (nc > 0 && nc <= C.opt.cd_hessian_max && nc <= cd_hessian_limit() &&
         cd_hessian_lds_bytes(nc) <= CD_MAX_LDS_BYTES) {
         W.HT.reserve((size_t)nc * nc);
@@ -903,6 +923,55 @@ int step_ls_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cp
         for (int t = 0; t < nt; ++t) logdet_out[i + t] = pd[t] ? ld[t] : NAN;
     }
     return SIC_OK;
+}
+
+}  // namespace sic
+
+namespace sic {
+
+int request_results(const sic_problem& q) { return q.n_lambda > 0 ? q.n_lambda : 1; }
+
+int solve_request(Context& C, Problem& P, const sic_problem& q, sic_csr* A_out, sic_info* info) {
+    if (!q.X || q.n < 1 || q.m < 1 || !(q.tol > 0.0) || q.n > INT32_MAX ||
+        (q.x_dtype != SIC_X_F64 && q.x_dtype != SIC_X_F32 && q.x_dtype != SIC_X_BF16) ||
+        (q.n_lambda > 0 && !q.lambda_path))
+        throw SicError(SIC_EINVAL, "bad problem");
+    const int nl = request_results(q);
+    auto lam_at = [&](int l) { return q.n_lambda > 0 ? q.lambda_path[l] : q.lambda; };
+    for (int l = 0; l < nl; ++l) {
+        const double lam = lam_at(l);
+        if (!(lam >= 0.0) || !std::isfinite(lam) || (lam == 0.0 && q.m <= q.n))
+            throw SicError(SIC_EINVAL, "bad lambda");
+    }
+    problem_init(C, P, q.X, q.x_dtype, q.n, q.m, lam_at(0));
+    if (q.A0) {
+        set_A_host(C, P, q.A0);
+        P.F = NAN;   // the tracked objective of a warm start is not known
+    }
+    int worst = SIC_OK;
+    for (int l = 0; l < nl; ++l) {
+        const double lam = lam_at(l);
+        if (l > 0) {
+            // warm start from the previous lambda: F changes by (lam - lam_prev) * ||A||_1
+            P.F += (lam - P.lam) * a_l1_norm(C, P);
+            P.lam = lam;
+        }
+        sic_info* inf = info ? &info[l] : nullptr;
+        const int st = solve_problem(C, P, q.tol, inf);
+        get_A_host(C, P, &A_out[l]);
+        if (st != SIC_OK && worst == SIC_OK) worst = st;
+    }
+    return worst;
+}
+
+}  // namespace sic
+
+namespace sic {
+
+void release_workspace(Context& C) {
+    sync(C);
+    C.work.~BlockWork();
+    new (&C.work) BlockWork();
 }
 
 }  // namespace sic

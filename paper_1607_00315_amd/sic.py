@@ -45,7 +45,8 @@ class Options(ct.Structure):
     _fields_ = [("device", ct.c_int), ("hbm_budget", ct.c_size_t), ("precision", ct.c_int),
                 ("block", ct.c_int), ("cg_tol_I", ct.c_double), ("cg_tol_N", ct.c_double),
                 ("cg_max_iter", ct.c_int), ("cd_tol", ct.c_double), ("cd_max_sweeps", ct.c_int),
-                ("cd_hessian_max", ct.c_int), ("ls_max_trials", ct.c_int), ("max_cycles", ct.c_int), ("stream", ct.c_void_p),
+                ("cd_hessian_max", ct.c_int), ("pcd_min_coords", ct.c_int),
+                ("ls_max_trials", ct.c_int), ("max_cycles", ct.c_int), ("stream", ct.c_void_p),
                 ("flags", ct.c_uint64), ("trace", ct.POINTER(TraceEntry)), ("trace_cap", ct.c_int)]
 
 
@@ -64,6 +65,19 @@ class ProblemSpec(ct.Structure):
     _fields_ = [("X", ct.c_void_p), ("n", ct.c_int64), ("m", ct.c_int64), ("x_dtype", ct.c_int),
                 ("lambda_", ct.c_double), ("tol", ct.c_double), ("A0", ct.POINTER(CSR)),
                 ("lambda_path", ct.POINTER(ct.c_double)), ("n_lambda", ct.c_int)]
+
+
+class ServerOptions(ct.Structure):
+    _fields_ = [("slots", ct.c_int), ("hbm_budget", ct.c_size_t), ("solver", Options),
+                ("device", ct.c_int)]
+
+
+class RequestTimes(ct.Structure):
+    _fields_ = [("submitted", ct.c_double), ("admitted", ct.c_double), ("finished", ct.c_double),
+                ("footprint", ct.c_size_t), ("slot", ct.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class BlockResult(ct.Structure):
@@ -117,6 +131,17 @@ SIGNATURES = {
     "sic_step_linesearch": (ct.c_int, [_P, ct.c_int, ct.c_int, _dp, _i64p, _i32p, _dp, _dp, _dp,
                                        ct.c_double, _dp, _dp, ct.POINTER(ct.c_int), _dp,
                                        ct.c_int]),
+    "sic_server_options_default": (None, [ct.POINTER(ServerOptions)]),
+    "sic_server_create": (ct.c_int, [_PP, ct.POINTER(ServerOptions)]),
+    "sic_server_footprint": (ct.c_size_t, [_P, ct.POINTER(ProblemSpec)]),
+    "sic_server_submit": (ct.c_int, [_P, ct.POINTER(ProblemSpec), ct.POINTER(ct.c_uint64)]),
+    "sic_server_wait": (ct.c_int, [_P, ct.c_uint64, ct.c_double, ct.POINTER(CSR),
+                                   ct.POINTER(Info), ct.POINTER(RequestTimes)]),
+    "sic_server_cancel": (ct.c_int, [_P, ct.c_uint64]),
+    "sic_request_results": (ct.c_int, [ct.POINTER(ProblemSpec)]),
+    "sic_server_status": (None, [_P, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
+                                 ct.POINTER(ct.c_int), ct.POINTER(ct.c_size_t)]),
+    "sic_server_destroy": (None, [_P]),
     "sic_profile_enable": (None, [ct.c_int]),
     "sic_profile_reset": (None, []),
     "sic_profile_read": (ct.c_int, [ct.c_int, _i64p, _dp, _dp, _dp]),
@@ -208,6 +233,30 @@ def options(**kw) -> Options:
     return o
 
 
+def _fill_spec(s: ProblemSpec, p: dict, keep: list) -> int:
+    """Fill a sic_problem from a dict; returns its result count. Arrays that
+    must outlive the call are appended to ``keep``."""
+    X = p["X"]
+    s.X = _data_ptr(X).value
+    s.n, s.m = X.shape[1], X.shape[0]
+    s.x_dtype = p.get("x_dtype", SIC_X_F64)
+    s.tol = p["tol"]
+    if p.get("A0") is not None:
+        c, arrs = csr_from_arrays(*p["A0"])
+        keep.extend([c, arrs])
+        s.A0 = ct.pointer(c)
+    path = p.get("lambda_path")
+    if path is not None:
+        arr = np.ascontiguousarray(path, dtype=np.float64)
+        keep.append(arr)
+        s.lambda_path = _ptr(arr, ct.c_double)
+        s.n_lambda = arr.size
+        return arr.size
+    s.lambda_ = p["lam"]
+    s.n_lambda = 0
+    return 1
+
+
 class Context:
     """One library context (HIP stream + device buffers) on one GPU."""
 
@@ -256,29 +305,13 @@ class Context:
         return A, info.as_dict(), self.trace(info.trace_len)
 
     def solve_batch(self, problems):
-        """problems: list of dicts with X, lam or lambda_path, tol, optional x_dtype."""
+        """problems: list of dicts with X, lam or lambda_path, tol, optional x_dtype, A0."""
         count = len(problems)
         specs = (ProblemSpec * count)()
         keep = []
         slots = 0
         for k, p in enumerate(problems):
-            X = p["X"]
-            s = specs[k]
-            s.X = _data_ptr(X).value
-            s.n, s.m = X.shape[1], X.shape[0]
-            s.x_dtype = p.get("x_dtype", SIC_X_F64)
-            s.tol = p["tol"]
-            path = p.get("lambda_path")
-            if path is not None:
-                arr = np.ascontiguousarray(path, dtype=np.float64)
-                keep.append(arr)
-                s.lambda_path = _ptr(arr, ct.c_double)
-                s.n_lambda = arr.size
-                slots += arr.size
-            else:
-                s.lambda_ = p["lam"]
-                s.n_lambda = 0
-                slots += 1
+            slots += _fill_spec(specs[k], p, keep)
         outs = (CSR * slots)()
         infos = (Info * slots)()
         code = lib().sic_solve_batch(self.h, count, specs, outs, infos)
@@ -290,6 +323,89 @@ class Context:
             return []
         return [dict(seconds=e.seconds, objective=e.objective, kkt_max=e.kkt_max, nnz=e.nnz,
                      cycle=e.cycle, levels=e.levels) for e in self._trace[:length]]
+
+
+class Server:
+    """The serving loop of include/sic_serve.h: submit problems, wait for them.
+
+    ``slots`` problems run concurrently (one HIP stream and host worker each);
+    ``hbm_budget`` bounds their device memory together (0: 80% of free).
+    Solver options are passed as keyword arguments, as for :class:`Context`.
+    """
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 0, device: int = 0, **opts):
+        o = ServerOptions()
+        lib().sic_server_options_default(ct.byref(o))
+        o.slots, o.hbm_budget, o.device = slots, hbm_budget, device
+        so = options(**opts)
+        o.solver = so
+        h = ct.c_void_p()
+        _check(lib().sic_server_create(ct.byref(h), ct.byref(o)), "sic_server_create")
+        self.h = h
+        self._live = {}   # ticket -> (spec, arrays the request reads, result count)
+
+    def footprint(self, problem: dict) -> int:
+        s = ProblemSpec()
+        keep = []
+        _fill_spec(s, problem, keep)
+        return lib().sic_server_footprint(self.h, ct.byref(s))
+
+    def submit(self, problem: dict) -> int:
+        """Queue a problem (dict as for Context.solve_batch); returns its ticket.
+        X is read when the request is admitted: it is kept alive here until
+        :meth:`wait` returns the request."""
+        s = ProblemSpec()
+        keep = [problem["X"]]
+        nres = _fill_spec(s, problem, keep)
+        t = ct.c_uint64()
+        _check(lib().sic_server_submit(self.h, ct.byref(s), ct.byref(t)), "sic_server_submit")
+        self._live[t.value] = (s, keep, nres)
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """Returns (status, [(rowptr, col, val), ...], [info dict, ...], times dict),
+        or None on timeout."""
+        _, _, nres = self._live[ticket]
+        outs = (CSR * nres)()
+        infos = (Info * nres)()
+        times = RequestTimes()
+        code = lib().sic_server_wait(self.h, ticket, float(timeout), outs, infos, ct.byref(times))
+        if code == 1:
+            return None
+        if code == SIC_EINVAL and ticket not in self._live:
+            raise SicError(code, "sic_server_wait")
+        del self._live[ticket]
+        results = []
+        for i in range(nres):
+            results.append(_csr_to_numpy(outs[i]) if outs[i].rowptr else None)
+        return code, results, [infos[i].as_dict() for i in range(nres)], times.as_dict()
+
+    def cancel(self, ticket: int) -> bool:
+        return lib().sic_server_cancel(self.h, ticket) == SIC_OK
+
+    def status(self):
+        q, r, d = ct.c_int(), ct.c_int(), ct.c_int()
+        held = ct.c_size_t()
+        lib().sic_server_status(self.h, ct.byref(q), ct.byref(r), ct.byref(d), ct.byref(held))
+        return dict(queued=q.value, running=r.value, done=d.value, held_bytes=held.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sic_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Prob:
@@ -439,7 +555,7 @@ def hierarchy(n, supp_keys, free_keys, free_absg):
     return rank[:rlen.value], list(sizes[:nl.value])
 
 
-KERNEL_CLASSES = 11
+KERNEL_CLASSES = 12
 
 
 def profile_enable(on=True):

@@ -33,7 +33,8 @@ def _exact_kkt(A, S, lam):
     ("chain_n200_m100", True, "hessian"), ("chain_n200_m100", False, "hessian"),
     ("chain_n200_m100", True, "u"), ("chain_n64_m48", True, "hessian"),
     ("random_n600_m300", True, "hessian"), ("random_n600_m300", True, "u"),
-    ("grid_n900_m600", True, "hessian")])
+    ("grid_n900_m600", True, "hessian"), ("chain_n200_m100", True, "pcd"),
+    ("random_n600_m300", True, "pcd"), ("grid_n900_m600", False, "pcd")])
 def test_solve_matches_oracle(name, multilevel, cd_form):
     from paper_1607_00315_amd import sic
     X, P, spec = workload(name)
@@ -42,7 +43,8 @@ def test_solve_matches_oracle(name, multilevel, cd_form):
     announce(f"solve {name} lam={lam} b={spec['block']} multilevel={multilevel} cd={cd_form}")
     flags = 0 if multilevel else sic.FLAG_NO_MULTILEVEL
     A, info = _solve(X, lam, 1e-7, block=spec["block"], flags=flags,
-                     cd_hessian_max=0 if cd_form == "hessian" else -1)
+                     cd_hessian_max=0 if cd_form == "hessian" else -1,
+                     pcd_min_coords=1 if cd_form == "pcd" else -1)
     Aq, _ = quic_plain.solve(S, lam, tol=1e-12)
     assert np.array_equal(A, A.T)
     assert np.array_equal(A != 0, Aq != 0), \

@@ -162,6 +162,51 @@ def test_cd_step_matches_oracle(ctx, ctx_u, rnd600, start, form):
     assert np.max(np.abs(got2 - ref2)) <= 1e-3 * max(1e-12, np.max(np.abs(ref2)))
 
 
+@pytest.fixture(scope="module")
+def ctx_pcd():
+    """Context whose blocks all take the PCD-CG direction."""
+    from paper_1607_00315_amd import sic
+    c = sic.Context(block=128, pcd_min_coords=1)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("start", ["identity", "iterate"])
+def test_pcd_step_matches_oracle(ctx_pcd, rnd600, start):
+    """PCD-CG against the oracle's PCD-CG: the same iterations (10 line
+    searches, no stop test), the default stopping rule, and run to convergence
+    against the cyclic-CD minimiser of the same block model."""
+    from oracle import pcd
+    from paper_1607_00315_amd import sic
+    X, P, spec, S = rnd600
+    lam = spec["lam"]
+    A = np.eye(600) if start == "identity" else _mlbcd_iterate(X, lam, 128)[0]
+    j0, j1 = 128, 256
+    d = _block_inputs(A, S, lam, j0, j1)
+    ci = d["c"] - j0
+    announce(f"step_cd (PCD-CG) random_n600 start={start} coords={d['r'].size} |N|={d['N'].size}")
+    got, st = sic.step_cd(ctx_pcd, d["wjj"], d["b"], d["cptr"], d["cp"], d["S"], d["A"], lam,
+                          max_sweeps=1, tol=0.0)
+    ref, its, _ = pcd.pcd_cg(d["wjj"], d["cp"], ci, d["S"], d["A"], lam, max_iter=10, tol=0.0)
+    if start == "iterate":
+        assert int(st[0]) == its
+    # at the identity start W = I makes the model separable: the first PCD step
+    # is its exact minimiser and the later line searches act on rounding noise,
+    # so the two sides may stop after different counts at the same answer
+    scale = max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(got - ref)) <= 1e-9 * scale
+    assert np.array_equal(got == -d["A"], ref == -d["A"])      # exact zeros agree
+    got2, st2 = sic.step_cd(ctx_pcd, d["wjj"], d["b"], d["cptr"], d["cp"], d["S"], d["A"], lam)
+    ref2, its2, _ = pcd.pcd_cg(d["wjj"], d["cp"], ci, d["S"], d["A"], lam)
+    assert abs(int(st2[0]) - its2) <= 1
+    assert np.max(np.abs(got2 - ref2)) <= 1e-3 * max(1e-12, np.max(np.abs(ref2)))
+    got3, st3 = sic.step_cd(ctx_pcd, d["wjj"], d["b"], d["cptr"], d["cp"], d["S"], d["A"], lam,
+                            max_sweeps=100, tol=1e-12)
+    ref3, _, _ = cd_sweeps(d["wjj"], d["cp"], ci, d["S"], d["A"], lam, 1000, 1e-14)
+    assert np.max(np.abs(got3 - ref3)) <= 1e-7 * max(1.0, np.max(np.abs(ref3)))
+    assert np.array_equal(got3 + d["A"] == 0, ref3 + d["A"] == 0)
+
+
 @pytest.mark.parametrize("start", ["identity", "iterate"])
 def test_linesearch_step_matches_oracle(ctx, rnd600, start):
     from paper_1607_00315_amd import sic

@@ -161,6 +161,58 @@ def test_cd_converges_to_model_kkt():
     assert np.all(np.abs(Gt[~on]) <= lam + 1e-10)
 
 
+def _model_block(seed, nj=8, lam=0.3):
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((nj, nj))
+    W = B @ B.T / nj + np.eye(nj)
+    S = rng.standard_normal((nj, nj)) * 0.5; S = S + S.T
+    A = rng.standard_normal((nj, nj)) * 0.2; A = (A + A.T) * (rng.random((nj, nj)) < 0.5)
+    A = np.triu(A) + np.triu(A, 1).T
+    ri, ci = np.triu_indices(nj)
+    return W, S, A, ri, ci, lam
+
+
+@pytest.mark.parametrize("seed", [8, 9, 10])
+def test_pcd_cg_converges_to_the_cd_minimiser(seed):
+    """PCD-CG and cyclic CD minimise the same strictly convex block model: run
+    to convergence they meet at its unique minimiser (checked by its KKT)."""
+    from oracle import pcd
+    W, S, A, ri, ci, lam = _model_block(seed)
+    Dc, _, _ = cd_sweeps(W, ri, ci, S[ri, ci], A[ri, ci], lam, 5000, 0.0)
+    Dp, its, _ = pcd.pcd_cg(W, ri, ci, S[ri, ci], A[ri, ci], lam, max_iter=3000, tol=1e-13)
+    assert its > 3
+    assert np.max(np.abs(Dp - Dc)) <= 1e-8 * max(1.0, np.max(np.abs(Dc)))
+    Dm = np.zeros_like(W); Dm[ri, ci] = Dp; Dm[ci, ri] = Dp
+    Gt = S - W + W @ Dm @ W
+    X = A + Dm
+    on = X != 0
+    assert np.all(np.abs(Gt[on] + lam * np.sign(X[on])) <= 1e-7)
+    assert np.all(np.abs(Gt[~on]) <= lam + 1e-7)
+
+
+def test_pcd_first_step_is_the_grid_minimiser_of_the_model():
+    """One PCD-CG iteration from Delta = 0: p is every coordinate's own 1-D
+    minimiser (brute force, independent of the closed form), and the step is
+    the candidate with the smallest model value evaluated directly with dense
+    matrices (independent of the B, C, l1 split the iteration uses)."""
+    from oracle import pcd
+    W, S, A, ri, ci, lam = _model_block(11, nj=7)
+    Sv, Av = S[ri, ci], A[ri, ci]
+    D1, its, _ = pcd.pcd_cg(W, ri, ci, Sv, Av, lam, max_iter=1, tol=0.0, snap=False)
+    assert its == 1
+    p = np.empty(ri.size)
+    for k in range(ri.size):
+        def f(mu, k=k):
+            e = np.zeros(ri.size); e[k] = mu
+            return pcd.block_model(W, ri, ci, Sv, Av, lam, e)
+        r = so.minimize_scalar(f, bracket=(-3, 3), tol=1e-14)
+        p[k] = r.x
+    vals = [pcd.block_model(W, ri, ci, Sv, Av, lam, s * p) for s in pcd.GRID]
+    best = pcd.GRID[int(np.argmin(vals))]
+    assert min(vals) < pcd.block_model(W, ri, ci, Sv, Av, lam, 0 * p)
+    assert np.max(np.abs(D1 - best * p)) <= 1e-6 * max(1.0, np.max(np.abs(p)))
+
+
 # ---------------------------------------------------------------- Schur route, App. A
 
 def _structured(seed, n=12, I=(0, 1, 2, 3), N=(5, 7, 9)):

@@ -33,6 +33,16 @@ def block_model(W, ri, ci, S_vals, A_vals, lam, D):
             + 0.5 * np.trace(W @ M @ W @ M))
 
 
+def l1_change(x, s):
+    """|x + s| - |x| term by term; where x + s keeps the sign of x this is +-s
+    exactly (near the minimiser the steps are far below |x|, and the difference
+    of two sums of |x| would lose them to rounding)."""
+    y = x + s
+    keep_pos = (x > 0) & (y >= 0)
+    keep_neg = (x < 0) & (y <= 0)
+    return np.where(keep_pos, s, np.where(keep_neg, -s, np.abs(y) - np.abs(x)))
+
+
 def hessian_product(W, ri, ci, p):
     """(W P W) at the free coordinates, P the symmetric matrix with entries p."""
     nj = W.shape[0]
@@ -86,11 +96,11 @@ def pcd_cg(W, ri, ci, S_vals, A_vals, lam, max_iter=200, tol=1e-4, snap=True):
         restart = False
         p = d + beta * p_prev
         zp = hessian_product(W, ri, ci, p)
-        B = np.sum(gam * b * p)
         C = np.sum(gam * p * zp)
         cand = centre * GRID
-        l1_0 = np.sum(gam * np.abs(x))
-        phi = np.array([s * B + 0.5 * s * s * C + lam * (np.sum(gam * np.abs(x + s * p)) - l1_0)
+        # linear and l1 parts coordinate by coordinate: near the minimiser b is
+        # close to -lam sign(x), and separate sums would cancel
+        phi = np.array([np.sum(gam * (s * p * b + lam * l1_change(x, s * p))) + 0.5 * s * s * C
                         for s in cand])
         j = int(np.argmin(phi))
         if phi[j] < 0.0:

@@ -67,24 +67,48 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, int64_t n, int k, const double* __restrict__ Z,
     double* __restrict__ P, double* __restrict__ Q, const double* __restrict__ scal,
-    double* __restrict__ part, const int* __restrict__ tctl) {
-    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
-    const bool first = tctl[blockIdx.x * T_INTS + T_ITER] == 0;
+    double* __restrict__ part, const int* __restrict__ tctl, int gx, int gy, int xcd_grouped) {
+    // Tile (tx = 64-column tile, ty = row partition). Grouped: a 1-D grid whose
+    // workgroup L runs on XCD L % 8 (round-robin dispatch); every row partition
+    // of a column tile lands on the same XCD, one tile after another, so the
+    // tile's gathered direction rows are served from that XCD's L2.
+    int tx, ty;
+    if (xcd_grouped) {
+        const int L = blockIdx.x, q = L & 7, slot = L >> 3;
+        const int t = slot / gy;
+        ty = slot - t * gy;
+        tx = q + 8 * t;
+        if (tx >= gx) return;
+    } else {
+        tx = blockIdx.x;
+        ty = blockIdx.y;
+    }
+    if (tctl[tx * T_INTS + T_DONE]) return;
+    const bool first = tctl[tx * T_INTS + T_ITER] == 0;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
-    const int j = blockIdx.x * 64 + lane;
+    const int j = tx * 64 + lane;
     const bool jok = j < k;
+    const int jj = jok ? j : k - 1;   // clamped: every lane loads, masked lanes discard
     const double beta = (jok && !first) ? scal[j * 4 + S_BETA] : 0.0;
     double pq = 0.0;
-    for (int64_t i = (int64_t)blockIdx.y * CG_WAVES + wave; i < n;
-         i += (int64_t)gridDim.y * CG_WAVES) {
+    for (int64_t i = (int64_t)ty * CG_WAVES + wave; i < n; i += (int64_t)gy * CG_WAVES) {
         const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
         double acc = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t c = col[e];
-            const double a = val[e];
-            if (jok) acc += a * Z[c * k + j];
+        int64_t e = e0;
+        // eight gathers in flight before their products (rows with many
+        // non-zeros would otherwise wait for each gather in turn)
+        for (; e + 8 <= e1; e += 8) {
+            double zv[8], av[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                av[u] = val[e + u];
+                zv[u] = Z[(int64_t)col[e + u] * k + jj];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += av[u] * zv[u];
         }
+        for (; e < e1; ++e) acc += val[e] * Z[(int64_t)col[e] * k + jj];
         if (jok) {
             const int64_t o = i * k + j;
             const double z = Z[o];
@@ -101,7 +125,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     if (wave == 0) {
         double s = 0.0;
         for (int w = 0; w < CG_WAVES; ++w) s += red[w][lane];
-        if (jok) part[(int64_t)blockIdx.y * k + j] = s;
+        if (jok) part[(int64_t)ty * k + j] = s;
     }
 }
 
@@ -244,6 +268,10 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
                        col_tiles, d_cols, wk.dinv.p, wk.R.p, wk.Z.p, wk.scal.p, wk.flags.p, tres);
     SIC_CHECK_LAUNCH();
     dim3 grid(col_tiles, row_tiles);
+    // XCD grouping of the product's tiles once there are enough column tiles to
+    // give every XCD one (fewer would leave XCDs idle)
+    const int grouped = col_tiles >= 8 ? 1 : 0;
+    const dim3 sgrid = grouped ? dim3((unsigned)(8 * ((col_tiles + 7) / 8) * row_tiles)) : grid;
     std::vector<int> hctl((size_t)T_INTS * col_tiles);
     std::vector<double> hres(col_tiles);
     int launched = 0;
@@ -266,9 +294,9 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
             Rec r;
             r.iter = it;
             prof_begin(KK_CG_SPMM, s);
-            hipLaunchKernelGGL(k_cg_spmm, grid, dim3(CG_THREADS), 0, s, A.rowptr.p, A.col.p,
+            hipLaunchKernelGGL(k_cg_spmm, sgrid, dim3(CG_THREADS), 0, s, A.rowptr.p, A.col.p,
                                A.val.p, n, k, wk.Z.p, wk.P.p, wk.Q.p, wk.scal.p, wk.part.p,
-                               wk.flags.p);
+                               wk.flags.p, col_tiles, row_tiles, grouped);
             SIC_CHECK_LAUNCH();
             r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
                               2.0 * A.nnz * k + 4.0 * n * k);

@@ -24,9 +24,11 @@
 //      the block columns (pdiag: p on each column's diagonal coordinate);
 //   4. line search on the exact model along p: the best of 64 step sizes on a
 //      geometric grid (ratio 2^(1/8)) centred on the last accepted step; the
-//      quadratic part is alpha B + alpha^2 C / 2 with B = <b, p>, C = <p, zp>,
-//      the l1 part is summed per candidate; no candidate below q(Delta) means
-//      alpha = 0 and a restart;
+//      model change is sum_k gam_k [alpha p_k b_k + lam (|x_k + alpha p_k| - |x_k|)]
+//      + alpha^2 C / 2 with C = <p, zp>, the first sum taken term by term per
+//      candidate (near the minimiser b_k is close to -lam sign(x_k) and the
+//      steps are far below |x_k|: separate sums would cancel); no candidate
+//      below q(Delta) means alpha = 0 and a restart;
 //   5. Delta += alpha p, z += alpha zp (z stays exact: the model is quadratic).
 // The iteration stops when max |alpha p| <= tol * max |Delta| (the inner
 // precision of Section 8, measured as the coordinate-descent sweeps measure
@@ -53,6 +55,16 @@ enum { SC_ALPHA, SC_CENTER, SC_BETA, SC_DONE, SC_RESTART, SC_ITERS, SC_STEP, SC_
 __device__ inline double wsum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// |x + s| - |x|, exact when x + s keeps the sign of x (it is then +-s): near
+// the minimiser the steps are many orders below |x|, and differencing two sums
+// of |x| would lose them to rounding.
+__device__ inline double l1_change(double x, double s) {
+    const double y = x + s;
+    if (x > 0.0 && y >= 0.0) return s;
+    if (x < 0.0 && y <= 0.0) return -s;
+    return fabs(y) - fabs(x);
 }
 
 __device__ inline double wmax(double v) {
@@ -216,7 +228,7 @@ __global__ __launch_bounds__(PT) void k_pcd_y(
 }
 
 // Second half of step 3 (zp on every coordinate, one wave per coordinate) and
-// the partial sums of step 4: B, C, the l1 sum at alpha = 0 and at every
+// the partial sums of step 4: B, C and the change of the l1 sum at every
 // candidate (lane j holds candidate j).
 __global__ __launch_bounds__(PT) void k_pcd_zp(
     int64_t nc, int jp, int b, const int32_t* __restrict__ c_p, const int32_t* __restrict__ c_ci,
@@ -225,12 +237,12 @@ __global__ __launch_bounds__(PT) void k_pcd_zp(
     const double* __restrict__ Y, const double* __restrict__ pdiag,
     const double* __restrict__ p_new, const double* __restrict__ delta,
     const double* __restrict__ z, double* __restrict__ zp_new, const double* __restrict__ sc,
-    double* __restrict__ part) {
+    double lam, double* __restrict__ part) {
     if (sc[SC_DONE] != 0.0) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double alpha_j = sc[SC_CENTER] * exp2((double)(lane - NCAND / 2) * 0.125);
     const int64_t nwaves = (int64_t)gridDim.x * (PT / 64);
-    double B = 0.0, C = 0.0, L0 = 0.0, Lj = 0.0;
+    double B = 0.0, C = 0.0, Lj = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * (PT / 64) + w; k < nc; k += nwaves) {
         const int r = c_p[k], c = c_ci[k];
         const double* yr = Y + (int64_t)r * b;
@@ -254,8 +266,10 @@ __global__ __launch_bounds__(PT) void k_pcd_zp(
         const double g = r == c ? 1.0 : 2.0;
         B += g * bb * pk;
         C += g * pk * zp;
-        L0 += g * fabs(x);
-        Lj += g * fabs(x + alpha_j * pk);
+        // the linear and l1 parts per coordinate: near the minimiser b is close
+        // to -lam sign(x) and their sums would cancel
+        const double sj = alpha_j * pk;
+        Lj += g * (sj * bb + lam * l1_change(x, sj));
     }
     __shared__ double lj[PT / 64][NCAND];
     __shared__ double bc[PT / 64][3];
@@ -263,7 +277,7 @@ __global__ __launch_bounds__(PT) void k_pcd_zp(
     if (lane == 0) {
         bc[w][0] = B;
         bc[w][1] = C;
-        bc[w][2] = L0;
+        bc[w][2] = 0.0;
     }
     __syncthreads();
     double* out = part + (int64_t)blockIdx.x * ZPP;
@@ -284,16 +298,15 @@ __global__ __launch_bounds__(64) void k_pcd_alpha(int nwg, const double* __restr
                                                   double lam, double* __restrict__ sc) {
     if (sc[SC_DONE] != 0.0) return;
     const int j = threadIdx.x;
-    double B = 0.0, C = 0.0, L0 = 0.0, Lj = 0.0;
+    double B = 0.0, C = 0.0, Lj = 0.0;
     for (int k = 0; k < nwg; ++k) {
         const double* p = part + (int64_t)k * ZPP;
         B += p[0];
         C += p[1];
-        L0 += p[2];
         Lj += p[3 + j];
     }
     const double a = sc[SC_CENTER] * exp2((double)(j - NCAND / 2) * 0.125);
-    const double phi = a * B + 0.5 * a * a * C + lam * (Lj - L0);   // q(Delta + a p) - q(Delta)
+    const double phi = Lj + 0.5 * a * a * C;   // q(Delta + a p) - q(Delta)
     // argmin over lanes, the smallest index on ties
     double best = phi;
     int bj = j;
@@ -391,7 +404,7 @@ int64_t launch_pcd(int64_t nc, int jp, int b, const int64_t* cptr, const int32_t
                            wk.d[nx].p, wk.p[cur].p, wk.p[nx].p, wk.pdiag.p, wk.Y.p, wk.sc.p);
         hipLaunchKernelGGL(k_pcd_zp, dim3(zgrid), dim3(PT), 0, s, nc, jp, b, c_p, c_ci, c_S, c_A,
                            c_wtc, WJJ, wk.Y.p, wk.pdiag.p, wk.p[nx].p, delta, wk.z.p,
-                           wk.zp[nx].p, wk.sc.p, wk.part.p);
+                           wk.zp[nx].p, wk.sc.p, lam, wk.part.p);
         hipLaunchKernelGGL(k_pcd_alpha, dim3(1), dim3(64), 0, s, zgrid, wk.part.p, lam, wk.sc.p);
         SIC_CHECK_LAUNCH();
         cur = nx;

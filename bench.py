@@ -8,9 +8,14 @@ libsic.so, run for the number of multilevel cycles c* after which the iterate's
 exact objective is within 1e-6 (relative) of F*; c* comes from an untimed
 calibration solve to KKT <= 1e-6 and is verified afterwards with an exact
 dense float64 objective of the returned iterate. X is resident in HBM before
-the timed region. Prints one JSON line.
+the timed region.
 
-    python bench.py [--gpus 1] [--steps 2] [--warmup 1]
+The second half of the metric (served solves/s with p50/p99 latency) comes
+from the serving loop on the first --serve-requests requests of the seeded
+256-request stream (see serving_leg); --serve-only runs that leg alone, e.g.
+on the whole stream. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--serve-requests 16]
 """
 
 from __future__ import annotations
@@ -105,6 +110,80 @@ def cpu_baseline(name, X, lam, golden, budget_s):
                 higher_is_better=False)
 
 
+def serving_leg(sic, torch, count, slots, tol):
+    """Served solves/s and p50/p99 latency on the request stream.
+
+    The stream is the serving workload's generator (Poisson arrivals; n
+    uniform in [500, 8000]; chain, grid or random graph; m = n/2; lambda
+    uniform in [0.05, 0.5]), its first ``count`` requests, with the samples
+    drawn on the device beforehand. The plain path solves them one after
+    another on one context; the server then receives them at Poisson arrival
+    times with rate 0.8 x the plain path's throughput, and once more all at
+    time 0 (burst). Latency is completion minus arrival on the server's clock.
+    """
+    from synth.device import request_samples_device
+    from synth.generators import request_stream
+    reqs = request_stream(256, seed=4, rate=1.0)[:count]
+    t = time.perf_counter()
+    Xs = [request_samples_device(r, "cuda:0")[0] for r in reqs]
+    torch.cuda.synchronize()
+    log(f"serving: {count} requests drawn on the device in {time.perf_counter()-t:.1f}s "
+        f"(n {min(r['n'] for r in reqs)}..{max(r['n'] for r in reqs)})")
+    probs = [dict(X=X, lam=r["lam"], tol=tol) for r, X in zip(reqs, Xs)]
+    solo_t, solo_res = [], []
+    with sic.Context() as c:
+        for k, p in enumerate(probs):
+            t = time.perf_counter()
+            code, res = c.solve_batch([p])
+            solo_t.append(time.perf_counter() - t)
+            solo_res.append(res[0])
+            log(f"  plain {k}: {reqs[k]['kind']} n={reqs[k]['n']} lam={reqs[k]['lam']:.3f} "
+                f"{solo_t[-1]:.2f}s status {code}")
+    seq_rate = count / sum(solo_t)
+    rate = 0.8 * seq_rate
+    arrive = np.array([r["t"] for r in reqs]) / rate   # the stream's gaps at rate 1, rescaled
+
+    def same(a, b):
+        (rp1, c1, v1), i1 = a
+        (rp2, c2, v2), i2 = b
+        return (np.array_equal(rp1, rp2) and np.array_equal(c1, c2)
+                and np.max(np.abs(v1 - v2)) <= 1e-12 * max(1.0, np.max(np.abs(v1))))
+
+    def serve(times):
+        with sic.Server(slots=slots) as srv:
+            t0 = time.perf_counter()
+            tickets = []
+            for k, p in enumerate(probs):
+                delay = t0 + times[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append(srv.submit(p))
+            out = []
+            for k, tk in enumerate(tickets):
+                out.append(srv.wait(tk))
+                log(f"  served {k}: latency {out[-1][3]['finished'] - out[-1][3]['submitted']:.2f}s")
+        lat = np.array([o[3]["finished"] - o[3]["submitted"] for o in out])
+        span = max(o[3]["finished"] for o in out) - min(o[3]["submitted"] for o in out)
+        ok = all(o[0] == 0 for o in out)
+        ident = all(same((o[1][0], o[2][0]), s) for o, s in zip(out, solo_res))
+        kkt = max(o[2][0]["kkt_max"] for o in out)
+        return dict(solves_per_s=count / span, p50_s=float(np.percentile(lat, 50)),
+                    p99_s=float(np.percentile(lat, 99)), all_converged=ok,
+                    identical_to_plain=ident, max_kkt=kkt)
+
+    log(f"serving: Poisson arrivals at {rate:.3f}/s ({slots} slots)")
+    poisson = serve(arrive)
+    log("serving: burst")
+    burst = serve(np.zeros(count))
+    del Xs, probs
+    torch.cuda.empty_cache()
+    return dict(requests=count, of_stream=256, slots=slots, tol_kkt=tol,
+                arrival_rate_per_s=rate, plain_sequential_solves_per_s=seq_rate,
+                plain_p50_s=float(np.percentile(solo_t, 50)),
+                plain_p99_s=float(np.percentile(solo_t, 99)),
+                poisson=poisson, burst=burst)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +196,11 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--cd-max-sweeps", type=int, default=0, help="0: library default")
     ap.add_argument("--cd-tol", type=float, default=0.0, help="0: library default")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="first requests of the 256-request serving stream (0: no serving leg)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-tol", type=float, default=1e-6)
+    ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--cycles", type=int, default=0,
                     help="skip the calibration solve and run this many cycles per step "
                          "(the exact gap is still measured and reported)")
@@ -133,6 +217,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serve_only:
+        out = serving_leg(sic, torch, args.serve_requests, args.serve_slots, args.serve_tol)
+        print(json.dumps(dict(metric="served solves/s + p50/p99 (s)", n_gpus=1, data="synthetic",
+                              dtype="f64", serving=out)), flush=True)
+        return
     name = args.workload
     gpath = os.path.join(ROOT, "tests", "golden", f"{name}.json")
     with open(gpath) as f:
@@ -222,6 +311,9 @@ def main():
         # the full profile of the timed region, per kernel class
         for kname, kv in kern.items():
             kv["avg_ms"] = kv["ms"] / kv["launches"] if kv["launches"] else None
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(sic, torch, args.serve_requests, args.serve_slots, args.serve_tol)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(name, X, lam, golden, args.cpu_sample_seconds)
@@ -235,7 +327,7 @@ def main():
         gap=gap, F_star=Fstar, support_identical_at_gap=bool(np.array_equal(keys, gkeys)),
         support_identical_at_kkt=sup_kkt,
         nnz=int(col.size), time_to_kkt_1e6_s=t_kkt, kkt_cycles=info["cycles"],
-        kkt_max=info["kkt_max"], roofline=roofline, cpu_baseline=cpu,
+        kkt_max=info["kkt_max"], roofline=roofline, cpu_baseline=cpu, serving=serving,
         kernels={k: dict(launches=v["launches"], ms=round(v["ms"], 3),
                          avg_ms=v["avg_ms"], GBps=(v["bytes"] / (v["ms"] * 1e-3) / 1e9)
                          if v["ms"] > 0 and v["bytes"] > 0 else None)

@@ -201,6 +201,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-tol", type=float, default=1e-6)
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--cycles", type=int, default=0,
                     help="skip the calibration solve and run this many cycles per step "
                          "(the exact gap is still measured and reported)")
@@ -241,56 +242,71 @@ def main():
         solver_opts["cd_max_sweeps"] = args.cd_max_sweeps
     if args.cd_tol:
         solver_opts["cd_tol"] = args.cd_tol
-    ctx = sic.Context(trace_cap=256, **solver_opts)
-    t_kkt = sup_kkt = None
-    info = {"cycles": None, "kkt_max": None}
-    if args.cycles > 0:
-        cstar = args.cycles
-        ctx_c = sic.Context(max_cycles=cstar, **solver_opts)
-    else:
-        # calibration: solve to KKT <= 1e-6, cycle trace of the tracked objective
-        t = time.perf_counter()
-        (rp, col, val), info, trace = ctx.solve(Xd, lam, 1e-6)
-        t_kkt = time.perf_counter() - t
-        F_final = exact_objective(rp, col, val, Xd, lam)
-        sup_kkt = bool(np.array_equal(support_keys(rp, col), gkeys))
-        drift = abs(info["objective"] - F_final)
-        log(f"calibration: {info['cycles']} cycles, {t_kkt:.2f}s to KKT {info['kkt_max']:.2e}, "
-            f"F exact {F_final:.12e} (F* {Fstar:.12e}), tracked drift {drift:.2e}")
-        cstar = len(trace)
-        for e in trace:
-            if (e["objective"] - Fstar + drift) / abs(Fstar) <= GAP:
-                cstar = e["cycle"] + 1
-                break
-        # verify c* with the exact objective of the iterate after c* cycles
-        while True:
-            ctx_c = sic.Context(max_cycles=cstar, **solver_opts)
-            (rp, col, val), info_c, _ = ctx_c.solve(Xd, lam, 1e-12)
-            gap = (exact_objective(rp, col, val, Xd, lam) - Fstar) / abs(Fstar)
-            log(f"c*={cstar}: exact gap {gap:.3e}")
-            if gap <= GAP or cstar >= info["cycles"] + 5:
-                break
-            ctx_c.close()
-            cstar += 1
-    for _ in range(args.warmup):
-        ctx_c.solve(Xd, lam, 1e-12)
-    if not args.no_kernel_timing:
-        sic.profile_reset()
-        sic.profile_enable(True)
-    times = []
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        (rp, col, val), info_s, _ = ctx_c.solve(Xd, lam, 1e-12)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t)
-    kern = sic.profile_read() if not args.no_kernel_timing else {}
-    sic.profile_enable(False)
-    gap = (exact_objective(rp, col, val, Xd, lam) - Fstar) / abs(Fstar)
-    keys = support_keys(rp, col)
-    value = float(np.mean(times))
-    log(f"timed: {['%.3f' % x for x in times]} s, gap {gap:.3e}, nnz {col.size}")
 
+    def time_to_gap(precision, profile):
+        """Calibrate c* (solve to KKT 1e-6, verify the exact gap after c*
+        cycles), then time `steps` solves of c* cycles."""
+        opts = dict(solver_opts, precision=precision)
+        t_kkt = sup_kkt = None
+        info = {"cycles": None, "kkt_max": None}
+        if args.cycles > 0:
+            cstar = args.cycles
+        else:
+            with sic.Context(trace_cap=256, **opts) as ctx:
+                t = time.perf_counter()
+                (rp, col, val), info, trace = ctx.solve(Xd, lam, 1e-6)
+                t_kkt = time.perf_counter() - t
+            F_final = exact_objective(rp, col, val, Xd, lam)
+            sup_kkt = bool(np.array_equal(support_keys(rp, col), gkeys))
+            drift = abs(info["objective"] - F_final)
+            log(f"[prec {precision}] calibration: {info['cycles']} cycles, {t_kkt:.2f}s to KKT "
+                f"{info['kkt_max']:.2e}, F exact {F_final:.12e} (F* {Fstar:.12e}), drift {drift:.2e}")
+            cstar = len(trace)
+            for e in trace:
+                if (e["objective"] - Fstar + drift) / abs(Fstar) <= GAP:
+                    cstar = e["cycle"] + 1
+                    break
+            while True:
+                with sic.Context(max_cycles=cstar, **opts) as ctx_c:
+                    (rp, col, val), _, _ = ctx_c.solve(Xd, lam, 1e-12)
+                gap = (exact_objective(rp, col, val, Xd, lam) - Fstar) / abs(Fstar)
+                log(f"[prec {precision}] c*={cstar}: exact gap {gap:.3e}")
+                if gap <= GAP or cstar >= info["cycles"] + 5:
+                    break
+                cstar += 1
+        ctx_c = sic.Context(max_cycles=cstar, **opts)
+        for _ in range(args.warmup):
+            ctx_c.solve(Xd, lam, 1e-12)
+        if profile:
+            sic.profile_reset()
+            sic.profile_enable(True)
+        times = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            (rp, col, val), _, _ = ctx_c.solve(Xd, lam, 1e-12)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        kern = sic.profile_read() if profile else {}
+        sic.profile_enable(False)
+        ctx_c.close()
+        gap = (exact_objective(rp, col, val, Xd, lam) - Fstar) / abs(Fstar)
+        keys = support_keys(rp, col)
+        log(f"[prec {precision}] timed: {['%.3f' % x for x in times]} s, gap {gap:.3e}, nnz {col.size}")
+        return dict(value=float(np.mean(times)), cycles=cstar, gap=gap,
+                    support_identical_at_gap=bool(np.array_equal(keys, gkeys)),
+                    support_identical_at_kkt=sup_kkt, nnz=int(col.size), time_to_kkt_1e6_s=t_kkt,
+                    kkt_cycles=info["cycles"], kkt_max=info["kkt_max"]), kern
+
+    res64, kern = time_to_gap(sic.SIC_FP64, not args.no_kernel_timing)
+    value, cstar, gap = res64["value"], res64["cycles"], res64["gap"]
+    mixed = None
+    if not args.no_mixed:
+        mixed, _ = time_to_gap(sic.SIC_MIXED, False)
+        mixed["speedup_vs_f64"] = value / mixed["value"]
+        mixed["schedule"] = ("bf16 S_J and float CG while the KKT measure > 1e-2, float S_J and "
+                             "float CG while > 1e-4, float64 after; float64 S at the coordinates, "
+                             "Cholesky / log det and KKT throughout")
     roofline = None
     if kern:
         total = sum(k["ms"] for k in kern.values())
@@ -324,17 +340,16 @@ def main():
         config=dict(workload=name, graph=spec["kind"], n=int(X.shape[1]), m=int(X.shape[0]),
                     **{"lambda": lam}, block=b, cycles=cstar, x_layout="m x n row-major f64",
                     cd_max_sweeps=args.cd_max_sweeps or 20, cd_tol=args.cd_tol or 1e-4),
-        gap=gap, F_star=Fstar, support_identical_at_gap=bool(np.array_equal(keys, gkeys)),
-        support_identical_at_kkt=sup_kkt,
-        nnz=int(col.size), time_to_kkt_1e6_s=t_kkt, kkt_cycles=info["cycles"],
-        kkt_max=info["kkt_max"], roofline=roofline, cpu_baseline=cpu, serving=serving,
+        gap=gap, F_star=Fstar, support_identical_at_gap=res64["support_identical_at_gap"],
+        support_identical_at_kkt=res64["support_identical_at_kkt"],
+        nnz=res64["nnz"], time_to_kkt_1e6_s=res64["time_to_kkt_1e6_s"],
+        kkt_cycles=res64["kkt_cycles"], kkt_max=res64["kkt_max"], mixed=mixed,
+        roofline=roofline, cpu_baseline=cpu, serving=serving,
         kernels={k: dict(launches=v["launches"], ms=round(v["ms"], 3),
                          avg_ms=v["avg_ms"], GBps=(v["bytes"] / (v["ms"] * 1e-3) / 1e9)
                          if v["ms"] > 0 and v["bytes"] > 0 else None)
                  for k, v in kern.items()} if kern else None,
     )
-    ctx_c.close()
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -23,8 +23,10 @@ extern "C" {
  *   4 screen_fine  free-set screening            9 cd_hess      coordinate Hessian
  *                                                               (explicit-Hessian CD)
  *                                               10 trsm         triangular solves
- *                                               11 pcd          PCD-CG Newton direction */
-#define SIC_KERNEL_CLASSES 12
+ *                                               11 pcd          PCD-CG Newton direction
+ *                                               12 sj_gemm_f32  S_J from float X (mixed precision)
+ *                                               13 sj_gemm_bf16 S_J from bfloat16 X (mixed precision) */
+#define SIC_KERNEL_CLASSES 14
 
 void sic_profile_enable(int on);      /* on != 0 starts timing, 0 stops it */
 void sic_profile_reset(void);         /* zero every counter */

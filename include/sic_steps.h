@@ -37,6 +37,12 @@ double sic_prob_objective(sic_prob* p);
  * kept, S implicit). out: n x b row-major host array. */
 int sic_step_cov_block(sic_prob* p, int64_t j0, int b, double* out);
 
+/* (a, mixed precision) The same block from X narrowed to x_dtype (SIC_X_F32:
+ * float; SIC_X_BF16: bfloat16, round to nearest even) with float
+ * accumulation on the matrix cores, widened to float64. out as above.
+ * SIC_EINVAL for another dtype or a bad range. */
+int sic_step_cov_block_low(sic_prob* p, int64_t j0, int b, int x_dtype, double* out);
+
 /* (a, coarse levels) Sampled covariance entries S_{r_t c_t} for `count`
  * pairs (Section 7: only entries in C_l are needed). out: count doubles. */
 int sic_step_cov_pairs(sic_prob* p, const int32_t* rows, const int32_t* cols, int64_t count,

@@ -284,6 +284,30 @@ int sic_step_cov_block(sic_prob* p, int64_t j0, int b, double* out) {
     });
 }
 
+int sic_step_cov_block_low(sic_prob* p, int64_t j0, int b, int x_dtype, double* out) {
+    if (!p || !out || j0 < 0 || b < 1 || j0 + b > p->P.n ||
+        (x_dtype != SIC_X_F32 && x_dtype != SIC_X_BF16))
+        return SIC_EINVAL;
+    return guard([&]() {
+        sic::Context& C = p->ctx->c;
+        sic::AccountScope scope(C.acct);
+        const size_t count = (size_t)p->P.n * p->P.m;
+        sic::DevBuf<float> xf;
+        sic::DevBuf<uint16_t> xb;
+        if (x_dtype == SIC_X_F32) xf.reserve(count); else xb.reserve(count);
+        sic::launch_narrow(p->P.X.p, (int64_t)count, x_dtype == SIC_X_F32 ? xf.p : nullptr,
+                           x_dtype == SIC_X_BF16 ? xb.p : nullptr, C.stream);
+        C.work.SJ.reserve((size_t)p->P.n * b);
+        sic::launch_sj_gemm_low(x_dtype == SIC_X_BF16 ? (const void*)xb.p : (const void*)xf.p,
+                                x_dtype == SIC_X_BF16, p->P.n, p->P.m, j0, b, C.work.SJ.p,
+                                C.stream);
+        SIC_HIP(hipMemcpyAsync(out, C.work.SJ.p, sizeof(double) * p->P.n * b,
+                               hipMemcpyDeviceToHost, C.stream));
+        SIC_HIP(hipStreamSynchronize(C.stream));
+        return SIC_OK;
+    });
+}
+
 int sic_step_cov_pairs(sic_prob* p, const int32_t* rows, const int32_t* cols, int64_t count,
                        double* out) {
     if (!p || count < 0 || (count > 0 && (!rows || !cols || !out))) return SIC_EINVAL;

@@ -40,15 +40,16 @@ __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __r
     dinv[i] = d > 0.0 ? 1.0 / d : 1.0;
 }
 
+template <typename V>
 __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __restrict__ cols,
-                          const double* __restrict__ dinv, double* __restrict__ R,
-                          double* __restrict__ Z, double* __restrict__ scal,
+                          const double* __restrict__ dinv, V* __restrict__ R,
+                          V* __restrict__ Z, double* __restrict__ scal,
                           int* __restrict__ tctl, double* __restrict__ tres) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < k) {
         const int64_t c = cols[j];
-        R[c * k + j] = 1.0;
-        Z[c * k + j] = dinv[c];
+        R[c * k + j] = (V)1.0;
+        Z[c * k + j] = (V)dinv[c];
         scal[j * 4 + S_RZ] = dinv[c];
         scal[j * 4 + S_ALPHA] = 0.0;
         scal[j * 4 + S_BETA] = 0.0;
@@ -63,10 +64,11 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+template <typename V>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, int64_t n, int k, const double* __restrict__ Z,
-    double* __restrict__ P, double* __restrict__ Q, const double* __restrict__ scal,
+    const double* __restrict__ val, int64_t n, int k, const V* __restrict__ Z,
+    V* __restrict__ P, V* __restrict__ Q, const double* __restrict__ scal,
     double* __restrict__ part, const int* __restrict__ tctl, int gx, int gy, int xcd_grouped) {
     // Tile (tx = 64-column tile, ty = row partition). Grouped: a 1-D grid whose
     // workgroup L runs on XCD L % 8 (round-robin dispatch); every row partition
@@ -103,20 +105,20 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 av[u] = val[e + u];
-                zv[u] = Z[(int64_t)col[e + u] * k + jj];
+                zv[u] = (double)Z[(int64_t)col[e + u] * k + jj];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc += av[u] * zv[u];
         }
-        for (; e < e1; ++e) acc += val[e] * Z[(int64_t)col[e] * k + jj];
+        for (; e < e1; ++e) acc += val[e] * (double)Z[(int64_t)col[e] * k + jj];
         if (jok) {
             const int64_t o = i * k + j;
-            const double z = Z[o];
-            const double p = first ? z : z + beta * P[o];
-            const double q = first ? acc : acc + beta * Q[o];
+            const double z = (double)Z[o];
+            const V p = (V)(first ? z : z + beta * (double)P[o]);
+            const V q = (V)(first ? acc : acc + beta * (double)Q[o]);
             P[o] = p;
             Q[o] = q;
-            pq += p * q;
+            pq += (double)p * (double)q;
         }
     }
     __shared__ double red[CG_WAVES][64];
@@ -150,10 +152,11 @@ __global__ __launch_bounds__(256) void k_cg_fin_alpha(int k, int row_tiles,
     }
 }
 
+template <typename V>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     int64_t n, int k, const double* __restrict__ dinv, double* __restrict__ W,
-    double* __restrict__ R, double* __restrict__ Z, const double* __restrict__ P,
-    const double* __restrict__ Q, const double* __restrict__ scal, double* __restrict__ part,
+    V* __restrict__ R, V* __restrict__ Z, const V* __restrict__ P,
+    const V* __restrict__ Q, const double* __restrict__ scal, double* __restrict__ part,
     const int* __restrict__ tctl) {
     if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
     const int lane = threadIdx.x & 63;
@@ -166,13 +169,75 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
         for (int64_t i = (int64_t)blockIdx.y * CG_WAVES + wave; i < n;
              i += (int64_t)gridDim.y * CG_WAVES) {
             const int64_t o = i * k + j;
-            W[o] += alpha * P[o];
-            const double r = R[o] - alpha * Q[o];
+            W[o] += alpha * (double)P[o];
+            const V r = (V)((double)R[o] - alpha * (double)Q[o]);
             R[o] = r;
-            const double z = dinv[i] * r;
+            const V z = (V)(dinv[i] * (double)r);
             Z[o] = z;
-            rz += r * z;
-            rr += r * r;
+            rz += (double)r * (double)z;
+            rr += (double)r * (double)r;
+        }
+    }
+    __shared__ double red[2][CG_WAVES][64];
+    red[0][wave][lane] = rz;
+    red[1][wave][lane] = rr;
+    __syncthreads();
+    if (wave == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int w = 0; w < CG_WAVES; ++w) {
+            s0 += red[0][w][lane];
+            s1 += red[1][w][lane];
+        }
+        if (jok) {
+            part[((int64_t)blockIdx.y * k + j) * 2 + 0] = s0;
+            part[((int64_t)blockIdx.y * k + j) * 2 + 1] = s1;
+        }
+    }
+}
+
+// Residual replacement for float vectors: r = e_j - A x from the float64
+// iterate x (W), in float64, then z = D^{-1} r, with the same partial sums as
+// the update. The recursively updated float residual drifts from the true
+// one; replacing it every few iterations keeps the convergence test honest.
+template <typename V>
+__global__ __launch_bounds__(CG_THREADS) void k_cg_true_residual(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, int64_t n, int k, const int32_t* __restrict__ cols,
+    const double* __restrict__ dinv, const double* __restrict__ W, V* __restrict__ R,
+    V* __restrict__ Z, double* __restrict__ part, const int* __restrict__ tctl) {
+    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_id();
+    const int j = blockIdx.x * 64 + lane;
+    const bool jok = j < k;
+    const int jj = jok ? j : k - 1;
+    const int64_t cj = cols[jj];
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.y * CG_WAVES + wave; i < n;
+         i += (int64_t)gridDim.y * CG_WAVES) {
+        const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+        double acc = 0.0;
+        int64_t e = e0;
+        for (; e + 8 <= e1; e += 8) {
+            double wv[8], av[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                av[u] = val[e + u];
+                wv[u] = W[(int64_t)col[e + u] * k + jj];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += av[u] * wv[u];
+        }
+        for (; e < e1; ++e) acc += val[e] * W[(int64_t)col[e] * k + jj];
+        if (jok) {
+            const int64_t o = i * k + j;
+            const double r = (i == cj ? 1.0 : 0.0) - acc;
+            const V rv = (V)r;
+            const V zv = (V)(dinv[i] * (double)rv);
+            R[o] = rv;
+            Z[o] = zv;
+            rz += (double)rv * (double)zv;
+            rr += (double)rv * (double)rv;
         }
     }
     __shared__ double red[2][CG_WAVES][64];
@@ -235,8 +300,15 @@ __global__ __launch_bounds__(256) void k_cg_fin_beta(int k, int row_tiles,
 
 }  // namespace
 
-CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
-                  double tol, int max_iter, CGWork& wk, hipStream_t s) {
+namespace {
+
+constexpr int CG_REPLACE_EVERY = 8;   // float vectors: true residual every this many iterations
+
+template <typename V>
+CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
+                       double tol, int max_iter, CGWork& wk, V* R, V* Z, V* P, V* Q,
+                       hipStream_t s) {
+    constexpr bool LOW = sizeof(V) < sizeof(double);
     CGResult res;
     const int64_t n = A.n;
     if (k <= 0) {
@@ -245,10 +317,6 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
     }
     if (ldw != k) throw SicError(SIC_EINTERNAL, "block_cg expects ldw == k");
     const size_t nk = (size_t)n * (size_t)k;
-    wk.R.reserve(nk);
-    wk.Z.reserve(nk);
-    wk.P.reserve(nk);
-    wk.Q.reserve(nk);
     wk.dinv.reserve(n);
     const int col_tiles = (k + 63) / 64;
     int row_tiles = (int)std::min<int64_t>(CG_ROW_TILES, (n + CG_WAVES - 1) / CG_WAVES);
@@ -258,14 +326,14 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
     wk.flags.reserve((size_t)T_INTS * col_tiles);
     double* tres = wk.scal.p + 4 * k;
     SIC_HIP(hipMemsetAsync(W, 0, nk * sizeof(double), s));
-    SIC_HIP(hipMemsetAsync(wk.R.p, 0, nk * sizeof(double), s));
-    SIC_HIP(hipMemsetAsync(wk.Z.p, 0, nk * sizeof(double), s));
+    SIC_HIP(hipMemsetAsync(R, 0, nk * sizeof(V), s));
+    SIC_HIP(hipMemsetAsync(Z, 0, nk * sizeof(V), s));
     hipLaunchKernelGGL(k_cg_dinv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        A.rowptr.p, A.col.p, A.val.p, n, wk.dinv.p);
     SIC_CHECK_LAUNCH();
     const int init_n = std::max(k, col_tiles);
-    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0, s, n, k,
-                       col_tiles, d_cols, wk.dinv.p, wk.R.p, wk.Z.p, wk.scal.p, wk.flags.p, tres);
+    hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0, s, n,
+                       k, col_tiles, d_cols, wk.dinv.p, R, Z, wk.scal.p, wk.flags.p, tres);
     SIC_CHECK_LAUNCH();
     dim3 grid(col_tiles, row_tiles);
     // XCD grouping of the product's tiles once there are enough column tiles to
@@ -290,13 +358,13 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
         recs.clear();
         for (int c = 0; c < chunk; ++c) {
             const int it = launched + c;
-            const double nkb = (double)n * k * 8.0;
+            const double nkb = (double)n * k * sizeof(V);
             Rec r;
             r.iter = it;
             prof_begin(KK_CG_SPMM, s);
-            hipLaunchKernelGGL(k_cg_spmm, sgrid, dim3(CG_THREADS), 0, s, A.rowptr.p, A.col.p,
-                               A.val.p, n, k, wk.Z.p, wk.P.p, wk.Q.p, wk.scal.p, wk.part.p,
-                               wk.flags.p, col_tiles, row_tiles, grouped);
+            hipLaunchKernelGGL(k_cg_spmm<V>, sgrid, dim3(CG_THREADS), 0, s, A.rowptr.p, A.col.p,
+                               A.val.p, n, k, Z, P, Q, wk.scal.p, wk.part.p, wk.flags.p,
+                               col_tiles, row_tiles, grouped);
             SIC_CHECK_LAUNCH();
             r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
                               2.0 * A.nnz * k + 4.0 * n * k);
@@ -304,10 +372,16 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
                                wk.part.p, wk.scal.p, wk.flags.p);
             SIC_CHECK_LAUNCH();
             prof_begin(KK_CG_UPDATE, s);
-            hipLaunchKernelGGL(k_cg_update, grid, dim3(CG_THREADS), 0, s, n, k, wk.dinv.p, W,
-                               wk.R.p, wk.Z.p, wk.P.p, wk.Q.p, wk.scal.p, wk.part.p, wk.flags.p);
+            hipLaunchKernelGGL(k_cg_update<V>, grid, dim3(CG_THREADS), 0, s, n, k, wk.dinv.p, W, R,
+                               Z, P, Q, wk.scal.p, wk.part.p, wk.flags.p);
             SIC_CHECK_LAUNCH();
-            r.upd = prof_end(KK_CG_UPDATE, s, 7.0 * nkb + n * 8.0, 10.0 * n * k);
+            r.upd = prof_end(KK_CG_UPDATE, s, 5.0 * nkb + 16.0 * n * k + n * 8.0, 10.0 * n * k);
+            if (LOW && (it + 1) % CG_REPLACE_EVERY == 0) {
+                hipLaunchKernelGGL(k_cg_true_residual<V>, grid, dim3(CG_THREADS), 0, s, A.rowptr.p,
+                                   A.col.p, A.val.p, n, k, d_cols, wk.dinv.p, W, R, Z, wk.part.p,
+                                   wk.flags.p);
+                SIC_CHECK_LAUNCH();
+            }
             hipLaunchKernelGGL(k_cg_fin_beta, dim3(col_tiles), dim3(256), 0, s, k, row_tiles,
                                wk.part.p, wk.scal.p, wk.flags.p, tres, tol);
             SIC_CHECK_LAUNCH();
@@ -352,6 +426,27 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
     res.converged = done;
     res.max_rel_res = mres;
     return res;
+}
+
+}  // namespace
+
+CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
+                  double tol, int max_iter, CGWork& wk, hipStream_t s, bool low_precision) {
+    const size_t nk = (size_t)A.n * (size_t)std::max(k, 1);
+    if (low_precision) {
+        wk.R32.reserve(nk);
+        wk.Z32.reserve(nk);
+        wk.P32.reserve(nk);
+        wk.Q32.reserve(nk);
+        return block_cg_impl<float>(A, d_cols, k, W, ldw, tol, max_iter, wk, wk.R32.p, wk.Z32.p,
+                                    wk.P32.p, wk.Q32.p, s);
+    }
+    wk.R.reserve(nk);
+    wk.Z.reserve(nk);
+    wk.P.reserve(nk);
+    wk.Q.reserve(nk);
+    return block_cg_impl<double>(A, d_cols, k, W, ldw, tol, max_iter, wk, wk.R.p, wk.Z.p, wk.P.p,
+                                 wk.Q.p, s);
 }
 
 }  // namespace sic

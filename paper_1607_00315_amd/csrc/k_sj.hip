@@ -10,6 +10,8 @@
 // products over rows of the transposed copy Xt (n x m row-major).
 #include "profiler.h"
 
+#include <type_traits>
+
 namespace sic {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -83,6 +85,122 @@ __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ 
             }
 }
 
+// Reduced-precision S_J (the mixed-precision path): the same 64 x 64 tiles,
+// float accumulation on MFMA, the result scaled and widened to float64.
+//   float X:    v_mfma_f32_16x16x4f32, operands A[l%16][l/16], B[l/16][l%16]
+//   bfloat16 X: v_mfma_f32_16x16x16bf16_1k, A[l%16][4(l/16)+q], B[4(l/16)+q][l%16]
+// both with the result in D[4(l/16)+v][l%16] (checked with a lane-layout probe).
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
+constexpr int SJR_KC = 32;    // samples staged per LDS round
+constexpr int SJR_PAD = 4;
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_sj_gemm_low(const void* __restrict__ Xv, int64_t n,
+                                                     int64_t m, int64_t j0, int b,
+                                                     double* __restrict__ out, double invm) {
+    typedef typename std::conditional<BF16, unsigned short, float>::type E;
+    const E* __restrict__ X = (const E*)Xv;
+    __shared__ E sA[SJR_KC][SJ_TILE + SJR_PAD];
+    __shared__ E sB[SJR_KC][SJ_TILE + SJR_PAD];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int64_t i0 = (int64_t)blockIdx.x * SJ_TILE;
+    const int c0 = blockIdx.y * SJ_TILE;
+    // loader: 32 rows x 64 columns, 8 consecutive elements per thread
+    const int lr = tid >> 3;          // 0..31
+    const int lc = (tid & 7) * 8;     // 0..56
+    float4_t acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb) acc[a][bb] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    for (int64_t r0 = 0; r0 < m; r0 += SJR_KC) {
+        const int64_t r = r0 + lr;
+        const bool rok = r < m;
+        const E* xrow = X + (rok ? r : 0) * n;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t ia = i0 + lc + q;
+            const int cb = c0 + lc + q;
+            const E va = xrow[(rok && ia < n) ? ia : 0];
+            const E vb = xrow[(rok && cb < b) ? j0 + cb : 0];
+            sA[lr][lc + q] = (rok && ia < n) ? va : (E)0;
+            sB[lr][lc + q] = (rok && cb < b) ? vb : (E)0;
+        }
+        __syncthreads();
+        if constexpr (BF16) {
+#pragma unroll
+            for (int kk = 0; kk < SJR_KC; kk += 16) {
+                const int kr = kk + 4 * (lane >> 4);
+                short4_t av[2], bv[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        av[a][q] = (short)sA[kr + q][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        bv[bb][q] = (short)sB[kr + q][wc * 32 + bb * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < 2; ++bb)
+                        acc[a][bb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[bb],
+                                                                              acc[a][bb], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < SJR_KC; kk += 4) {
+                const int kr = kk + (lane >> 4);
+                float av[2], bv[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) av[a] = sA[kr][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) bv[bb] = sB[kr][wc * 32 + bb * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < 2; ++bb)
+                        acc[a][bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[bb], acc[a][bb],
+                                                                          0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + v;
+                const int c = c0 + wc * 32 + bb * 16 + (lane & 15);
+                if (i < n && c < b) out[i * b + c] = (double)acc[a][bb][v] * invm;
+            }
+}
+
+// float64 -> float (round to nearest) and -> bfloat16 (round to nearest even)
+__global__ void k_narrow(const double* __restrict__ X, int64_t count, float* __restrict__ xf,
+                         unsigned short* __restrict__ xb) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const float f = (float)X[t];
+    if (xf) xf[t] = f;
+    if (xb) {
+        unsigned u = __float_as_uint(f);
+        if ((u & 0x7f800000u) == 0x7f800000u) {
+            xb[t] = (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));   // inf / nan
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            xb[t] = (unsigned short)(u >> 16);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X, int64_t m, int64_t n,
                                                    double* __restrict__ Xt) {
     __shared__ double tile[32][33];
@@ -142,6 +260,28 @@ void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b
     SIC_CHECK_LAUNCH();
     // algorithmic: X read once (m x n) and S_J written once; 2 n b m flops
     prof_end(KK_SJ, s, 8.0 * ((double)m * n + (double)n * b), 2.0 * (double)n * b * m);
+}
+
+void launch_sj_gemm_low(const void* X, bool bf16, int64_t n, int64_t m, int64_t j0, int b,
+                        double* out, hipStream_t s) {
+    dim3 grid((unsigned)((n + SJ_TILE - 1) / SJ_TILE), (unsigned)((b + SJ_TILE - 1) / SJ_TILE));
+    const double esz = bf16 ? 2.0 : 4.0;
+    prof_begin(bf16 ? KK_SJ_BF16 : KK_SJ_F32, s);
+    if (bf16)
+        hipLaunchKernelGGL(k_sj_gemm_low<true>, grid, dim3(256), 0, s, X, n, m, j0, b, out,
+                           1.0 / (double)m);
+    else
+        hipLaunchKernelGGL(k_sj_gemm_low<false>, grid, dim3(256), 0, s, X, n, m, j0, b, out,
+                           1.0 / (double)m);
+    SIC_CHECK_LAUNCH();
+    prof_end(bf16 ? KK_SJ_BF16 : KK_SJ_F32, s, esz * (double)m * n + 8.0 * (double)n * b,
+             2.0 * (double)n * b * m);
+}
+
+void launch_narrow(const double* X, int64_t count, float* xf, uint16_t* xb, hipStream_t s) {
+    hipLaunchKernelGGL(k_narrow, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, X, count,
+                       xf, (unsigned short*)xb);
+    SIC_CHECK_LAUNCH();
 }
 
 void launch_transpose(const double* X, int64_t m, int64_t n, double* Xt, hipStream_t s) {

@@ -110,4 +110,24 @@ void launch_iota_i32(int32_t* p, int64_t count, int32_t start, hipStream_t s) {
     SIC_CHECK_LAUNCH();
 }
 
+
+namespace {
+__global__ void k_coord_globals(int64_t nc, const int32_t* __restrict__ c_p,
+                                const int32_t* __restrict__ c_ci, const int32_t* __restrict__ Jp,
+                                int64_t j0, int32_t* __restrict__ gr, int32_t* __restrict__ gc) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc) return;
+    gr[t] = Jp[c_p[t]];
+    gc[t] = (int32_t)(j0 + c_ci[t]);
+}
+}  // namespace
+
+void launch_coord_globals(int64_t nc, const int32_t* c_p, const int32_t* c_ci, const int32_t* Jp,
+                          int64_t j0, int32_t* gr, int32_t* gc, hipStream_t s) {
+    if (nc <= 0) return;
+    hipLaunchKernelGGL(k_coord_globals, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc,
+                       c_p, c_ci, Jp, j0, gr, gc);
+    SIC_CHECK_LAUNCH();
+}
+
 }  // namespace sic

@@ -18,6 +18,8 @@ enum KernelKind {
     KK_CD_HESS,
     KK_TRSM,
     KK_PCD,
+    KK_SJ_F32,
+    KK_SJ_BF16,
     KK_COUNT
 };
 

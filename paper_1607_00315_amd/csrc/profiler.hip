@@ -65,7 +65,7 @@ void resolve() {
 const char* kernel_kind_name(int kind) {
     static const char* names[KK_COUNT] = {"sj_gemm_f64", "sddmm", "cg_spmm", "cg_update",
                                           "screen_fine", "cd", "chol", "gemm_small", "upd_rows", "cd_hess",
-                                          "trsm", "pcd"};
+                                          "trsm", "pcd", "sj_gemm_f32", "sj_gemm_bf16"};
     return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";
 }
 

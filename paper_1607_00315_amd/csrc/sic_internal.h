@@ -107,6 +107,11 @@ struct DevCSR {
 // ---------------------------------------------------------------- k_sj.hip
 void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b, double* out,
                         hipStream_t s);
+// S_J from a float or bfloat16 copy of X (float accumulation, float64 result)
+void launch_sj_gemm_low(const void* X, bool bf16, int64_t n, int64_t m, int64_t j0, int b,
+                        double* out, hipStream_t s);
+// narrowed copies of X (either output may be null)
+void launch_narrow(const double* X, int64_t count, float* xf, uint16_t* xb, hipStream_t s);
 void launch_transpose(const double* X, int64_t m, int64_t n, double* Xt, hipStream_t s);
 void launch_diag_s(const double* Xt, int64_t n, int64_t m, double* d, hipStream_t s);
 void launch_sddmm(const double* Xt, int64_t m, const int32_t* rows, const int32_t* cols,
@@ -115,6 +120,7 @@ void launch_sddmm(const double* Xt, int64_t m, const int32_t* rows, const int32_
 // ---------------------------------------------------------------- k_cg.hip
 struct CGWork {
     DevBuf<double> R, Z, P, Q, dinv, part, scal;
+    DevBuf<float> R32, Z32, P32, Q32;   // the float vectors of the reduced-precision CG
     DevBuf<int32_t> flags;
 };
 struct CGResult {
@@ -122,8 +128,11 @@ struct CGResult {
     double max_rel_res = 0;
     bool converged = false;
 };
+// low_precision: float vectors with float64 iterate, scalars and sums, and the
+// true residual recomputed in float64 every few iterations (tol >= ~1e-6).
 CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
-                  double tol, int max_iter, CGWork& wk, hipStream_t s);
+                  double tol, int max_iter, CGWork& wk, hipStream_t s,
+                  bool low_precision = false);
 
 // ---------------------------------------------------------------- k_util.hip
 void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* total, hipStream_t s);
@@ -131,6 +140,9 @@ void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets
                           hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 void launch_iota_i32(int32_t* p, int64_t count, int32_t start, hipStream_t s);
+// global (row, column) of every coordinate: Jp[c_p[t]], j0 + c_ci[t]
+void launch_coord_globals(int64_t nc, const int32_t* c_p, const int32_t* c_ci, const int32_t* Jp,
+                          int64_t j0, int32_t* gr, int32_t* gc, hipStream_t s);
 
 // ---------------------------------------------------------------- k_screen.hip
 void launch_scatter_aj(const DevCSR& A, int64_t j0, int b, double* AJ, hipStream_t s);

@@ -5,6 +5,8 @@
 
 namespace sic {
 
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
 struct Options {
     int block = 256;
     double cg_tol_I = 1e-5, cg_tol_N = 1e-4;
@@ -34,7 +36,7 @@ struct BlockWork {
     DevBuf<int32_t> Jp, lmap;
     // coordinates
     DevBuf<int64_t> cptr;
-    DevBuf<int32_t> c_p, c_e, c_ci;
+    DevBuf<int32_t> c_p, c_e, c_ci, c_gr, c_gc;
     DevBuf<double> c_S, c_A, c_a, c_inva, c_wtc, c_wtt, delta, mu, cdstats;
     // line search
     DevBuf<double> Dinv, Rb, D11, Mo, Y, Pm, T1, D1, X, XtX, RPR, E1, E2, C, chol_out, alphas, lin;
@@ -67,6 +69,9 @@ struct Problem {
     int64_t n = 0, m = 0;
     double lam = 0;
     DevBuf<double> X, Xt, diagS;
+    DevBuf<float> Xf;        // narrowed copies of X for the mixed-precision path
+    DevBuf<uint16_t> Xb;
+    bool narrow = false;
     DevCSR A[2];
     int cur = 0;
     double F = 0;
@@ -97,6 +102,9 @@ struct Context {
     int64_t* h_i64 = nullptr;
     double* h_f64 = nullptr;
     BlockResult last;
+    // precision of the current sweep (mixed-precision path): S_J from X in
+    // float64, float or bfloat16; CG vectors in float unless PREC_F64
+    int prec = PREC_F64;
 };
 
 // context set-up (stream, pinned staging, options) and release; the context's

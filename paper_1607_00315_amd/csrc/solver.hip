@@ -219,6 +219,12 @@ void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n,
         SIC_CHECK_LAUNCH();
         sync(C);
     }
+    P.narrow = C.opt.precision == SIC_MIXED;
+    if (P.narrow) {
+        P.Xf.reserve(count);
+        P.Xb.reserve(count);
+        launch_narrow(P.X.p, (int64_t)count, P.Xf.p, P.Xb.p, s);
+    }
     P.Xt.reserve(count);
     launch_transpose(P.X.p, m, n, P.Xt.p, s);
     P.diagS.reserve(n);
@@ -349,6 +355,15 @@ void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count) 
 // coordinate Hessian form when the block has at most cd_hessian_max
 // coordinates (and its z and Delta fit in LDS), else the U = Delta W form.
 // Returns the profiler record to scale by the sweep count (or -1).
+// S_J of columns [j0, j0+b) in the current sweep's precision (float64 result).
+static void cov_block(Context& C, Problem& P, int64_t j0, int b, double* out) {
+    if (C.prec != PREC_F64 && P.narrow)
+        launch_sj_gemm_low(C.prec == PREC_BF16 ? (const void*)P.Xb.p : (const void*)P.Xf.p,
+                           C.prec == PREC_BF16, P.n, P.m, j0, b, out, C.stream);
+    else
+        launch_sj_gemm_f64(P.X.p, P.n, P.m, j0, b, out, C.stream);
+}
+
 static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max_sweeps,
                       double tol) {
     BlockWork& W = C.work;
@@ -399,9 +414,10 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         W.SJ.reserve(nb);
         W.WI.reserve(nb);
         W.cols.reserve(std::max<int64_t>(b, 1));
-        launch_sj_gemm_f64(P.X.p, n, P.m, j0, b, W.SJ.p, s);
+        cov_block(C, P, j0, b, W.SJ.p);
         launch_iota_i32(W.cols.p, b, (int32_t)j0, s);
-        CGResult cg = block_cg(A, W.cols.p, b, W.WI.p, b, tolI, C.opt.cg_max_iter, W.cg, s);
+        CGResult cg = block_cg(A, W.cols.p, b, W.WI.p, b, tolI, C.opt.cg_max_iter, W.cg, s,
+                               C.prec != PREC_F64);
         R.cg_iters_I = cg.iterations;
         R.cg_res_I = cg.max_rel_res;
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
@@ -437,7 +453,8 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         launch_flag_compact(W.cflag.p, W.scan_n.p, n, W.NC.p, W.cmap.p, s);
         W.WNC.reserve((size_t)n * std::max<int64_t>(nC, 1));
         if (nC > 0) {
-            CGResult cg = block_cg(A, W.NC.p, (int)nC, W.WNC.p, nC, tolI, C.opt.cg_max_iter, W.cg, s);
+            CGResult cg = block_cg(A, W.NC.p, (int)nC, W.WNC.p, nC, tolI, C.opt.cg_max_iter, W.cg,
+                                   s, C.prec != PREC_F64);
             R.cg_iters_N = cg.iterations;
             R.cg_res_N = cg.max_rel_res;
         }
@@ -497,7 +514,8 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     // W_N at the finest level
     if (fine && nN > 0) {
         W.WN.reserve((size_t)n * nN);
-        CGResult cg = block_cg(A, W.Jp.p + b, (int)nN, W.WN.p, nN, tolN, C.opt.cg_max_iter, W.cg, s);
+        CGResult cg = block_cg(A, W.Jp.p + b, (int)nN, W.WN.p, nN, tolN, C.opt.cg_max_iter, W.cg,
+                               s, C.prec != PREC_F64);
         R.cg_iters_N = cg.iterations;
         R.cg_res_N = cg.max_rel_res;
     }
@@ -508,6 +526,15 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     // (d) coordinate descent
     launch_cd_prep(W.cptr.p, b, nc, W.c_p.p, W.WJJ.p, jp, W.c_ci.p, W.c_a.p, W.c_inva.p, W.c_wtc.p,
                    W.c_wtt.p, W.delta.p, s);
+    if (fine && C.prec != PREC_F64 && nc > 0) {
+        // reduced-precision S_J served the screening; the model the direction
+        // and the line search use takes float64 S at its coordinates (a
+        // sampled product of 2 m flops each, against 2 n b m for the block)
+        W.c_gr.reserve(ncs);
+        W.c_gc.reserve(ncs);
+        launch_coord_globals(nc, W.c_p.p, W.c_ci.p, W.Jp.p, j0, W.c_gr.p, W.c_gc.p, s);
+        launch_sddmm(P.Xt.p, P.m, W.c_gr.p, W.c_gc.p, nc, W.c_S.p, s);
+    }
     const int64_t cd_rec = run_cd(C, jp, b, nc, P.lam, C.opt.cd_max_sweeps, C.opt.cd_tol);
     double cds[7];
     SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
@@ -626,7 +653,7 @@ void initial_free_set(Context& C, Problem& P) {
         W.colptr.reserve(bb + 1);
         SIC_HIP(hipMemsetAsync(W.AJ.p, 0, sizeof(double) * nb, s));
         launch_scatter_aj(P.Acur(), j0, bb, W.AJ.p, s);
-        launch_sj_gemm_f64(P.X.p, n, P.m, j0, bb, W.SJ.p, s);
+        cov_block(C, P, j0, bb, W.SJ.p);
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
         W.tilecount.reserve((size_t)tiles * bb);
         W.offsets.reserve((size_t)tiles * bb);
@@ -782,12 +809,29 @@ static double a_l1_norm(Context& C, Problem& P) {
     return s;
 }
 
+// Mixed-precision schedule (reduced precision only while far from the
+// optimum): bfloat16 S_J while the last finest sweep's KKT measure exceeds
+// 1e-2 (the error of S from bfloat16 samples is ~1e-3), float S_J while it
+// exceeds 1e-4 (the CG tolerance is then at least 1e-6, within float CG's
+// reach with residual replacement), float64 after that.
+static int cycle_precision(const Context& C, const Problem& P, double kkt_prev) {
+    if (C.opt.precision != SIC_MIXED || !P.narrow) return PREC_F64;
+    if (kkt_prev > 1e-2) return PREC_BF16;
+    if (kkt_prev > 1e-4) return PREC_F32;
+    return PREC_F64;
+}
+
 int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
     auto secs = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
     const bool ml = !(C.opt.flags & SIC_FLAG_NO_MULTILEVEL);
     const bool verbose = (C.opt.flags & SIC_FLAG_VERBOSE) != 0;
+    struct PrecReset {   // the step entry points always run in float64
+        Context& c;
+        ~PrecReset() { c.prec = PREC_F64; }
+    } prec_reset{C};
+    C.prec = cycle_precision(C, P, INFINITY);
     initial_free_set(C, P);
     double kkt_prev = INFINITY, kkt_l1 = INFINITY;
     int status = SIC_ENOCONV;
@@ -796,6 +840,7 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
     for (int cyc = 0; cyc < C.opt.max_cycles; ++cyc) {
         const double tolI = std::min(C.opt.cg_tol_I, std::max(1e-12, 0.01 * kkt_prev));
         const double tolN = std::min(C.opt.cg_tol_N, std::max(1e-12, 0.01 * kkt_prev));
+        C.prec = cycle_precision(C, P, kkt_prev);
         int levels = 0;
         if (ml) {
             std::vector<int64_t> ranking, sizes;
@@ -819,8 +864,9 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
         kkt_prev = sr.kkt_max;
         kkt_l1 = sr.kkt_l1;
         if (verbose)
-            fprintf(stderr, "[sic] cycle %d levels %d F=%.15e kkt=%.3e nnz=%lld t=%.3fs\n", cyc,
-                    levels, P.F, sr.kkt_max, (long long)P.Acur().nnz, secs());
+            fprintf(stderr, "[sic] cycle %d levels %d prec %s F=%.15e kkt=%.3e nnz=%lld t=%.3fs\n",
+                    cyc, levels, C.prec == PREC_F64 ? "f64" : (C.prec == PREC_F32 ? "f32" : "bf16"),
+                    P.F, sr.kkt_max, (long long)P.Acur().nnz, secs());
         if (C.trace && trace_len < C.trace_cap) {
             sic_trace_entry& e = C.trace[trace_len++];
             e.seconds = secs();
@@ -830,11 +876,14 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
             e.cycle = cyc;
             e.levels = levels;
         }
-        if (sr.kkt_max <= tol) {
+        // a reduced-precision cycle measures the KKT with approximate S and W:
+        // only a float64 cycle may end the solve
+        if (sr.kkt_max <= tol && C.prec == PREC_F64) {
             status = SIC_OK;
             break;
         }
     }
+    C.prec = PREC_F64;
     double kkt_final = kkt_prev;
     if (C.opt.flags & SIC_FLAG_FINAL_KKT) {
         kkt_final = exact_kkt(C, P, std::max(1e-13, std::min(1e-10, 0.01 * tol)), &kkt_l1);

@@ -118,6 +118,7 @@ SIGNATURES = {
     "sic_prob_objective": (ct.c_double, [_P]),
     "sic_step_cov_block": (ct.c_int, [_P, ct.c_int64, ct.c_int, _dp]),
     "sic_step_cov_pairs": (ct.c_int, [_P, _i32p, _i32p, ct.c_int64, _dp]),
+    "sic_step_cov_block_low": (ct.c_int, [_P, ct.c_int64, ct.c_int, ct.c_int, _dp]),
     "sic_step_inverse_columns": (ct.c_int, [_P, _i32p, ct.c_int, ct.c_double, ct.c_int, _dp,
                                             ct.POINTER(ct.c_int), _dp]),
     "sic_step_set_level": (ct.c_int, [_P, _i64p, ct.c_int64]),
@@ -448,6 +449,12 @@ class Prob:
         _check(lib().sic_step_cov_block(self.h, j0, b, _ptr(out, ct.c_double)), "cov_block")
         return out
 
+    def cov_block_low(self, j0, b, x_dtype):
+        out = np.empty((self.n, b))
+        _check(lib().sic_step_cov_block_low(self.h, j0, b, int(x_dtype), _ptr(out, ct.c_double)),
+               "cov_block_low")
+        return out
+
     def cov_pairs(self, rows, cols):
         rows = np.ascontiguousarray(rows, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -555,7 +562,7 @@ def hierarchy(n, supp_keys, free_keys, free_absg):
     return rank[:rlen.value], list(sizes[:nl.value])
 
 
-KERNEL_CLASSES = 12
+KERNEL_CLASSES = 14
 
 
 def profile_enable(on=True):

@@ -69,6 +69,42 @@ def test_cov_block_many_samples():
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+def _narrow(X, dtype):
+    """X rounded to float or to bfloat16 (nearest even), back in float64."""
+    x32 = np.asarray(X, dtype=np.float32)
+    if dtype == "f32":
+        return x32.astype(np.float64)
+    u = x32.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("name,j0,b", [("random_n600_m300", 512, 88),
+                                       ("grid_n2500_m1500", 2304, 196)])
+def test_cov_block_low(dtype, name, j0, b):
+    """Reduced-precision S_J against the float64 product of the same narrowed
+    samples, within the float accumulation bound gamma_(m+2) (|X|^T |X|)/m."""
+    from paper_1607_00315_amd import sic
+    X, P, spec = workload(name)
+    m = X.shape[0]
+    announce(f"cov_block_low {name} {dtype} j0={j0} b={b}")
+    with sic.Context(block=256) as c:
+        pr = sic.Prob(c, X, spec["lam"])
+        got = pr.cov_block_low(j0, b, sic.SIC_X_F32 if dtype == "f32" else sic.SIC_X_BF16)
+        pr.close()
+    Xn = _narrow(X, dtype)
+    ref = Xn.T @ Xn[:, j0:j0 + b] / m
+    u = 2.0 ** -24
+    gam = (m + 2) * u / (1 - (m + 2) * u)
+    bound = gam * (np.abs(Xn).T @ np.abs(Xn[:, j0:j0 + b])) / m
+    assert np.all(np.abs(got - ref) <= bound + 1e-300)
+    # and the narrowing itself is what separates it from float64 S
+    full = steps.cov_block(X, j0, j0 + b)
+    rel = np.max(np.abs(got - full)) / np.max(np.abs(full))
+    assert rel < (2e-6 if dtype == "f32" else 2e-2)
+
+
 def test_cov_pairs(ctx, rnd600):
     X, P, spec, S = rnd600
     announce("cov_pairs random_n600")

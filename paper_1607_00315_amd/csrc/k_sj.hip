@@ -27,17 +27,25 @@ constexpr int SJ_PAD = 4;
 // MFMA f64 16x16x4 operand layout: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; the 16x16 result sits in 4 registers per lane as
 // D[(l/16) + 4*v][l%16], v = 0..3 (checked with a lane-layout probe).
+// Tile order: a 1-D grid whose workgroup L runs on XCD L % 8 (round-robin
+// dispatch). Each XCD takes every eighth 64-row slab and runs the slab's
+// column tiles one after another, so the slab of X they all read is fetched
+// into that XCD's L2 once instead of once per column tile.
 __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ X, int64_t n,
                                                      int64_t m, int64_t j0, int b,
-                                                     double* __restrict__ out, double invm) {
+                                                     double* __restrict__ out, double invm,
+                                                     int row_tiles, int col_tiles) {
     __shared__ double sA[SJ_KC][SJ_TILE + SJ_PAD];
     __shared__ double sB[SJ_KC][SJ_TILE + SJ_PAD];
+    const int L = blockIdx.x, xcd = L & 7, slot = L >> 3;
+    const int rt = (slot / col_tiles) * 8 + xcd, ct = slot % col_tiles;
+    if (rt >= row_tiles) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int64_t i0 = (int64_t)blockIdx.x * SJ_TILE;   // rows of S_J (variables)
-    const int c0 = blockIdx.y * SJ_TILE;                // block columns
+    const int64_t i0 = (int64_t)rt * SJ_TILE;   // rows of S_J (variables)
+    const int c0 = ct * SJ_TILE;                // block columns
     // loader mapping: 16 rows x 64 columns, 4 consecutive doubles per thread
     const int lr = tid >> 4;          // 0..15
     const int lc = (tid & 15) * 4;    // 0..60
@@ -254,9 +262,12 @@ __global__ __launch_bounds__(256) void k_sddmm(const double* __restrict__ Xt, in
 
 void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b, double* out,
                         hipStream_t s) {
-    dim3 grid((unsigned)((n + SJ_TILE - 1) / SJ_TILE), (unsigned)((b + SJ_TILE - 1) / SJ_TILE));
+    const int row_tiles = (int)((n + SJ_TILE - 1) / SJ_TILE);
+    const int col_tiles = (b + SJ_TILE - 1) / SJ_TILE;
+    const unsigned grid = (unsigned)(8 * ((row_tiles + 7) / 8) * col_tiles);
     prof_begin(KK_SJ, s);
-    hipLaunchKernelGGL(k_sj_gemm_f64, grid, dim3(256), 0, s, X, n, m, j0, b, out, 1.0 / (double)m);
+    hipLaunchKernelGGL(k_sj_gemm_f64, dim3(grid), dim3(256), 0, s, X, n, m, j0, b, out,
+                       1.0 / (double)m, row_tiles, col_tiles);
     SIC_CHECK_LAUNCH();
     // algorithmic: X read once (m x n) and S_J written once; 2 n b m flops
     prof_end(KK_SJ, s, 8.0 * ((double)m * n + (double)n * b), 2.0 * (double)n * b * m);

@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--serve-tol", type=float, default=1e-6)
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the block-relaxation-only (no levels) leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="copy this many MiB device to device first (a reference kernel of "
                          "known traffic for the HBM byte counters of a profiler run)")
@@ -276,10 +278,10 @@ def main():
     if args.cd_tol:
         solver_opts["cd_tol"] = args.cd_tol
 
-    def time_to_gap(precision, profile):
+    def time_to_gap(precision, profile, flags=0):
         """Calibrate c* (solve to KKT 1e-6, verify the exact gap after c*
         cycles), then time `steps` solves of c* cycles."""
-        opts = dict(solver_opts, precision=precision)
+        opts = dict(solver_opts, precision=precision, flags=flags)
         t_kkt = sup_kkt = None
         info = {"cycles": None, "kkt_max": None}
         if args.cycles > 0:
@@ -340,6 +342,12 @@ def main():
         mixed["schedule"] = ("bf16 S_J and float CG while the KKT measure > 1e-2, float S_J and "
                              "float CG while > 1e-4, float64 after; float64 S at the coordinates, "
                              "Cholesky / log det and KKT throughout")
+    ablation = None
+    if not args.no_ablation:
+        # the block relaxation alone (Algorithm 2 without the levels of Algorithm 1)
+        abl, _ = time_to_gap(sic.SIC_FP64, False, sic.FLAG_NO_MULTILEVEL)
+        abl["multilevel_speedup"] = abl["value"] / value
+        ablation = dict(no_multilevel=abl)
     roofline = None
     if kern:
         total = sum(k["ms"] for k in kern.values())
@@ -376,7 +384,7 @@ def main():
         gap=gap, F_star=Fstar, support_identical_at_gap=res64["support_identical_at_gap"],
         support_identical_at_kkt=res64["support_identical_at_kkt"],
         nnz=res64["nnz"], time_to_kkt_1e6_s=res64["time_to_kkt_1e6_s"],
-        kkt_cycles=res64["kkt_cycles"], kkt_max=res64["kkt_max"], mixed=mixed,
+        kkt_cycles=res64["kkt_cycles"], kkt_max=res64["kkt_max"], mixed=mixed, ablation=ablation,
         roofline=roofline, cpu_baseline=cpu, serving=serving,
         kernels={k: dict(launches=v["launches"], ms=round(v["ms"], 3),
                          avg_ms=v["avg_ms"], GBps=(v["bytes"] / (v["ms"] * 1e-3) / 1e9)

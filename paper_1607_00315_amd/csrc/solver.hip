@@ -18,6 +18,9 @@
 
 namespace sic {
 
+// line-search trials per launch
+constexpr int LS_BATCH = 8;
+
 size_t CD_MAX_LDS_BYTES = 65536;
 
 namespace {
@@ -83,10 +86,10 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN) {
     W.T1.reserve(bb); W.D1.reserve(bb); W.X.reserve(bb); W.XtX.reserve(bb);
     W.RPR.reserve(bb); W.E1.reserve(bb); W.E2.reserve(bb);
     W.Y.reserve((size_t)std::max<int64_t>(nN, 1) * b);
-    W.C.reserve(4 * bb);
-    W.chol_out.reserve(16);
-    W.alphas.reserve(4);
-    W.lin.reserve(4);
+    W.C.reserve(LS_BATCH * bb);
+    W.chol_out.reserve(2 + 2 * LS_BATCH);
+    W.alphas.reserve(LS_BATCH);
+    W.lin.reserve(LS_BATCH);
     // R R^T = W_II
     launch_copy_block(W.WJJ.p, jp, b, W.Rb.p, s);
     launch_chol(W.Rb.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s, W.Dinv.p);
@@ -107,14 +110,14 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN) {
     launch_ls_e(W.D1.p, W.X.p, W.XtX.p, W.RPR.p, b, W.E1.p, W.E2.p, s);
 }
 
-// Evaluate nt <= 4 trial steps: log det change, PD flag, linear terms.
+// Evaluate nt <= LS_BATCH trial steps: log det change, PD flag, linear terms.
 // Returns whether W_II itself factored (positive definite).
 bool ls_eval(Context& C, int b, int64_t ncoord, double lam, const double* al, int nt,
              double* logdet, int* pd, double* lin) {
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
     const size_t bb = (size_t)b * b;
-    double h_out[10];
+    double h_out[2 + 2 * LS_BATCH];
     SIC_HIP(hipMemcpyAsync(W.alphas.p, al, sizeof(double) * nt, hipMemcpyHostToDevice, s));
     launch_ls_trials(W.E1.p, W.E2.p, b, W.alphas.p, nt, W.C.p, s);
     launch_chol(W.C.p, (int64_t)bb, nt, b, b, 1, W.chol_out.p + 2, s);
@@ -133,7 +136,8 @@ bool ls_eval(Context& C, int b, int64_t ncoord, double lam, const double* al, in
 
 // Step length by the backtracking rule of Section 6.1.2: alpha = 2^-i,
 // non-PD trials skipped, then continue while F keeps decreasing; alpha = 0
-// when no trial decreases F. Trials are evaluated four at a time.
+// when no trial decreases F. Trials are evaluated LS_BATCH at a time (one
+// workgroup each, so a batch costs one factorization's latency).
 LineSearch line_search(Context& C, double lam, int jp, int b, int64_t nN, int64_t ncoord) {
     ls_prepare(C, jp, b, nN);
     LineSearch res;
@@ -142,9 +146,9 @@ LineSearch line_search(Context& C, double lam, int jp, int b, int64_t nN, int64_
     int i = 0;
     const int max_trials = std::max(1, C.opt.ls_max_trials);
     while (!stop && i < max_trials) {
-        const int nt = std::min(4, max_trials - i);
-        double al[4], ld[4], lin[4];
-        int pd[4];
+        const int nt = std::min(LS_BATCH, max_trials - i);
+        double al[LS_BATCH], ld[LS_BATCH], lin[LS_BATCH];
+        int pd[LS_BATCH];
         for (int t = 0; t < nt; ++t) al[t] = std::ldexp(1.0, -(i + t));
         res.wii_pd = ls_eval(C, b, ncoord, lam, al, nt, ld, pd, lin);
         if (!res.wii_pd) break;
@@ -461,7 +465,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         const size_t bb = (size_t)b * b;
         W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb); W.Dinv.reserve(8 * 1024);
         W.err.reserve(1);
-        W.chol_out.reserve(16);
+        W.chol_out.reserve(2 + 2 * LS_BATCH);
         SIC_HIP(hipMemsetAsync(W.err.p, 0, sizeof(int32_t), s));
         launch_a2_k(A, j0, b, W.WNC.p, nC, W.cmap.p, W.Kb.p, W.err.p, s);
         launch_dense_aii(A, j0, b, W.AII.p, s);

@@ -119,3 +119,58 @@ def test_device_input_pointer():
     A1, _ = _solve(X, spec["lam"], 1e-8, block=16)
     A2, _ = _solve(torch.from_numpy(X).cuda(), spec["lam"], 1e-8, block=16)
     assert np.array_equal(A1, A2)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_full_size_grid_solve(precision):
+    """The benchmark workload (n = 10,000, m = 5,000, lambda = 0.08, block 256)
+    at full size, in the benchmark's launch configuration:
+      * support identical to the oracle's minimiser (stored by
+        tests/golden/make_golden.py, which calls only oracle/);
+      * objective within 1e-8 of the oracle's F*, evaluated exactly in float64;
+      * a KKT certificate on 48 sampled columns: W columns by a sparse direct
+        solve on the CPU, S columns from the samples, |g| <= lam off the
+        support and g = -lam sign(A) on it, within 1e-6."""
+    import json
+    import os
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    from paper_1607_00315_amd import sic
+    name = "grid_n10000_m5000"
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    golden = json.load(open(os.path.join(gdir, f"{name}.json")))
+    gkeys = np.load(os.path.join(gdir, f"{name}_support.npz"))["keys"]
+    X, P, spec = workload(name)
+    lam, n, m = spec["lam"], X.shape[1], X.shape[0]
+    announce(f"full-size solve {name} precision={precision}")
+    prec = sic.SIC_MIXED if precision == "mixed" else sic.SIC_FP64
+    with sic.Context(block=spec["block"], precision=prec) as c:
+        (rp, col, val), info, _ = c.solve(X, lam, 1e-6)
+    assert info["status"] == 0 and info["kkt_max"] <= 1e-6
+    check_csr_valid(rp, col, val, n)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    keep = col >= rows
+    keys = np.sort(rows[keep] * n + col[keep].astype(np.int64))
+    assert np.array_equal(keys, gkeys), "support differs from the oracle's minimiser"
+    A = sp.csr_matrix((val, col, rp), shape=(n, n))
+    assert (abs(A - A.T) > 0).nnz == 0
+    # exact objective: log det by a sparse Cholesky-free route (LU of the SPD
+    # iterate), tr(SA) from the samples
+    lu = spl.splu(A.tocsc())
+    logdet = float(np.sum(np.log(np.abs(lu.U.diagonal()))))
+    XA = (A @ X.T).T
+    tr = float(np.sum(XA * X)) / m
+    F = -logdet + tr + lam * float(np.abs(val).sum())
+    assert abs(F - golden["F_star"]) <= 1e-8 * abs(golden["F_star"])
+    # KKT certificate on sampled columns
+    rng = np.random.default_rng(7)
+    cols = np.sort(rng.choice(n, 48, replace=False))
+    E = np.zeros((n, cols.size))
+    E[cols, np.arange(cols.size)] = 1.0
+    Wc = lu.solve(E)
+    Sc = X.T @ X[:, cols] / m
+    G = Sc - Wc
+    Ac = A[:, cols].toarray()
+    on = Ac != 0
+    assert np.max(np.abs(G[on] + lam * np.sign(Ac[on]))) <= 1e-6
+    assert np.max(np.abs(G[~on])) <= lam + 1e-6

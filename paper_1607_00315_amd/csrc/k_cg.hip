@@ -96,28 +96,32 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     double pq = 0.0;
     for (int64_t i = (int64_t)ty * CG_WAVES + wave; i < n; i += (int64_t)gy * CG_WAVES) {
         const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+        // this row's own z, p, q issued together with the gathers below
+        const int64_t oi = i * k + jj;
+        const double zi = (double)Z[oi];
+        const double pi = first ? 0.0 : (double)P[oi];
+        const double qi = first ? 0.0 : (double)Q[oi];
         double acc = 0.0;
-        int64_t e = e0;
-        // eight gathers in flight before their products (rows with many
-        // non-zeros would otherwise wait for each gather in turn)
-        for (; e + 8 <= e1; e += 8) {
+        // eight gathers in flight before their products (a row would otherwise
+        // wait for each gather in turn); a short last batch repeats the row's
+        // last entry with a zero coefficient
+        for (int64_t e = e0; e < e1; e += 8) {
             double zv[8], av[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                av[u] = val[e + u];
-                zv[u] = (double)Z[(int64_t)col[e + u] * k + jj];
+                const bool in = e + u < e1;
+                const int64_t ee = in ? e + u : e1 - 1;
+                av[u] = in ? val[ee] : 0.0;
+                zv[u] = (double)Z[(int64_t)col[ee] * k + jj];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc += av[u] * zv[u];
         }
-        for (; e < e1; ++e) acc += val[e] * (double)Z[(int64_t)col[e] * k + jj];
         if (jok) {
-            const int64_t o = i * k + j;
-            const double z = (double)Z[o];
-            const V p = (V)(first ? z : z + beta * (double)P[o]);
-            const V q = (V)(first ? acc : acc + beta * (double)Q[o]);
-            P[o] = p;
-            Q[o] = q;
+            const V p = (V)(first ? zi : zi + beta * pi);
+            const V q = (V)(first ? acc : acc + beta * qi);
+            P[oi] = p;
+            Q[oi] = q;
             pq += (double)p * (double)q;
         }
     }

@@ -49,11 +49,26 @@ __global__ __launch_bounds__(256) void k_screen_fine(
     double kmax = 0.0, ksum = 0.0;
     if (ci < b) {
         int pos = pass ? offsets[tile * b + ci] : 0;
-        for (int64_t r = r0; r < r1; ++r) {
-            const int64_t o = r * b + ci;
-            const double s = SJ[o];
-            const double w = WI ? WI[o] : (r == c ? 1.0 : 0.0);
-            const double a = AJ[o];
+        // rows in groups of sixteen: all 48 loads in flight before the (ordered)
+        // screening of the group; rows past the tile end load row r0 and are skipped
+        constexpr int G = 16;
+        for (int64_t rg = r0; rg < r1; rg += G) {
+            double sv[G], wv[G], av[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int64_t r = rg + u < r1 ? rg + u : r0;
+                const int64_t o = r * b + ci;
+                sv[u] = SJ[o];
+                wv[u] = WI ? WI[o] : (r == c ? 1.0 : 0.0);
+                av[u] = AJ[o];
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+            const int64_t r = rg + u;
+            if (r >= r1) break;
+            const double s = sv[u];
+            const double w = wv[u];
+            const double a = av[u];
             const double g = s - w;
             const bool fr = (a != 0.0) || (fabs(g) > lam);
             if (pass == 0) {
@@ -70,6 +85,7 @@ __global__ __launch_bounds__(256) void k_screen_fine(
                 ++pos;
             }
             cnt += fr ? 1 : 0;
+            }
         }
         if (pass == 0) tilecount[tile * b + ci] = cnt;
     }

@@ -17,8 +17,16 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_i32(const int32_t* __rest
     const int t = threadIdx.x;
     const int64_t chunk = (count + SCAN_THREADS - 1) / SCAN_THREADS;
     const int64_t b0 = t * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
+    constexpr int G = 8;   // eight loads in flight per batch (clamped past the chunk end)
     int64_t s = 0;
-    for (int64_t i = b0; i < b1; ++i) s += in[i];
+    for (int64_t i0 = b0; i0 < b1; i0 += G) {
+        int32_t v[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) v[u] = in[i0 + u < b1 ? i0 + u : b0];
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+            if (i0 + u < b1) s += v[u];
+    }
     sums[t] = s;
     __syncthreads();
     for (int off = 1; off < SCAN_THREADS; off <<= 1) {
@@ -28,9 +36,16 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_i32(const int32_t* __rest
         __syncthreads();
     }
     int64_t run = t > 0 ? sums[t - 1] : 0;
-    for (int64_t i = b0; i < b1; ++i) {
-        out[i] = run;
-        run += in[i];
+    for (int64_t i0 = b0; i0 < b1; i0 += G) {
+        int32_t v[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) v[u] = in[i0 + u < b1 ? i0 + u : b0];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            if (i0 + u >= b1) break;
+            out[i0 + u] = run;
+            run += v[u];
+        }
     }
     if (t == SCAN_THREADS - 1) {
         out[count] = sums[t];
@@ -50,10 +65,24 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* _
     const int64_t count = (int64_t)tiles * b;
     const int64_t chunk = (count + SCAN_THREADS - 1) / SCAN_THREADS;
     const int64_t b0 = t * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
+    // the chunk walks columns tile by tile (strided gathers): eight loads in
+    // flight per batch, clamped to the chunk's first entry past its end
+    constexpr int G = 8;
+    auto gather = [&](int64_t q0, int32_t* v) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int64_t q = q0 + u < b1 ? q0 + u : b0;
+            const int64_t c = q / tiles, tile = q % tiles;
+            v[u] = cnt[tile * b + c];
+        }
+    };
     int64_t s = 0;
-    for (int64_t q = b0; q < b1; ++q) {
-        const int64_t c = q / tiles, tile = q % tiles;
-        s += cnt[tile * b + c];
+    for (int64_t q0 = b0; q0 < b1; q0 += G) {
+        int32_t v[G];
+        gather(q0, v);
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+            if (q0 + u < b1) s += v[u];
     }
     sums[t] = s;
     __syncthreads();
@@ -64,11 +93,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* _
         __syncthreads();
     }
     int64_t run = t > 0 ? sums[t - 1] : 0;
-    for (int64_t q = b0; q < b1; ++q) {
-        const int64_t c = q / tiles, tile = q % tiles;
-        offsets[tile * b + c] = (int32_t)run;
-        if (tile == 0) colptr[c] = run;
-        run += cnt[tile * b + c];
+    for (int64_t q0 = b0; q0 < b1; q0 += G) {
+        int32_t v[G];
+        gather(q0, v);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int64_t q = q0 + u;
+            if (q >= b1) break;
+            const int64_t c = q / tiles, tile = q % tiles;
+            offsets[tile * b + c] = (int32_t)run;
+            if (tile == 0) colptr[c] = run;
+            run += v[u];
+        }
     }
     if (t == SCAN_THREADS - 1) colptr[b] = sums[t];
 }

@@ -42,7 +42,7 @@ AccountScope::~AccountScope() { t_account = prev_; }
 
 namespace {
 
-constexpr int ROWS_PER_TILE = 64;
+constexpr int ROWS_PER_TILE = 32;
 
 void sync(Context& C) { SIC_HIP(hipStreamSynchronize(C.stream)); }
 

@@ -205,6 +205,34 @@ def serving_leg(sic, torch, count, slots, tol):
                 poisson=poisson, burst=burst)
 
 
+def path_leg(sic, torch, count):
+    """The warm-started lambda path of random_n20000_m1000_path (its first
+    ``count`` values) as one request, float64 and mixed precision, to KKT 1e-6.
+    The samples are drawn on the device (same law as the host generator)."""
+    from synth.device import sample_gaussian_device
+    from synth.generators import WORKLOADS, _precision
+    spec = WORKLOADS["random_n20000_m1000_path"]
+    rng = np.random.default_rng(spec["seed"])
+    P = _precision(spec["kind"], spec["n"], rng, spec["pairs_per_node"])
+    X = sample_gaussian_device(P, spec["m"], int(rng.integers(0, 2**62)), "cuda:0")
+    torch.cuda.synchronize()
+    path = spec["lam"][:count]
+    out = dict(workload="random_n20000_m1000_path", n=spec["n"], m=spec["m"],
+               lambdas=[float(l) for l in path], tol_kkt=1e-6)
+    for label, prec in (("f64", sic.SIC_FP64), ("mixed", sic.SIC_MIXED)):
+        with sic.Context(block=spec["block"], precision=prec) as c:
+            t = time.perf_counter()
+            code, res = c.solve_batch([dict(X=X, lambda_path=path, tol=1e-6)])
+            dt = time.perf_counter() - t
+        out[label] = dict(seconds=dt, status=code,
+                          per_lambda=[dict(seconds=i["seconds"], cycles=i["cycles"],
+                                           kkt_max=i["kkt_max"], nnz=i["nnz"])
+                                      for _, i in res])
+        log(f"path {label}: {dt:.1f}s " + " ".join(f"{i['seconds']:.1f}s/{i['cycles']}cyc"
+                                                    for _, i in res))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +250,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-tol", type=float, default=1e-6)
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--path-only", type=int, default=0, metavar="K",
+                    help="run only the warm-started lambda path (its first K values)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the block-relaxation-only (no levels) leg")
@@ -244,6 +274,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.path_only > 0:
+        out = path_leg(sic, torch, args.path_only)
+        print(json.dumps(dict(metric="lambda path: time to KKT 1e-6 per lambda (s)", n_gpus=1,
+                              data="synthetic", path=out)), flush=True)
+        return
     if args.serve_only:
         out = serving_leg(sic, torch, args.serve_requests, args.serve_slots, args.serve_tol)
         print(json.dumps(dict(metric="served solves/s + p50/p99 (s)", n_gpus=1, data="synthetic",

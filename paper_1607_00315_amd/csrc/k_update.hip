@@ -64,7 +64,7 @@ __global__ void k_upd_rows(int pass, int64_t n, int64_t j0, int b,
                            const int64_t* __restrict__ cptr, const int32_t* __restrict__ c_p,
                            const int32_t* __restrict__ Jp, const double* __restrict__ ANEW,
                            int32_t* __restrict__ cnt, const int64_t* __restrict__ nrowptr,
-                           int32_t* __restrict__ ncol, double* __restrict__ nval) {
+                           int32_t* __restrict__ ncol, double* __restrict__ nval, int64_t cap) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int64_t j1 = j0 + b;
@@ -73,8 +73,10 @@ __global__ void k_upd_rows(int pass, int64_t n, int64_t j0, int b,
     const double* arow = ANEW + r * b;
     auto emit = [&](int64_t c, double v) {
         if (pass) {
-            ncol[o] = (int32_t)c;
-            nval[o] = v;
+            if (o < cap) {   // the host checks the total against cap after the block
+                ncol[o] = (int32_t)c;
+                nval[o] = v;
+            }
             ++o;
         }
         ++count;
@@ -153,11 +155,11 @@ void launch_upd_reset(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, c
 void launch_upd_rows(int pass, int64_t n, int64_t j0, int b, const DevCSR& A, const int32_t* lmap,
                      const int64_t* cptr, const int32_t* c_p, const int32_t* Jp, const double* ANEW,
                      int32_t* cnt, const int64_t* nrowptr, int32_t* ncol, double* nval,
-                     hipStream_t s) {
+                     hipStream_t s, int64_t cap) {
     prof_begin(KK_UPD_ROWS, s);
     hipLaunchKernelGGL(k_upd_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pass, n, j0, b,
                        A.rowptr.p, A.col.p, A.val.p, lmap, cptr, c_p, Jp, ANEW, cnt, nrowptr, ncol,
-                       nval);
+                       nval, cap);
     SIC_CHECK_LAUNCH();
     prof_end(KK_UPD_ROWS, s, (double)A.nnz * 12.0 * (pass ? 2.0 : 0.0) + (double)n * 16.0, 0.0);
 }

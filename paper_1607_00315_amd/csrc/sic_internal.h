@@ -247,6 +247,6 @@ void launch_upd_reset(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, c
 void launch_upd_rows(int pass, int64_t n, int64_t j0, int b, const DevCSR& A, const int32_t* lmap,
                      const int64_t* cptr, const int32_t* c_p, const int32_t* Jp, const double* ANEW,
                      int32_t* cnt, const int64_t* nrowptr, int32_t* ncol, double* nval,
-                     hipStream_t s);
+                     hipStream_t s, int64_t cap = 0);   // pass 1 writes only below cap
 
 }  // namespace sic

@@ -540,10 +540,15 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         launch_sddmm(P.Xt.p, P.m, W.c_gr.p, W.c_gc.p, nc, W.c_S.p, s);
     }
     const int64_t cd_rec = run_cd(C, jp, b, nc, P.lam, C.opt.cd_max_sweeps, C.opt.cd_tol);
-    double cds[7];
-    SIC_HIP(hipMemcpyAsync(cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
+    // the sweep statistics go to pinned staging: the copy does not hold the host,
+    // and the line search's first read-back waits for it
+    double* h_cds = C.h_f64 + 40;
+    SIC_HIP(hipMemcpyAsync(h_cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     // (e) line search
     LineSearch ls = line_search(C, P.lam, jp, b, nN, nc);
+    sync(C);   // (no-op when the line search ended on a read-back)
+    double cds[7];
+    std::copy(h_cds, h_cds + 7, cds);
     R.cd_sweeps = (int)cds[0];
     R.cd_last_maxmu = cds[1];
     prof_scale(cd_rec, cds[0]);
@@ -560,6 +565,8 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     R.dF = ls.dF;
     R.trials = ls.trials;
     // A <- A + alpha Delta
+    bool new_nnz_pending = false;
+    int64_t new_cap = 0;
     if (ls.alpha != 0.0) {
         DevCSR& An = P.A[1 - P.cur];
         const int64_t cap = A.nnz + 2 * nc;
@@ -573,16 +580,18 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         launch_upd_rows(0, n, j0, b, A, W.lmap.p, W.cptr.p, W.c_p.p, W.Jp.p, W.ANEW.p, W.rcount.p,
                         nullptr, nullptr, nullptr, s);
         launch_scan_i32(W.rcount.p, n, An.rowptr.p, nullptr, s);
-        An.nnz = read_i64(C, An.rowptr.p + n);
-        if (An.nnz > cap) throw SicError(SIC_EINTERNAL, "CSR rebuild exceeded its bound");
+        // the new entry count is read at the block's closing synchronisation;
+        // the fill pass writes nothing at or beyond cap meanwhile
+        SIC_HIP(hipMemcpyAsync(C.h_i64 + 8, An.rowptr.p + n, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+        new_nnz_pending = true;
+        new_cap = cap;
         launch_upd_rows(1, n, j0, b, A, W.lmap.p, W.cptr.p, W.c_p.p, W.Jp.p, W.ANEW.p, W.rcount.p,
-                        An.rowptr.p, An.col.p, An.val.p, s);
+                        An.rowptr.p, An.col.p, An.val.p, s, cap);
         launch_upd_reset(nc, W.c_p.p, W.c_ci.p, W.Jp.p, j0, b, W.ANEW.p, s);
         P.cur = 1 - P.cur;
         P.F += ls.dF;
-        P.max_nnz = std::max(P.max_nnz, An.nnz);
     }
-    R.nnz_after = P.Acur().nnz;
     // free pairs and |g| for the next hierarchy
     if (record && R.E > 0) {
         std::vector<int64_t> cp(b + 1);
@@ -609,6 +618,13 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     launch_reset_rows(W.Jp.p, jp, nullptr, W.lmap.p, s);
     if (!fine && nC > 0) launch_reset_rows(W.NC.p, nC, W.cflag.p, W.cmap.p, s);
     sync(C);
+    if (new_nnz_pending) {
+        DevCSR& An = P.Acur();
+        An.nnz = C.h_i64[8];
+        if (An.nnz > new_cap) throw SicError(SIC_EINTERNAL, "CSR rebuild exceeded its bound");
+        P.max_nnz = std::max(P.max_nnz, An.nnz);
+    }
+    R.nnz_after = P.Acur().nnz;
     C.last = R;
     return R;
 }

@@ -6,16 +6,19 @@
 // All k right-hand sides run together on row-major n x k blocks, so that one
 // sparse row of A gathers whole 64-column segments of the direction block
 // (coalesced 512-byte reads) and the per-column CG scalars stay independent.
-// One iteration is four launches:
-//   spmm:       p = z + beta p,  q = A z + beta q  (= A p),   partial p.q
-//   fin_alpha:  alpha = r.z / p.q per column (one small workgroup per 64 columns)
-//   update:     x += alpha p, r -= alpha q, z = D^{-1} r,     partial r.z, r.r
-//   fin_beta:   beta = r.z_new / r.z_old, residual norms, convergence per tile
-// The per-column reductions are finished in separate small launches rather
-// than by the last workgroup to arrive: a device-scope fence in every
-// workgroup would write back the L2 of each XCD. Summation order is fixed,
-// so results do not depend on scheduling. Convergence is tracked per
-// 64-column tile; launches for a converged tile return at once.
+// One iteration is two launches; each finishes the previous launch's
+// per-column sums in its prologue (every workgroup of a column tile sums the
+// same partials in the same order, so all take the same decision):
+//   spmm(it):   rz, rr of the last update -> convergence of the tile (it > 0),
+//               beta = rz / rz_old; p = z + beta p, q = A z + beta q (= A p),
+//               partial p.q
+//   update(it): alpha = rz / p.q; x += alpha p, r -= alpha q, z = D^{-1} r,
+//               partial r.z, r.r
+// rz alternates between two slots by iteration parity, so no launch reads a
+// scalar that the same launch writes. No device-scope fences (they would
+// write back the L2 of each XCD), no atomics: results do not depend on
+// scheduling. Convergence is tracked per 64-column tile; launches for a
+// converged tile return at once.
 #include "profiler.h"
 
 namespace sic {
@@ -28,7 +31,7 @@ constexpr int CG_ROW_TILES = 128;   // row partitions (partials per column)
 
 // per-tile control block: [0] done, [1] iterations finished
 enum { T_DONE = 0, T_ITER = 1, T_INTS = 2 };
-enum { S_RZ = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3 };
+enum { S_RZ0 = 0, S_RZ1 = 1, S_RR = 3 };   // rz by iteration parity; r.r
 
 __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                           const double* __restrict__ val, int64_t n, double* __restrict__ dinv) {
@@ -50,9 +53,9 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
         const int64_t c = cols[j];
         R[c * k + j] = (V)1.0;
         Z[c * k + j] = (V)dinv[c];
-        scal[j * 4 + S_RZ] = dinv[c];
-        scal[j * 4 + S_ALPHA] = 0.0;
-        scal[j * 4 + S_BETA] = 0.0;
+        scal[j * 4 + S_RZ0] = dinv[c];
+        scal[j * 4 + S_RZ1] = 0.0;
+        scal[j * 4 + 2] = 0.0;
         scal[j * 4 + S_RR] = 1.0;
     }
     if (j < col_tiles) {
@@ -68,8 +71,10 @@ template <typename V>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, int64_t n, int k, const V* __restrict__ Z,
-    V* __restrict__ P, V* __restrict__ Q, const double* __restrict__ scal,
-    double* __restrict__ part, const int* __restrict__ tctl, int gx, int gy, int xcd_grouped) {
+    V* __restrict__ P, V* __restrict__ Q, double* __restrict__ scal,
+    const double* __restrict__ rzrr, double* __restrict__ part, int* __restrict__ tctl,
+    double* __restrict__ tres, double tol, int it, int gx, int gy, int xcd_grouped,
+    int check_only) {
     // Tile (tx = 64-column tile, ty = row partition). Grouped: a 1-D grid whose
     // workgroup L runs on XCD L % 8 (round-robin dispatch); every row partition
     // of a column tile lands on the same XCD, one tile after another, so the
@@ -86,13 +91,49 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
         ty = blockIdx.y;
     }
     if (tctl[tx * T_INTS + T_DONE]) return;
-    const bool first = tctl[tx * T_INTS + T_ITER] == 0;
+    const bool first = it == 0;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
     const int j = tx * 64 + lane;
     const bool jok = j < k;
     const int jj = jok ? j : k - 1;   // clamped: every lane loads, masked lanes discard
-    const double beta = (jok && !first) ? scal[j * 4 + S_BETA] : 0.0;
+    double beta = 0.0;
+    if (!first) {
+        // r.z and r.r of the last update (fixed order: row partitions t = w mod 8
+        // in wave w, then the waves in order)
+        __shared__ double rsum[2][CG_WAVES][64];
+        double a0 = 0.0, a1 = 0.0;
+        for (int t = wave; t < gy; t += CG_WAVES) {
+            a0 += rzrr[((int64_t)t * k + jj) * 2 + 0];
+            a1 += rzrr[((int64_t)t * k + jj) * 2 + 1];
+        }
+        rsum[0][wave][lane] = a0;
+        rsum[1][wave][lane] = a1;
+        __syncthreads();
+        double rz = 0.0, rr = 0.0;
+        for (int w = 0; w < CG_WAVES; ++w) {
+            rz += rsum[0][w][lane];
+            rr += rsum[1][w][lane];
+        }
+        double res = jok ? sqrt(rr) : 0.0;
+        for (int off = 32; off > 0; off >>= 1) res = fmax(res, __shfl_xor(res, off, 64));
+        const double rz_old = scal[jj * 4 + ((it - 1) & 1)];
+        beta = (jok && rz_old > 0.0) ? rz / rz_old : 0.0;
+        const bool conv = res <= tol;   // the same in every workgroup of the tile
+        if (ty == 0 && wave == 0) {     // the tile's record, for the host and update(it)
+            if (jok) {
+                scal[j * 4 + (it & 1)] = rz;
+                scal[j * 4 + S_RR] = rr;
+            }
+            if (lane == 0) {
+                tres[tx] = res;
+                tctl[tx * T_INTS + T_ITER] = (conv || check_only) ? it : it + 1;
+                if (conv) tctl[tx * T_INTS + T_DONE] = 1;
+            }
+        }
+        if (conv) return;
+    }
+    if (check_only) return;
     double pq = 0.0;
     for (int64_t i = (int64_t)ty * CG_WAVES + wave; i < n; i += (int64_t)gy * CG_WAVES) {
         const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
@@ -135,39 +176,28 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     }
 }
 
-// alpha = r.z / p.q for the 64 columns of tile blockIdx.x (4 partial sums per column)
-__global__ __launch_bounds__(256) void k_cg_fin_alpha(int k, int row_tiles,
-                                                      const double* __restrict__ part,
-                                                      double* __restrict__ scal,
-                                                      const int* __restrict__ tctl) {
-    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
-    __shared__ double red[4][64];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + c;
-    double s = 0.0;
-    if (j < k)
-        for (int t = g; t < row_tiles; t += 4) s += part[(int64_t)t * k + j];
-    red[g][c] = s;
-    __syncthreads();
-    if (g == 0 && j < k) {
-        const double pq = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-        const double rz = scal[j * 4 + S_RZ];
-        scal[j * 4 + S_ALPHA] = (pq > 0.0 && rz > 0.0) ? rz / pq : 0.0;
-    }
-}
-
 template <typename V>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     int64_t n, int k, const double* __restrict__ dinv, double* __restrict__ W,
     V* __restrict__ R, V* __restrict__ Z, const V* __restrict__ P,
-    const V* __restrict__ Q, const double* __restrict__ scal, double* __restrict__ part,
-    const int* __restrict__ tctl) {
+    const V* __restrict__ Q, const double* __restrict__ scal, const double* __restrict__ pqp,
+    double* __restrict__ part, const int* __restrict__ tctl, int it) {
     if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
     const int j = blockIdx.x * 64 + lane;
     const bool jok = j < k;
-    const double alpha = jok ? scal[j * 4 + S_ALPHA] : 0.0;
+    const int jj = jok ? j : k - 1;
+    // alpha = r.z / p.q (p.q summed in a fixed order, as in the product's prologue)
+    __shared__ double psum[CG_WAVES][64];
+    double a = 0.0;
+    for (int t = wave; t < (int)gridDim.y; t += CG_WAVES) a += pqp[(int64_t)t * k + jj];
+    psum[wave][lane] = a;
+    __syncthreads();
+    double pq = 0.0;
+    for (int w = 0; w < CG_WAVES; ++w) pq += psum[w][lane];
+    const double rz0 = scal[jj * 4 + (it & 1)];
+    const double alpha = (jok && pq > 0.0 && rz0 > 0.0) ? rz0 / pq : 0.0;
     double rz = 0.0, rr = 0.0;
     if (jok) {
         for (int64_t i = (int64_t)blockIdx.y * CG_WAVES + wave; i < n;
@@ -261,47 +291,6 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_true_residual(
     }
 }
 
-// beta, new r.z, residual norms; the tile converges when every column's
-// relative residual ||r_j|| / ||e_j|| = ||r_j|| is at most tol.
-__global__ __launch_bounds__(256) void k_cg_fin_beta(int k, int row_tiles,
-                                                     const double* __restrict__ part,
-                                                     double* __restrict__ scal,
-                                                     int* __restrict__ tctl,
-                                                     double* __restrict__ tres, double tol) {
-    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
-    __shared__ double red[2][4][64];
-    __shared__ double mx[64];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + c;
-    double s0 = 0.0, s1 = 0.0;
-    if (j < k)
-        for (int t = g; t < row_tiles; t += 4) {
-            s0 += part[((int64_t)t * k + j) * 2 + 0];
-            s1 += part[((int64_t)t * k + j) * 2 + 1];
-        }
-    red[0][g][c] = s0;
-    red[1][g][c] = s1;
-    __syncthreads();
-    if (g == 0) {
-        double res = 0.0;
-        if (j < k) {
-            const double rz = (red[0][0][c] + red[0][1][c]) + (red[0][2][c] + red[0][3][c]);
-            const double rr = (red[1][0][c] + red[1][1][c]) + (red[1][2][c] + red[1][3][c]);
-            const double rz_old = scal[j * 4 + S_RZ];
-            scal[j * 4 + S_BETA] = rz_old > 0.0 ? rz / rz_old : 0.0;
-            scal[j * 4 + S_RZ] = rz;
-            scal[j * 4 + S_RR] = rr;
-            res = sqrt(rr);
-        }
-        for (int off = 32; off > 0; off >>= 1) res = fmax(res, __shfl_xor(res, off, 64));
-        if (c == 0) {
-            tres[blockIdx.x] = res;
-            tctl[blockIdx.x * T_INTS + T_ITER] += 1;
-            if (res <= tol) tctl[blockIdx.x * T_INTS + T_DONE] = 1;
-        }
-    }
-}
-
 }  // namespace
 
 namespace {
@@ -325,7 +314,10 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
     const int col_tiles = (k + 63) / 64;
     int row_tiles = (int)std::min<int64_t>(CG_ROW_TILES, (n + CG_WAVES - 1) / CG_WAVES);
     if (row_tiles < 1) row_tiles = 1;
-    wk.part.reserve((size_t)row_tiles * k * 2);
+    // partials: r.z and r.r of an update (two per entry), then p.q of a product
+    wk.part.reserve((size_t)row_tiles * k * 3);
+    double* part_rz = wk.part.p;
+    double* part_pq = wk.part.p + (size_t)row_tiles * k * 2;
     wk.scal.reserve((size_t)4 * k + col_tiles);
     wk.flags.reserve((size_t)T_INTS * col_tiles);
     double* tres = wk.scal.p + 4 * k;
@@ -367,31 +359,32 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
             r.iter = it;
             prof_begin(KK_CG_SPMM, s);
             hipLaunchKernelGGL(k_cg_spmm<V>, sgrid, dim3(CG_THREADS), 0, s, A.rowptr.p, A.col.p,
-                               A.val.p, n, k, Z, P, Q, wk.scal.p, wk.part.p, wk.flags.p,
-                               col_tiles, row_tiles, grouped);
+                               A.val.p, n, k, Z, P, Q, wk.scal.p, part_rz, part_pq, wk.flags.p,
+                               tres, tol, it, col_tiles, row_tiles, grouped, 0);
             SIC_CHECK_LAUNCH();
             r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
                               2.0 * A.nnz * k + 4.0 * n * k);
-            hipLaunchKernelGGL(k_cg_fin_alpha, dim3(col_tiles), dim3(256), 0, s, k, row_tiles,
-                               wk.part.p, wk.scal.p, wk.flags.p);
-            SIC_CHECK_LAUNCH();
             prof_begin(KK_CG_UPDATE, s);
             hipLaunchKernelGGL(k_cg_update<V>, grid, dim3(CG_THREADS), 0, s, n, k, wk.dinv.p, W, R,
-                               Z, P, Q, wk.scal.p, wk.part.p, wk.flags.p);
+                               Z, P, Q, wk.scal.p, part_pq, part_rz, wk.flags.p, it);
             SIC_CHECK_LAUNCH();
             r.upd = prof_end(KK_CG_UPDATE, s, 5.0 * nkb + 16.0 * n * k + n * 8.0, 10.0 * n * k);
             if (LOW && (it + 1) % CG_REPLACE_EVERY == 0) {
                 hipLaunchKernelGGL(k_cg_true_residual<V>, grid, dim3(CG_THREADS), 0, s, A.rowptr.p,
-                                   A.col.p, A.val.p, n, k, d_cols, wk.dinv.p, W, R, Z, wk.part.p,
+                                   A.col.p, A.val.p, n, k, d_cols, wk.dinv.p, W, R, Z, part_rz,
                                    wk.flags.p);
                 SIC_CHECK_LAUNCH();
             }
-            hipLaunchKernelGGL(k_cg_fin_beta, dim3(col_tiles), dim3(256), 0, s, k, row_tiles,
-                               wk.part.p, wk.scal.p, wk.flags.p, tres, tol);
-            SIC_CHECK_LAUNCH();
             recs.push_back(r);
         }
         launched += chunk;
+        if (launched >= max_iter) {
+            // the last update's residual has no product after it to test it
+            hipLaunchKernelGGL(k_cg_spmm<V>, dim3(col_tiles, 1), dim3(CG_THREADS), 0, s,
+                               A.rowptr.p, A.col.p, A.val.p, n, k, Z, P, Q, wk.scal.p, part_rz,
+                               part_pq, wk.flags.p, tres, tol, launched, col_tiles, row_tiles, 0, 1);
+            SIC_CHECK_LAUNCH();
+        }
         SIC_HIP(hipMemcpyAsync(hctl.data(), wk.flags.p, sizeof(int) * hctl.size(),
                                hipMemcpyDeviceToHost, s));
         SIC_HIP(hipMemcpyAsync(hres.data(), tres, sizeof(double) * col_tiles,

@@ -221,8 +221,14 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
                 const double t = chol_readlane(rw[k], k);
                 const double piv = identity ? 1.0 + t : t;
                 if (!(piv > 0.0) || !isfinite(piv)) bad = 1;
-                const double lkk = sqrt(piv);
-                const double ikk = 1.0 / lkk;
+                // 1/sqrt(piv): the hardware estimate and two Newton steps (each
+                // doubles the correct bits), then sqrt(piv) = piv / sqrt(piv); a
+                // third of the dependent operations of a rounded sqrt and divide
+                double ikk = __builtin_amdgcn_rsq(piv);
+                const double hp = 0.5 * piv;
+#pragma unroll
+                for (int it = 0; it < 2; ++it) ikk = fma(ikk, fma(-hp * ikk, ikk, 0.5), ikk);
+                const double lkk = piv * ikk;
                 ikks[k] = ikk;
                 if (lane == k) tsave = t;
                 rw[k] = (lane == k) ? lkk : rw[k] * ikk;   // lanes > k: L_ik

@@ -4,7 +4,8 @@
  * every timed launch (the traffic and work the kernel must do at minimum), so
  * that achieved bandwidth / throughput can be reported without a profiler.
  * Timing adds two event records per launch; leave it off for production runs.
- * The counters are process-wide.
+ * The switch, the class selection and the counters belong to the calling host
+ * thread: a solve is timed on the thread that runs it.
  */
 #ifndef SIC_PROFILE_H
 #define SIC_PROFILE_H
@@ -30,6 +31,9 @@ extern "C" {
 
 void sic_profile_enable(int on);      /* on != 0 starts timing, 0 stops it */
 void sic_profile_reset(void);         /* zero every counter */
+/* Restrict timing to the classes whose bit (1 << class) is set in mask; the
+ * others launch with no event around them. The default selects every class. */
+void sic_profile_select(uint32_t mask);
 /* Totals of one kernel class since the last reset; returns SIC_EINVAL (-1)
  * for an unknown class. Any output pointer may be NULL. */
 int sic_profile_read(int kind, int64_t* launches, double* milliseconds, double* bytes,

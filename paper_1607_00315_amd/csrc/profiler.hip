@@ -20,6 +20,7 @@ struct Pending {
 
 struct Profiler {
     bool enabled = false;
+    uint32_t mask = ~0u;   // classes timed while enabled
     std::vector<hipEvent_t> free_events;
     std::vector<Pending> pending;
     KernelStat stat[KK_COUNT];
@@ -82,7 +83,7 @@ void prof_reset() {
 }
 
 void prof_begin(int kind, hipStream_t s) {
-    if (!g.enabled) return;
+    if (!g.enabled || !((g.mask >> kind) & 1u)) return;
     hipEvent_t e = take_event();
     SIC_HIP(hipEventRecord(e, s));
     g.open[kind] = e;
@@ -127,6 +128,8 @@ void sic_profile_enable(int on) {
     } catch (...) {
     }
 }
+
+void sic_profile_select(uint32_t mask) { sic::g.mask = mask; }
 
 void sic_profile_reset(void) {
     try {

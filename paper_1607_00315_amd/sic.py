@@ -145,6 +145,7 @@ SIGNATURES = {
     "sic_server_destroy": (None, [_P]),
     "sic_profile_enable": (None, [ct.c_int]),
     "sic_profile_reset": (None, []),
+    "sic_profile_select": (None, [ct.c_uint32]),
     "sic_profile_read": (ct.c_int, [ct.c_int, _i64p, _dp, _dp, _dp]),
     "sic_profile_kernel_name": (ct.c_char_p, [ct.c_int]),
     "sic_hierarchy": (ct.c_int, [ct.c_int64, _i64p, ct.c_int64, _i64p, _dp, ct.c_int64, _i64p,
@@ -571,6 +572,20 @@ def profile_enable(on=True):
 
 def profile_reset():
     lib().sic_profile_reset()
+
+
+def profile_select(names=None):
+    """Time only the named kernel classes (None: every class)."""
+    if names is None:
+        mask = (1 << KERNEL_CLASSES) - 1
+    else:
+        index = {lib().sic_profile_kernel_name(k).decode(): k for k in range(KERNEL_CLASSES)}
+        mask = 0
+        for nm in names:
+            if nm not in index:
+                raise ValueError(f"unknown kernel class {nm!r}")
+            mask |= 1 << index[nm]
+    lib().sic_profile_select(mask)
 
 
 def profile_read():

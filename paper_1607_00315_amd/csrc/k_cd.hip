@@ -552,7 +552,11 @@ __global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
 constexpr int CDP_THREADS = 1024;
 constexpr int CDP_WORKERS = CDP_THREADS - 64;
 constexpr int CDP_TILE = CDH_K * CDH_K;
-constexpr int CDP_TPT = (2 * CDP_TILE + CDP_WORKERS - 1) / CDP_WORKERS;   // tile loads per worker
+constexpr int CDP_CONST = 4 * CDH_K;   // a chunk's 1/a, A, S and W_rc, staged with its tiles
+constexpr int CDP_TPT = (2 * CDP_TILE + CDP_CONST + CDP_WORKERS - 1) / CDP_WORKERS;   // prefetch loads per worker
+// The step list is zero padded to a multiple of this, the column loads a worker
+// has in flight at once
+constexpr int CDP_PAD = 16;
 
 __device__ __forceinline__ double cd_soft(double y, double t) {
     return y > t ? y - t : (y < -t ? y + t : 0.0);
@@ -571,7 +575,8 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
     double* St = Dt + 2 * CDP_TILE;           // [2][64 x 64] H[chunk i][chunk i-1], [t][k]
     double* mud = St + 2 * CDP_TILE;          // [2][64] steps of the chunk, dense (0 when none)
     double* nzm = mud + 2 * CDH_K;            // [2][64] nonzero steps (zero padded)
-    int* nzl = (int*)(nzm + 2 * CDH_K);       // [2][64] their chunk positions
+    double* cst = nzm + 2 * CDH_K;            // [2][4][64] chunk i's 1/a, A, S, W_rc
+    int* nzl = (int*)(cst + 2 * CDP_CONST);   // [2][64] their chunk positions
     __shared__ int s_nnz[2];
     __shared__ int s_stop;
     const int tid = threadIdx.x;
@@ -582,20 +587,31 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
         const int64_t r = nc - (int64_t)c * CDH_K;
         return (int)(r < CDH_K ? r : CDH_K);
     };
-    // worker: load the tiles of chunk ci (and its predecessor cp) into registers
+    // worker: load the tiles of chunk ci (and its predecessor cp) and the
+    // constants of chunk ci into registers
     double treg[CDP_TPT];
     auto load_tiles = [&](int ci, int cp) {
         const int64_t ki = (int64_t)ci * CDH_K, kp = (int64_t)cp * CDH_K;
         const int Ki = klen(ci), Kp = klen(cp);
 #pragma unroll
         for (int r = 0; r < CDP_TPT; ++r) {
+            // one unconditional load per slot: a tile entry, a constant, or (past
+            // both) element 0 of H, discarded
             const int e = (tid - 64) + CDP_WORKERS * r;
+            const bool is_tile = e < 2 * CDP_TILE;
             const int which = e / CDP_TILE, f = e % CDP_TILE;
             const int t = f / CDH_K, k = f % CDH_K;
             const bool dtile = which == 0;
-            const bool ok = e < 2 * CDP_TILE && k < Ki && (dtile ? t < Ki : t < Kp);
             const int64_t col = (dtile ? ki : kp) + t;
-            treg[r] = load_or(HT, col * nc + ki + k, ok, 0.0);
+            const int g = e - 2 * CDP_TILE, gw = g / CDH_K, gk = g % CDH_K;
+            const double* src = !is_tile && gw == 0 ? c_inva
+                              : (!is_tile && gw == 1 ? c_A
+                              : (!is_tile && gw == 2 ? c_S
+                              : (!is_tile && gw == 3 ? c_wtc : HT)));
+            const int64_t idx = is_tile ? col * nc + ki + k : ki + gk;
+            const bool ok = is_tile ? (k < Ki && (dtile ? t < Ki : t < Kp))
+                                    : (g < CDP_CONST && gk < Ki);
+            treg[r] = load_or(src, idx, ok, 0.0);
         }
     };
     auto store_tiles = [&](int b) {
@@ -605,6 +621,8 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
             if (e < 2 * CDP_TILE) {
                 const int which = e / CDP_TILE, f = e % CDP_TILE;
                 (which == 0 ? Dt : St)[b * CDP_TILE + f] = treg[r];
+            } else if (e < 2 * CDP_TILE + CDP_CONST) {
+                cst[b * CDP_CONST + e - 2 * CDP_TILE] = treg[r];
             }
         }
     };
@@ -617,21 +635,8 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
         load_tiles(0, C - 1);
         store_tiles(0);
     }
-    // wave 0: the next chunk's per-coordinate constants, one coordinate per lane
-    double nIa = 0.0, nA = 0.0, nS = 0.0, nW = 0.0;
-    auto load_consts = [&](int c) {
-        const int64_t k = (int64_t)c * CDH_K + lane;
-        const bool on = k < nc;
-        nIa = load_or(c_inva, k, on, 0.0);
-        nA = load_or(c_A, k, on, 0.0);
-        nS = load_or(c_S, k, on, 0.0);
-        nW = load_or(c_wtc, k, on, 0.0);
-    };
-    if (wave == 0) {
-        load_consts(0);
-        // the chain is the critical path: let its wave win issue arbitration on its SIMD
-        __builtin_amdgcn_s_setprio(3);
-    }
+    // the chain is the critical path: let its wave win issue arbitration on its SIMD
+    if (wave == 0) __builtin_amdgcn_s_setprio(3);
     if (tid == 0) {
         s_nnz[0] = 0;
         s_nnz[1] = 0;
@@ -641,8 +646,13 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
 
     int sweeps = 0;
     double maxmu = 0.0;   // wave 0
-    long long tph[3] = {0, 0, 0};   // thread 0: step application, chain, barrier wait
-    long long tlast = wall_clock64();
+    // thread 0's phase clocks (step application, chain, barrier wait), in LDS:
+    // registers are the workers' load depth
+    __shared__ long long s_tph[4];
+    if (tid == 0) {
+        s_tph[0] = s_tph[1] = s_tph[2] = 0;
+        s_tph[3] = wall_clock64();
+    }
     int64_t g = 0;
     bool done = false;
     for (int sweep = 0; sweep < max_sweeps && !done; ++sweep) {
@@ -675,13 +685,13 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                     }
                     z += on ? (a[0] + a[1]) + (a[2] + a[3]) : 0.0;
                 }
-                if (tid == 0) { const long long now = wall_clock64(); tph[0] += now - tlast; tlast = now; }
-                // chain constants of this chunk, broadcast from LDS inside the chain
-                const double ia = on ? nIa : 0.0;
+                if (tid == 0) { const long long now = wall_clock64(); s_tph[0] += now - s_tph[3]; s_tph[3] = now; }
+                // chain constants of this chunk (staged with its tiles; zero past K)
+                const double* cb = cst + b * CDP_CONST;
+                const double ia = cb[lane];
                 const double d0 = on ? ds[kl] : 0.0;
-                const double xl = on ? nA + d0 : 0.0;
-                const double pv = on ? xl - (nS - nW) * ia : 0.0;
-                load_consts((i + 1) % C);
+                const double xl = on ? cb[CDH_K + lane] + d0 : 0.0;
+                const double pv = on ? xl - (cb[2 * CDH_K + lane] - cb[3 * CDH_K + lane]) * ia : 0.0;
                 const double* dt = Dt + b * CDP_TILE;
                 double mul = 0.0;
                 const int K4 = (K + 3) & ~3;
@@ -729,7 +739,7 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                     ol[pos] = lane;
                     om[pos] = mul;
                 }
-                const int npad = (nnz + CDH_PAD - 1) / CDH_PAD * CDH_PAD;
+                const int npad = (nnz + CDP_PAD - 1) / CDP_PAD * CDP_PAD;
                 if (lane >= nnz && lane < npad) {
                     ol[lane] = 0;
                     om[lane] = 0.0;
@@ -746,11 +756,17 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                         stats[2] = dm;
                     }
                 }
-                if (tid == 0) { const long long now = wall_clock64(); tph[1] += now - tlast; tlast = now; }
+                if (tid == 0) { const long long now = wall_clock64(); s_tph[1] += now - s_tph[3]; s_tph[3] = now; }
             } else {
+                // next interval's tiles and constants (chunk i+1 and its predecessor
+                // i), issued first so that their latency hides behind the column
+                // stream (with two rows per thread the registers do not allow it:
+                // then they follow the stream and hide behind the chain)
+                constexpr bool early = ROWS == 1;
+                if (early) load_tiles((i + 1) % C, i);
                 // steps of the previous chunk onto every row outside chunks cp and i
                 if (have_prev && C > 2) {
-                    const int np = (s_nnz[pb] + CDH_PAD - 1) / CDH_PAD * CDH_PAD;
+                    const int np = (s_nnz[pb] + CDP_PAD - 1) / CDP_PAD * CDP_PAD;
                     const double* pm = nzm + pb * CDH_K;
                     const int* pl = nzl + pb * CDH_K;
                     const double* hcol = HT + kp0 * nc;
@@ -770,7 +786,7 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                     }
                     // the column index is the same in every lane: a scalar base address
                     // plus a 32-bit row offset per load
-                    constexpr int BATCH = 16 / ROWS;
+                    constexpr int BATCH = CDP_PAD / ROWS;
 #pragma unroll 1
                     for (int q0 = 0; q0 < np; q0 += BATCH) {
                         double hv[ROWS][BATCH];
@@ -792,13 +808,11 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                     for (int r = 0; r < ROWS; ++r)
                         if (rv[r]) zs[rk[r]] += acc[r];
                 }
-                // next interval's tiles (chunk i+1 and its predecessor i); their latency
-                // hides behind the chain
-                load_tiles((i + 1) % C, i);
+                if (!early) load_tiles((i + 1) % C, i);
                 store_tiles(pb);
             }
             lds_barrier();
-            if (tid == 0) { const long long now = wall_clock64(); tph[2] += now - tlast; tlast = now; }
+            if (tid == 0) { const long long now = wall_clock64(); s_tph[2] += now - s_tph[3]; s_tph[3] = now; }
             if (i == C - 1) {
                 ++sweeps;
                 if (s_stop) {
@@ -811,7 +825,7 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
     for (int64_t k = tid; k < nc; k += CDP_THREADS) delta[k] = ds[k];
     if (tid == 0) {
         stats[0] = (double)sweeps;
-        for (int i = 0; i < 3; ++i) stats[3 + i] = (double)tph[i];
+        for (int i = 0; i < 3; ++i) stats[3 + i] = (double)s_tph[i];
         stats[6] = 0.0;
     }
 }
@@ -871,7 +885,7 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
 int64_t cd_hessian_limit() { return (int64_t)CDH_RMAX * CDH_THREADS; }
 
 size_t cd_pipe_lds_bytes(int64_t ncoord) {
-    return sizeof(double) * ((size_t)2 * ncoord + 4 * CDP_TILE + 4 * CDH_K) +
+    return sizeof(double) * ((size_t)2 * ncoord + 4 * CDP_TILE + 4 * CDH_K + 2 * CDP_CONST) +
            sizeof(int) * 2 * CDH_K;
 }
 

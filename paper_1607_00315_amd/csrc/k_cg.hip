@@ -45,23 +45,34 @@ __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __r
 
 template <typename V>
 __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __restrict__ cols,
-                          const double* __restrict__ dinv, V* __restrict__ R,
-                          V* __restrict__ Z, double* __restrict__ scal,
+                          const double* __restrict__ dinv, double* __restrict__ W,
+                          V* __restrict__ R, V* __restrict__ Z, double* __restrict__ scal,
                           int* __restrict__ tctl, double* __restrict__ tres) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < k) {
-        const int64_t c = cols[j];
-        R[c * k + j] = (V)1.0;
-        Z[c * k + j] = (V)dinv[c];
-        scal[j * 4 + S_RZ0] = dinv[c];
-        scal[j * 4 + S_RZ1] = 0.0;
-        scal[j * 4 + 2] = 0.0;
-        scal[j * 4 + S_RR] = 1.0;
+    // x0 = 0, r0 = e_cols[j], z0 = D^{-1} r0 over the whole n x k block (rows
+    // over workgroups, columns over threads)
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const double di = dinv[i];
+        for (int j = threadIdx.x; j < k; j += blockDim.x) {
+            const int64_t o = i * k + j;
+            const bool unit = cols[j] == i;
+            W[o] = 0.0;
+            R[o] = unit ? (V)1.0 : (V)0.0;
+            Z[o] = unit ? (V)di : (V)0.0;
+        }
     }
-    if (j < col_tiles) {
-        tctl[j * T_INTS + T_DONE] = 0;
-        tctl[j * T_INTS + T_ITER] = 0;
-        tres[j] = 1.0;
+    if (blockIdx.x == 0) {
+        for (int j = threadIdx.x; j < k; j += blockDim.x) {
+            const int64_t c = cols[j];
+            scal[j * 4 + S_RZ0] = dinv[c];
+            scal[j * 4 + S_RZ1] = 0.0;
+            scal[j * 4 + 2] = 0.0;
+            scal[j * 4 + S_RR] = 1.0;
+        }
+        for (int j = threadIdx.x; j < col_tiles; j += blockDim.x) {
+            tctl[j * T_INTS + T_DONE] = 0;
+            tctl[j * T_INTS + T_ITER] = 0;
+            tres[j] = 1.0;
+        }
     }
 }
 
@@ -300,7 +311,7 @@ constexpr int CG_REPLACE_EVERY = 8;   // float vectors: true residual every this
 template <typename V>
 CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
                        double tol, int max_iter, CGWork& wk, V* R, V* Z, V* P, V* Q,
-                       hipStream_t s) {
+                       hipStream_t s, int slot) {
     constexpr bool LOW = sizeof(V) < sizeof(double);
     CGResult res;
     const int64_t n = A.n;
@@ -309,7 +320,6 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
         return res;
     }
     if (ldw != k) throw SicError(SIC_EINTERNAL, "block_cg expects ldw == k");
-    const size_t nk = (size_t)n * (size_t)k;
     wk.dinv.reserve(n);
     const int col_tiles = (k + 63) / 64;
     int row_tiles = (int)std::min<int64_t>(CG_ROW_TILES, (n + CG_WAVES - 1) / CG_WAVES);
@@ -321,23 +331,22 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
     wk.scal.reserve((size_t)4 * k + col_tiles);
     wk.flags.reserve((size_t)T_INTS * col_tiles);
     double* tres = wk.scal.p + 4 * k;
-    SIC_HIP(hipMemsetAsync(W, 0, nk * sizeof(double), s));
-    SIC_HIP(hipMemsetAsync(R, 0, nk * sizeof(V), s));
-    SIC_HIP(hipMemsetAsync(Z, 0, nk * sizeof(V), s));
     hipLaunchKernelGGL(k_cg_dinv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        A.rowptr.p, A.col.p, A.val.p, n, wk.dinv.p);
     SIC_CHECK_LAUNCH();
-    const int init_n = std::max(k, col_tiles);
-    hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0, s, n,
-                       k, col_tiles, d_cols, wk.dinv.p, R, Z, wk.scal.p, wk.flags.p, tres);
+    hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, s,
+                       n, k, col_tiles, d_cols, wk.dinv.p, W, R, Z, wk.scal.p, wk.flags.p, tres);
     SIC_CHECK_LAUNCH();
     dim3 grid(col_tiles, row_tiles);
     // XCD grouping of the product's tiles once there are enough column tiles to
     // give every XCD one (fewer would leave XCDs idle)
     const int grouped = col_tiles >= 8 ? 1 : 0;
     const dim3 sgrid = grouped ? dim3((unsigned)(8 * ((col_tiles + 7) / 8) * row_tiles)) : grid;
-    std::vector<int> hctl((size_t)T_INTS * col_tiles);
-    std::vector<double> hres(col_tiles);
+    wk.hctl.reserve((size_t)T_INTS * col_tiles);
+    wk.hres.reserve(col_tiles);
+    const int* hctl = wk.hctl.p;
+    const double* hres = wk.hres.p;
+    int& predicted = wk.predict[(slot & 3) * 2 + (LOW ? 1 : 0)];
     int launched = 0;
     int active = col_tiles;   // tiles still iterating (as of the last check)
     // algorithmic traffic of one tile-launch (bytes): the sparse matrix once,
@@ -350,7 +359,11 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
     std::vector<Rec> recs;
     bool done = false;
     while (launched < max_iter && !done) {
-        const int chunk = std::min(launched < 16 ? 4 : 8, max_iter - launched);
+        // the first check where the last solve of this kind converged (its last
+        // update is tested by the next launch's product), then every 4 or 8
+        const int first = predicted > 0 ? predicted + 1 : 4;
+        const int chunk = std::min(launched == 0 ? first : (launched < 16 ? 4 : 8),
+                                   max_iter - launched);
         recs.clear();
         for (int c = 0; c < chunk; ++c) {
             const int it = launched + c;
@@ -385,9 +398,9 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
                                part_pq, wk.flags.p, tres, tol, launched, col_tiles, row_tiles, 0, 1);
             SIC_CHECK_LAUNCH();
         }
-        SIC_HIP(hipMemcpyAsync(hctl.data(), wk.flags.p, sizeof(int) * hctl.size(),
+        SIC_HIP(hipMemcpyAsync(wk.hctl.p, wk.flags.p, sizeof(int) * T_INTS * col_tiles,
                                hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(hres.data(), tres, sizeof(double) * col_tiles,
+        SIC_HIP(hipMemcpyAsync(wk.hres.p, tres, sizeof(double) * col_tiles,
                                hipMemcpyDeviceToHost, s));
         SIC_HIP(hipStreamSynchronize(s));
         // a launch did work only for the tiles still iterating at its index:
@@ -422,13 +435,15 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
     res.iterations = iters;
     res.converged = done;
     res.max_rel_res = mres;
+    predicted = done ? iters : 0;
     return res;
 }
 
 }  // namespace
 
 CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
-                  double tol, int max_iter, CGWork& wk, hipStream_t s, bool low_precision) {
+                  double tol, int max_iter, CGWork& wk, hipStream_t s, bool low_precision,
+                  int slot) {
     const size_t nk = (size_t)A.n * (size_t)std::max(k, 1);
     if (low_precision) {
         wk.R32.reserve(nk);
@@ -436,14 +451,14 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
         wk.P32.reserve(nk);
         wk.Q32.reserve(nk);
         return block_cg_impl<float>(A, d_cols, k, W, ldw, tol, max_iter, wk, wk.R32.p, wk.Z32.p,
-                                    wk.P32.p, wk.Q32.p, s);
+                                    wk.P32.p, wk.Q32.p, s, slot);
     }
     wk.R.reserve(nk);
     wk.Z.reserve(nk);
     wk.P.reserve(nk);
     wk.Q.reserve(nk);
     return block_cg_impl<double>(A, d_cols, k, W, ldw, tol, max_iter, wk, wk.R.p, wk.Z.p, wk.P.p,
-                                 wk.Q.p, s);
+                                 wk.Q.p, s, slot);
 }
 
 }  // namespace sic

@@ -522,11 +522,12 @@ __global__ void k_ls_e(const double* __restrict__ D1, const double* __restrict__
     }
 }
 
+// Trial steps are alpha = 2^-(first + trial), formed exactly on the device.
 __global__ void k_ls_trials(const double* __restrict__ E1, const double* __restrict__ E2, int b,
-                            const double* __restrict__ alphas, double* __restrict__ C) {
+                            int first, double* __restrict__ C) {
     const int trial = blockIdx.y;
     const int i = blockIdx.x;
-    const double a = alphas[trial];
+    const double a = ldexp(1.0, -(first + trial));
     double* Ct = C + (int64_t)trial * b * b;
     for (int j = threadIdx.x; j < b; j += blockDim.x) {
         const int64_t o = (int64_t)i * b + j;
@@ -551,10 +552,9 @@ __global__ __launch_bounds__(256) void k_ls_linear(int64_t ncoord, const int32_t
                                                    const double* __restrict__ c_S,
                                                    const double* __restrict__ c_A,
                                                    const double* __restrict__ delta, double lam,
-                                                   const double* __restrict__ alphas,
-                                                   double* __restrict__ lin) {
+                                                   int first, double* __restrict__ lin) {
     __shared__ double red[256];
-    const double a = alphas[blockIdx.x];
+    const double a = ldexp(1.0, -(first + (int)blockIdx.x));
     double s = 0.0;
     for (int64_t t = threadIdx.x; t < ncoord; t += 256) {
         const double w = (c_p[t] == c_ci[t]) ? 1.0 : 2.0;
@@ -661,17 +661,17 @@ void launch_ls_e(const double* D1, const double* X, const double* XtX, const dou
     SIC_CHECK_LAUNCH();
 }
 
-void launch_ls_trials(const double* E1, const double* E2, int b, const double* alphas, int ntrial,
+void launch_ls_trials(const double* E1, const double* E2, int b, int first, int ntrial,
                       double* C, hipStream_t s) {
-    hipLaunchKernelGGL(k_ls_trials, dim3(b, ntrial), dim3(256), 0, s, E1, E2, b, alphas, C);
+    hipLaunchKernelGGL(k_ls_trials, dim3(b, ntrial), dim3(256), 0, s, E1, E2, b, first, C);
     SIC_CHECK_LAUNCH();
 }
 
 void launch_ls_linear(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, const double* c_S,
-                      const double* c_A, const double* delta, double lam, const double* alphas,
+                      const double* c_A, const double* delta, double lam, int first,
                       int ntrial, double* lin, hipStream_t s) {
     hipLaunchKernelGGL(k_ls_linear, dim3(ntrial), dim3(256), 0, s, ncoord, c_p, c_ci, c_S, c_A, delta,
-                       lam, alphas, lin);
+                       lam, first, lin);
     SIC_CHECK_LAUNCH();
 }
 

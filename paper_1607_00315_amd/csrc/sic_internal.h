@@ -96,6 +96,33 @@ struct DevBuf {
     }
 };
 
+// Pinned host buffer with grow-only capacity, for read-backs the host waits on
+// (a copy into pageable memory goes through a staging buffer and its own wait).
+template <typename T>
+struct HostBuf {
+    T* p = nullptr;
+    size_t cap = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+    ~HostBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void reserve(size_t count) {
+        if (count <= cap && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t c = count ? count : 1;
+        if (hipHostMalloc((void**)&p, c * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw SicError(SIC_ENOMEM, "pinned host allocation failed");
+        }
+        cap = c;
+    }
+};
+
 // Symmetric sparse matrix on the device: full CSR (both triangles), sorted columns.
 struct DevCSR {
     int64_t n = 0, nnz = 0;
@@ -122,6 +149,11 @@ struct CGWork {
     DevBuf<double> R, Z, P, Q, dinv, part, scal;
     DevBuf<float> R32, Z32, P32, Q32;   // the float vectors of the reduced-precision CG
     DevBuf<int32_t> flags;
+    HostBuf<int32_t> hctl;              // per-tile control words, read back at each check
+    HostBuf<double> hres;               // per-tile relative residuals
+    // iterations of the last solve of each kind (caller's slot x precision): the
+    // first convergence check comes when a solve like it would have converged
+    int predict[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 struct CGResult {
     int iterations = 0;
@@ -130,9 +162,10 @@ struct CGResult {
 };
 // low_precision: float vectors with float64 iterate, scalars and sums, and the
 // true residual recomputed in float64 every few iterations (tol >= ~1e-6).
+// slot (0..3) names the caller's kind of solve for the iteration prediction.
 CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
                   double tol, int max_iter, CGWork& wk, hipStream_t s,
-                  bool low_precision = false);
+                  bool low_precision = false, int slot = 0);
 
 // ---------------------------------------------------------------- k_util.hip
 void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* total, hipStream_t s);
@@ -231,10 +264,11 @@ void launch_ls_terms(const int64_t* cptr, const int32_t* c_p, const double* delt
                      double* P, hipStream_t s);
 void launch_ls_e(const double* D1, const double* X, const double* XtX, const double* RPR, int b,
                  double* E1, double* E2, hipStream_t s);
-void launch_ls_trials(const double* E1, const double* E2, int b, const double* alphas, int ntrial,
+// Trial steps alpha = 2^-(first + t), t < ntrial (formed on the device).
+void launch_ls_trials(const double* E1, const double* E2, int b, int first, int ntrial,
                       double* C, hipStream_t s);
 void launch_ls_linear(int64_t ncoord, const int32_t* c_p, const int32_t* c_ci, const double* c_S,
-                      const double* c_A, const double* delta, double lam, const double* alphas,
+                      const double* c_A, const double* delta, double lam, int first,
                       int ntrial, double* lin, hipStream_t s);
 void launch_identity_minus(const double* K, int b, double* out, hipStream_t s);
 

@@ -39,7 +39,7 @@ struct BlockWork {
     DevBuf<int32_t> c_p, c_e, c_ci, c_gr, c_gc;
     DevBuf<double> c_S, c_A, c_a, c_inva, c_wtc, c_wtt, delta, mu, cdstats;
     // line search
-    DevBuf<double> Dinv, Rb, D11, Mo, Y, Pm, T1, D1, X, XtX, RPR, E1, E2, C, chol_out, alphas, lin;
+    DevBuf<double> Dinv, Rb, D11, Mo, Y, Pm, T1, D1, X, XtX, RPR, E1, E2, C, chol_out;
     // coarse levels
     DevBuf<int32_t> cand_col, cflag, cmap, NC, err;
     DevBuf<double> S_cand, WNC, WII, Kb, AII;
@@ -98,7 +98,10 @@ struct Context {
     BlockWork work;
     sic_trace_entry* trace = nullptr;
     int trace_cap = 0;
-    // pinned staging for small device-to-host reads
+    // pinned staging for small device-to-host reads (64 entries each):
+    //   h_i64[0] counts, [8] the rebuilt CSR's entry count, [16] the coarse-level
+    //   error flag (int32); h_f64[0, 26) line-search trials, [32] the PCD stop
+    //   flag, [40, 47) sweep statistics, [48, 50) the coarse A_II factor's flags
     int64_t* h_i64 = nullptr;
     double* h_f64 = nullptr;
     BlockResult last;

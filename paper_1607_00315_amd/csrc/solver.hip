@@ -87,9 +87,8 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN) {
     W.RPR.reserve(bb); W.E1.reserve(bb); W.E2.reserve(bb);
     W.Y.reserve((size_t)std::max<int64_t>(nN, 1) * b);
     W.C.reserve(LS_BATCH * bb);
-    W.chol_out.reserve(2 + 2 * LS_BATCH);
-    W.alphas.reserve(LS_BATCH);
-    W.lin.reserve(LS_BATCH);
+    // chol_out: W_II's log det and PD flag, two per trial, then the trials' linear terms
+    W.chol_out.reserve(2 + 3 * LS_BATCH);
     // R R^T = W_II
     launch_copy_block(W.WJJ.p, jp, b, W.Rb.p, s);
     launch_chol(W.Rb.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s, W.Dinv.p);
@@ -110,26 +109,27 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN) {
     launch_ls_e(W.D1.p, W.X.p, W.XtX.p, W.RPR.p, b, W.E1.p, W.E2.p, s);
 }
 
-// Evaluate nt <= LS_BATCH trial steps: log det change, PD flag, linear terms.
+// Evaluate the nt <= LS_BATCH trial steps alpha = 2^-(first + t): log det
+// change, PD flag, linear terms, read back in one copy to pinned memory.
 // Returns whether W_II itself factored (positive definite).
-bool ls_eval(Context& C, int b, int64_t ncoord, double lam, const double* al, int nt,
+bool ls_eval(Context& C, int b, int64_t ncoord, double lam, int first, int nt,
              double* logdet, int* pd, double* lin) {
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
     const size_t bb = (size_t)b * b;
-    double h_out[2 + 2 * LS_BATCH];
-    SIC_HIP(hipMemcpyAsync(W.alphas.p, al, sizeof(double) * nt, hipMemcpyHostToDevice, s));
-    launch_ls_trials(W.E1.p, W.E2.p, b, W.alphas.p, nt, W.C.p, s);
+    double* dlin = W.chol_out.p + 2 + 2 * LS_BATCH;
+    launch_ls_trials(W.E1.p, W.E2.p, b, first, nt, W.C.p, s);
     launch_chol(W.C.p, (int64_t)bb, nt, b, b, 1, W.chol_out.p + 2, s);
-    launch_ls_linear(ncoord, W.c_p.p, W.c_ci.p, W.c_S.p, W.c_A.p, W.delta.p, lam, W.alphas.p, nt,
-                     W.lin.p, s);
-    SIC_HIP(hipMemcpyAsync(h_out, W.chol_out.p, sizeof(double) * (2 + 2 * nt),
+    launch_ls_linear(ncoord, W.c_p.p, W.c_ci.p, W.c_S.p, W.c_A.p, W.delta.p, lam, first, nt,
+                     dlin, s);
+    double* h_out = C.h_f64;   // 2 + 3 LS_BATCH doubles of the pinned staging
+    SIC_HIP(hipMemcpyAsync(h_out, W.chol_out.p, sizeof(double) * (2 + 3 * LS_BATCH),
                            hipMemcpyDeviceToHost, s));
-    SIC_HIP(hipMemcpyAsync(lin, W.lin.p, sizeof(double) * nt, hipMemcpyDeviceToHost, s));
     sync(C);
     for (int t = 0; t < nt; ++t) {
         logdet[t] = h_out[2 + 2 * t];
         pd[t] = h_out[2 + 2 * t + 1] != 0.0;
+        lin[t] = h_out[2 + 2 * LS_BATCH + t];
     }
     return h_out[1] != 0.0;
 }
@@ -150,7 +150,7 @@ LineSearch line_search(Context& C, double lam, int jp, int b, int64_t nN, int64_
         double al[LS_BATCH], ld[LS_BATCH], lin[LS_BATCH];
         int pd[LS_BATCH];
         for (int t = 0; t < nt; ++t) al[t] = std::ldexp(1.0, -(i + t));
-        res.wii_pd = ls_eval(C, b, ncoord, lam, al, nt, ld, pd, lin);
+        res.wii_pd = ls_eval(C, b, ncoord, lam, i, nt, ld, pd, lin);
         if (!res.wii_pd) break;
         for (int t = 0; t < nt; ++t) {
             res.trials++;
@@ -421,7 +421,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         cov_block(C, P, j0, b, W.SJ.p);
         launch_iota_i32(W.cols.p, b, (int32_t)j0, s);
         CGResult cg = block_cg(A, W.cols.p, b, W.WI.p, b, tolI, C.opt.cg_max_iter, W.cg, s,
-                               C.prec != PREC_F64);
+                               C.prec != PREC_F64, 0);
         R.cg_iters_I = cg.iterations;
         R.cg_res_I = cg.max_rel_res;
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
@@ -458,14 +458,14 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         W.WNC.reserve((size_t)n * std::max<int64_t>(nC, 1));
         if (nC > 0) {
             CGResult cg = block_cg(A, W.NC.p, (int)nC, W.WNC.p, nC, tolI, C.opt.cg_max_iter, W.cg,
-                                   s, C.prec != PREC_F64);
+                                   s, C.prec != PREC_F64, 2);
             R.cg_iters_N = cg.iterations;
             R.cg_res_N = cg.max_rel_res;
         }
         const size_t bb = (size_t)b * b;
         W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb); W.Dinv.reserve(8 * 1024);
         W.err.reserve(1);
-        W.chol_out.reserve(2 + 2 * LS_BATCH);
+        W.chol_out.reserve(2 + 3 * LS_BATCH);
         SIC_HIP(hipMemsetAsync(W.err.p, 0, sizeof(int32_t), s));
         launch_a2_k(A, j0, b, W.WNC.p, nC, W.cmap.p, W.Kb.p, W.err.p, s);
         launch_dense_aii(A, j0, b, W.AII.p, s);
@@ -474,12 +474,12 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         launch_identity_minus(W.Kb.p, b, W.WII.p, s);
         launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 0, s);
         launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 1, s);
-        double h[2];
-        int32_t herr = 0;
+        double* h = C.h_f64 + 48;                          // pinned staging
+        int32_t* herr = reinterpret_cast<int32_t*>(C.h_i64 + 16);
         SIC_HIP(hipMemcpyAsync(h, W.chol_out.p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(&herr, W.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(herr, W.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         sync(C);
-        if (herr) throw SicError(SIC_EINTERNAL, "support of A is not inside the level set");
+        if (*herr) throw SicError(SIC_EINTERNAL, "support of A is not inside the level set");
         if (h[1] == 0.0) throw SicError(SIC_ENOTPD, "diagonal block of A is not positive definite");
         launch_screen_coarse(0, P.crow.p, P.ccol.p, base, j0, b, P.lam, W.S_cand.p, W.WII.p,
                              W.WNC.p, nC, W.cmap.p, W.AJ.p, W.ccount.p, nullptr, nullptr, nullptr,
@@ -519,7 +519,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     if (fine && nN > 0) {
         W.WN.reserve((size_t)n * nN);
         CGResult cg = block_cg(A, W.Jp.p + b, (int)nN, W.WN.p, nN, tolN, C.opt.cg_max_iter, W.cg,
-                               s, C.prec != PREC_F64);
+                               s, C.prec != PREC_F64, 1);
         R.cg_iters_N = cg.iterations;
         R.cg_res_N = cg.max_rel_res;
     }
@@ -800,7 +800,8 @@ double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1) {
         launch_scatter_aj(P.Acur(), j0, bb, W.AJ.p, s);
         launch_sj_gemm_f64(P.X.p, n, P.m, j0, bb, W.SJ.p, s);
         launch_iota_i32(W.cols.p, bb, (int32_t)j0, s);
-        block_cg(P.Acur(), W.cols.p, bb, W.WI.p, bb, tol_cg, C.opt.cg_max_iter * 4, W.cg, s);
+        block_cg(P.Acur(), W.cols.p, bb, W.WI.p, bb, tol_cg, C.opt.cg_max_iter * 4, W.cg, s,
+                 false, 3);
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
         W.tilecount.reserve((size_t)tiles * bb);
         W.kkt.reserve(2 * (size_t)tiles);
@@ -985,10 +986,9 @@ int step_ls_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cp
     if (trials) *trials = ls.trials;
     for (int i = 0; logdet_out && i < n_alpha; i += 4) {
         const int nt = std::min(4, n_alpha - i);
-        double al[4], ld[4], lin[4];
+        double ld[4], lin[4];
         int pd[4];
-        for (int t = 0; t < nt; ++t) al[t] = std::ldexp(1.0, -(i + t));
-        ls_eval(C, b, nc, lambda, al, nt, ld, pd, lin);
+        ls_eval(C, b, nc, lambda, i, nt, ld, pd, lin);
         for (int t = 0; t < nt; ++t) logdet_out[i + t] = pd[t] ? ld[t] : NAN;
     }
     return SIC_OK;

@@ -89,6 +89,9 @@ void context_init(Context& C, const sic_options& o) {
         SIC_HIP(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
         C.own_stream = true;
     }
+    SIC_HIP(hipStreamCreateWithFlags(&C.side, hipStreamNonBlocking));
+    SIC_HIP(hipEventCreateWithFlags(&C.ev_fork, hipEventDisableTiming));
+    SIC_HIP(hipEventCreateWithFlags(&C.ev_join, hipEventDisableTiming));
     SIC_HIP(hipHostMalloc((void**)&C.h_i64, 64 * sizeof(int64_t), hipHostMallocDefault));
     SIC_HIP(hipHostMalloc((void**)&C.h_f64, 64 * sizeof(double), hipHostMallocDefault));
     opts_from(C, o);
@@ -97,7 +100,14 @@ void context_init(Context& C, const sic_options& o) {
 void context_release(Context& C) {
     (void)hipSetDevice(C.device);
     if (C.stream) (void)hipStreamSynchronize(C.stream);
+    if (C.side) (void)hipStreamSynchronize(C.side);
     if (C.own_stream && C.stream) (void)hipStreamDestroy(C.stream);
+    if (C.side) (void)hipStreamDestroy(C.side);
+    if (C.ev_fork) (void)hipEventDestroy(C.ev_fork);
+    if (C.ev_join) (void)hipEventDestroy(C.ev_join);
+    C.side = nullptr;
+    C.ev_fork = nullptr;
+    C.ev_join = nullptr;
     if (C.h_i64) (void)hipHostFree(C.h_i64);
     if (C.h_f64) (void)hipHostFree(C.h_f64);
     C.stream = nullptr;

@@ -402,7 +402,7 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
                                hipMemcpyDeviceToHost, s));
         SIC_HIP(hipMemcpyAsync(wk.hres.p, tres, sizeof(double) * col_tiles,
                                hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipStreamSynchronize(s));
+        stream_wait(s);
         // a launch did work only for the tiles still iterating at its index:
         // scale its algorithmic bytes, drop launches that found nothing to do
         for (const Rec& r : recs) {

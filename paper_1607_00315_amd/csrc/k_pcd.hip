@@ -298,10 +298,9 @@ __global__ __launch_bounds__(64) void k_pcd_alpha(int nwg, const double* __restr
                                                   double lam, double* __restrict__ sc) {
     if (sc[SC_DONE] != 0.0) return;
     const int j = threadIdx.x;
-    double B = 0.0, C = 0.0, Lj = 0.0;
+    double C = 0.0, Lj = 0.0;
     for (int k = 0; k < nwg; ++k) {
         const double* p = part + (int64_t)k * ZPP;
-        B += p[0];
         C += p[1];
         Lj += p[3 + j];
     }
@@ -410,7 +409,7 @@ int64_t launch_pcd(int64_t nc, int jp, int b, const int64_t* cptr, const int32_t
         cur = nx;
         if ((it & 3) == 3) {
             SIC_HIP(hipMemcpyAsync(h_flag, wk.sc.p + SC_DONE, sizeof(double), hipMemcpyDeviceToHost, s));
-            SIC_HIP(hipStreamSynchronize(s));
+            stream_wait(s);
             if (*h_flag != 0.0) break;
         }
     }

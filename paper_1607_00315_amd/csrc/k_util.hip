@@ -55,58 +55,73 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_i32(const int32_t* __rest
 
 // Scan of per-(tile, column) counts in column-major order (column outer,
 // tile inner): offsets[tile*b + c] = number of entries of columns < c plus
-// entries of column c in tiles < tile. colptr[c] = offsets[0*b + c].
+// entries of column c in tiles < tile. colptr[c] = offsets[0*b + c], and
+// colptr[b] the total. b <= 256: thread t takes column t % 256 over a quarter
+// of the tiles (group t / 256), so every load reads a contiguous row segment
+// of the count matrix: column sums by quarter, an exclusive scan of the column
+// totals, then the offsets in a second pass.
+constexpr int CM_COLS = 256;
+constexpr int CM_GROUPS = SCAN_THREADS / CM_COLS;
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* __restrict__ cnt,
                                                                 int tiles, int b,
                                                                 int32_t* __restrict__ offsets,
                                                                 int64_t* __restrict__ colptr) {
-    __shared__ int64_t sums[SCAN_THREADS];
+    __shared__ int64_t part[CM_GROUPS][CM_COLS];
+    __shared__ int64_t cs[CM_COLS];
     const int t = threadIdx.x;
-    const int64_t count = (int64_t)tiles * b;
-    const int64_t chunk = (count + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int64_t b0 = t * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
-    // the chunk walks columns tile by tile (strided gathers): eight loads in
-    // flight per batch, clamped to the chunk's first entry past its end
-    constexpr int G = 8;
-    auto gather = [&](int64_t q0, int32_t* v) {
+    const int c = t % CM_COLS, g = t / CM_COLS;
+    const bool on = c < b;
+    const int tile0 = (int)((int64_t)g * tiles / CM_GROUPS);
+    const int tile1 = (int)((int64_t)(g + 1) * tiles / CM_GROUPS);
+    constexpr int G = 8;   // loads in flight per batch, clamped to a valid entry
+    auto gather = [&](int q0, int32_t* v) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-            const int64_t q = q0 + u < b1 ? q0 + u : b0;
-            const int64_t c = q / tiles, tile = q % tiles;
-            v[u] = cnt[tile * b + c];
+            const int tile = q0 + u < tile1 ? q0 + u : tile0;
+            v[u] = cnt[(int64_t)tile * b + (on ? c : 0)];
         }
     };
     int64_t s = 0;
-    for (int64_t q0 = b0; q0 < b1; q0 += G) {
+    for (int q0 = tile0; q0 < tile1; q0 += G) {
         int32_t v[G];
         gather(q0, v);
 #pragma unroll
         for (int u = 0; u < G; ++u)
-            if (q0 + u < b1) s += v[u];
+            if (q0 + u < tile1) s += v[u];
     }
-    sums[t] = s;
+    part[g][c] = on ? s : 0;
     __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        int64_t v = t >= off ? sums[t - off] : 0;
+    // column totals, then their inclusive scan over the columns (group 0)
+    if (g == 0) {
+        int64_t tot = 0;
+        for (int q = 0; q < CM_GROUPS; ++q) tot += part[q][c];
+        cs[c] = tot;
+    }
+    __syncthreads();
+    for (int off = 1; off < CM_COLS; off <<= 1) {
+        const int64_t v = (g == 0 && c >= off) ? cs[c - off] : 0;
         __syncthreads();
-        sums[t] += v;
+        if (g == 0) cs[c] += v;
         __syncthreads();
     }
-    int64_t run = t > 0 ? sums[t - 1] : 0;
-    for (int64_t q0 = b0; q0 < b1; q0 += G) {
+    // this thread's start: entries of columns < c, then of column c in earlier quarters
+    int64_t run = c > 0 ? cs[c - 1] : 0;
+    for (int q = 0; q < g; ++q) run += part[q][c];
+    if (g == 0 && on) colptr[c] = run;
+    if (t == 0) colptr[b] = cs[b - 1];
+    for (int q0 = tile0; q0 < tile1; q0 += G) {
         int32_t v[G];
         gather(q0, v);
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-            const int64_t q = q0 + u;
-            if (q >= b1) break;
-            const int64_t c = q / tiles, tile = q % tiles;
-            offsets[tile * b + c] = (int32_t)run;
-            if (tile == 0) colptr[c] = run;
-            run += v[u];
+            const int tile = q0 + u;
+            if (tile < tile1 && on) {
+                offsets[(int64_t)tile * b + c] = (int32_t)run;
+                run += v[u];
+            }
         }
     }
-    if (t == SCAN_THREADS - 1) colptr[b] = sums[t];
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t count, int32_t v) {
@@ -128,6 +143,8 @@ void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* to
 
 void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets, int64_t* colptr,
                           hipStream_t s) {
+    if (b < 1 || b > CM_COLS || tiles < 1)
+        throw SicError(SIC_EINTERNAL, "column-major scan: 1 <= b <= 256 and tiles >= 1 required");
     hipLaunchKernelGGL(k_scan_colmajor, dim3(1), dim3(SCAN_THREADS), 0, s, cnt, tiles, b, offsets,
                        colptr);
     SIC_CHECK_LAUNCH();

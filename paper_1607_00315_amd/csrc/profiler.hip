@@ -44,8 +44,9 @@ hipEvent_t take_event() {
 
 void resolve() {
     if (g.pending.empty()) return;
-    SIC_HIP(hipEventSynchronize(g.pending.back().e1));
     for (Pending& p : g.pending) {
+        // launches on two streams: each record's own end event
+        SIC_HIP(hipEventSynchronize(p.e1));
         if (p.kind >= 0) {
             float ms = 0.f;
             SIC_HIP(hipEventElapsedTime(&ms, p.e0, p.e1));

@@ -53,6 +53,12 @@ struct AccountScope {
   private:
     std::shared_ptr<MemAccount> prev_;
 };
+// Waits for everything queued on stream s (of the current device) so far:
+// polls an event for up to two milliseconds (the host sees completion within
+// microseconds, where a blocking wait can sleep through tens of them), then
+// blocks. The solver's read-backs, all on the critical path, wait this way.
+void stream_wait(hipStream_t s);
+
 // Largest dynamic LDS a workgroup may use on the current device.
 extern size_t CD_MAX_LDS_BYTES;
 

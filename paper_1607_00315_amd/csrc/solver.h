@@ -91,6 +91,10 @@ struct Problem {
 struct Context {
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream of the context: work of a block update that can run beside
+    // the main stream's (forked after, and joined before, events on the main one)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool own_stream = false;
     Options opt;
     size_t budget = 0;
@@ -99,7 +103,7 @@ struct Context {
     sic_trace_entry* trace = nullptr;
     int trace_cap = 0;
     // pinned staging for small device-to-host reads (64 entries each):
-    //   h_i64[0] counts, [8] the rebuilt CSR's entry count, [16] the coarse-level
+    //   h_i64[0, 3) counts, [8] the rebuilt CSR's entry count, [16] the coarse-level
     //   error flag (int32); h_f64[0, 26) line-search trials, [32] the PCD stop
     //   flag, [40, 47) sweep statistics, [48, 50) the coarse A_II factor's flags
     int64_t* h_i64 = nullptr;

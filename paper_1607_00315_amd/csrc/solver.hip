@@ -40,16 +40,45 @@ AccountScope::AccountScope(const std::shared_ptr<MemAccount>& a) : prev_(t_accou
 }
 AccountScope::~AccountScope() { t_account = prev_; }
 
+void stream_wait(hipStream_t s) {
+    // one event per host thread and device (serving threads wait concurrently)
+    thread_local std::vector<std::pair<int, hipEvent_t>> events;
+    int dev = 0;
+    SIC_HIP(hipGetDevice(&dev));
+    hipEvent_t ev = nullptr;
+    for (auto& e : events)
+        if (e.first == dev) ev = e.second;
+    if (!ev) {
+        SIC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        events.emplace_back(dev, ev);
+    }
+    SIC_HIP(hipEventRecord(ev, s));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) SIC_HIP(e);
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000)) break;
+    }
+    SIC_HIP(hipEventSynchronize(ev));
+}
+
 namespace {
 
 constexpr int ROWS_PER_TILE = 32;
 
-void sync(Context& C) { SIC_HIP(hipStreamSynchronize(C.stream)); }
+void sync(Context& C) { stream_wait(C.stream); }
 
 int64_t read_i64(Context& C, const int64_t* d) {
     SIC_HIP(hipMemcpyAsync(C.h_i64, d, sizeof(int64_t), hipMemcpyDeviceToHost, C.stream));
     sync(C);
     return C.h_i64[0];
+}
+
+// The screening's free pairs (rows, gradients, S, A, W entries): at most one
+// per entry of the n x b block, so the emit pass runs without the count.
+void reserve_free_lists(BlockWork& W, size_t nb) {
+    W.e_row.reserve(nb); W.e_g.reserve(nb); W.e_s.reserve(nb); W.e_a.reserve(nb); W.e_w.reserve(nb);
 }
 
 void ensure_flags(Context& C, int64_t n, int b) {
@@ -75,11 +104,9 @@ struct LineSearch {
     bool wii_pd = true;
 };
 
-// Whitened Schur-complement matrices E1, E2 of the line search (see k_dense.hip):
-// log det(A + a Delta) - log det A = log det(I + a E1 + a^2 E2).
-void ls_prepare(Context& C, int jp, int b, int64_t nN) {
+// Every buffer of the line search, sized before any of its work is queued.
+void ls_reserve(Context& C, int b, int64_t nN) {
     BlockWork& W = C.work;
-    hipStream_t s = C.stream;
     const size_t bb = (size_t)b * b;
     W.Dinv.reserve(8 * 1024);
     W.Rb.reserve(bb); W.D11.reserve(bb); W.Mo.reserve(bb); W.Pm.reserve(bb);
@@ -89,10 +116,28 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN) {
     W.C.reserve(LS_BATCH * bb);
     // chol_out: W_II's log det and PD flag, two per trial, then the trials' linear terms
     W.chol_out.reserve(2 + 3 * LS_BATCH);
-    // R R^T = W_II
-    launch_copy_block(W.WJJ.p, jp, b, W.Rb.p, s);
-    launch_chol(W.Rb.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s, W.Dinv.p);
-    launch_zero_upper(W.Rb.p, b, b, s);
+}
+
+// R R^T = W_II (R lower, in W.Rb; its diagonal-block inverses in W.Dinv), on stream st.
+void ls_factor_wii(Context& C, int jp, int b, hipStream_t st) {
+    BlockWork& W = C.work;
+    launch_copy_block(W.WJJ.p, jp, b, W.Rb.p, st);
+    launch_chol(W.Rb.p, (int64_t)b * b, 1, b, b, 0, W.chol_out.p, st, W.Dinv.p);
+    launch_zero_upper(W.Rb.p, b, b, st);
+}
+
+// Whitened Schur-complement matrices E1, E2 of the line search (see k_dense.hip):
+// log det(A + a Delta) - log det A = log det(I + a E1 + a^2 E2).
+// factored: W_II's factor was queued on the side stream (the main stream
+// waits for it here); otherwise it is computed in order.
+void ls_prepare(Context& C, int jp, int b, int64_t nN, bool factored) {
+    BlockWork& W = C.work;
+    hipStream_t s = C.stream;
+    ls_reserve(C, b, nN);
+    if (factored)
+        SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
+    else
+        ls_factor_wii(C, jp, b, s);
     launch_ls_terms(W.cptr.p, W.c_p.p, W.delta.p, W.WJJ.p, jp, b, (int)nN, W.D11.p, W.Mo.p, W.Y.p,
                     W.Pm.p, s);
     // X = R^{-1} (M^T R) = K1^T
@@ -138,8 +183,9 @@ bool ls_eval(Context& C, int b, int64_t ncoord, double lam, int first, int nt,
 // non-PD trials skipped, then continue while F keeps decreasing; alpha = 0
 // when no trial decreases F. Trials are evaluated LS_BATCH at a time (one
 // workgroup each, so a batch costs one factorization's latency).
-LineSearch line_search(Context& C, double lam, int jp, int b, int64_t nN, int64_t ncoord) {
-    ls_prepare(C, jp, b, nN);
+LineSearch line_search(Context& C, double lam, int jp, int b, int64_t nN, int64_t ncoord,
+                       bool factored = false) {
+    ls_prepare(C, jp, b, nN, factored);
     LineSearch res;
     bool have = false, stop = false;
     double best_a = 0.0, best_f = 0.0;
@@ -433,9 +479,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
                            W.nflag.p, W.kkt.p, s);
         if (record) launch_kkt_accumulate(W.kkt.p, tiles, W.kkt_acc.p, s);
         launch_scan_colmajor(W.tilecount.p, tiles, b, W.offsets.p, W.colptr.p, s);
-        R.E = read_i64(C, W.colptr.p + b);
-        const size_t E = (size_t)std::max<int64_t>(R.E, 1);
-        W.e_row.reserve(E); W.e_g.reserve(E); W.e_s.reserve(E); W.e_a.reserve(E); W.e_w.reserve(E);
+        reserve_free_lists(W, nb);
         launch_screen_fine(1, n, j0, b, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, W.WI.p, W.AJ.p,
                            W.tilecount.p, W.offsets.p, W.e_row.p, W.e_g.p, W.e_s.p, W.e_a.p,
                            W.e_w.p, W.nflag.p, W.kkt.p, s);
@@ -485,29 +529,33 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
                              W.WNC.p, nC, W.cmap.p, W.AJ.p, W.ccount.p, nullptr, nullptr, nullptr,
                              nullptr, nullptr, nullptr, W.nflag.p, s);
         launch_scan_i32(W.ccount.p, b, W.colptr.p, nullptr, s);
-        R.E = read_i64(C, W.colptr.p + b);
-        const size_t E = (size_t)std::max<int64_t>(R.E, 1);
-        W.e_row.reserve(E); W.e_g.reserve(E); W.e_s.reserve(E); W.e_a.reserve(E); W.e_w.reserve(E);
+        reserve_free_lists(W, nb);
         launch_screen_coarse(1, P.crow.p, P.ccol.p, base, j0, b, P.lam, W.S_cand.p, W.WII.p,
                              W.WNC.p, nC, W.cmap.p, W.AJ.p, W.ccount.p, W.colptr.p, W.e_row.p,
                              W.e_g.p, W.e_s.p, W.e_a.p, W.e_w.p, W.nflag.p, s);
     }
-    // neighbourhood N and J' = I u N
+    // neighbourhood N and J' = I u N, and the coordinates; |N| and the
+    // coordinate count come back in one read (J' is sized for b + n, past any
+    // count the flags can give)
     W.scan_n.reserve(n + 1);
     launch_scan_i32(W.nflag.p, n, W.scan_n.p, nullptr, s);
-    R.nN = read_i64(C, W.scan_n.p + n);
+    W.Jp.reserve(n + b);
+    launch_nbr_compact(W.nflag.p, W.scan_n.p, n, j0, b, W.Jp.p, W.lmap.p, s);
+    W.cptr.reserve(b + 1);
+    launch_coord_count(W.colptr.p, W.e_row.p, j0, b, W.ccount.p, s);
+    launch_scan_i32(W.ccount.p, b, W.cptr.p, nullptr, s);
+    SIC_HIP(hipMemcpyAsync(C.h_i64, W.scan_n.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SIC_HIP(hipMemcpyAsync(C.h_i64 + 1, W.cptr.p + b, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SIC_HIP(hipMemcpyAsync(C.h_i64 + 2, W.colptr.p + b, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    sync(C);
+    R.nN = C.h_i64[0];
+    R.ncoord = C.h_i64[1];
+    R.E = C.h_i64[2];
     const int64_t nN = R.nN;
     const int64_t jp64 = b + nN;
     if (jp64 > (int64_t)INT32_MAX / 2) throw SicError(SIC_ETOOBIG, "neighbourhood too large");
     const int jp = (int)jp64;
     R.jp = jp;
-    W.Jp.reserve(jp);
-    launch_nbr_compact(W.nflag.p, W.scan_n.p, n, j0, b, W.Jp.p, W.lmap.p, s);
-    // coordinates
-    W.cptr.reserve(b + 1);
-    launch_coord_count(W.colptr.p, W.e_row.p, j0, b, W.ccount.p, s);
-    launch_scan_i32(W.ccount.p, b, W.cptr.p, nullptr, s);
-    R.ncoord = read_i64(C, W.cptr.p + b);
     const int64_t nc = R.ncoord;
     const size_t ncs = (size_t)std::max<int64_t>(nc, 1);
     W.c_p.reserve(ncs); W.c_e.reserve(ncs); W.c_ci.reserve(ncs);
@@ -527,6 +575,14 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     W.WJJ.reserve((size_t)jp * jp);
     launch_gather_wjj(fine ? 0 : 1, W.Jp.p, jp, b, W.WI.p, W.WN.p, nN, W.WII.p, W.WNC.p, nC,
                       W.cmap.p, W.WJJ.p, s);
+    // W_II = R R^T for the line search on the side stream, beside the
+    // coordinate descent (one workgroup each): the side stream starts once W_J'J'
+    // is gathered, the line search waits for it
+    ls_reserve(C, b, nN);
+    SIC_HIP(hipEventRecord(C.ev_fork, s));
+    SIC_HIP(hipStreamWaitEvent(C.side, C.ev_fork, 0));
+    ls_factor_wii(C, jp, b, C.side);
+    SIC_HIP(hipEventRecord(C.ev_join, C.side));
     // (d) coordinate descent
     launch_cd_prep(W.cptr.p, b, nc, W.c_p.p, W.WJJ.p, jp, W.c_ci.p, W.c_a.p, W.c_inva.p, W.c_wtc.p,
                    W.c_wtt.p, W.delta.p, s);
@@ -545,7 +601,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     double* h_cds = C.h_f64 + 40;
     SIC_HIP(hipMemcpyAsync(h_cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     // (e) line search
-    LineSearch ls = line_search(C, P.lam, jp, b, nN, nc);
+    LineSearch ls = line_search(C, P.lam, jp, b, nN, nc, true);
     sync(C);   // (no-op when the line search ended on a read-back)
     double cds[7];
     std::copy(h_cds, h_cds + 7, cds);
@@ -1039,6 +1095,7 @@ namespace sic {
 
 void release_workspace(Context& C) {
     sync(C);
+    if (C.side) stream_wait(C.side);
     C.work.~BlockWork();
     new (&C.work) BlockWork();
 }

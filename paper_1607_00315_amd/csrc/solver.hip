@@ -406,12 +406,12 @@ void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count) 
 // coordinates (and its z and Delta fit in LDS), else the U = Delta W form.
 // Returns the profiler record to scale by the sweep count (or -1).
 // S_J of columns [j0, j0+b) in the current sweep's precision (float64 result).
-static void cov_block(Context& C, Problem& P, int64_t j0, int b, double* out) {
+static void cov_block(Context& C, Problem& P, int64_t j0, int b, double* out, hipStream_t st) {
     if (C.prec != PREC_F64 && P.narrow)
         launch_sj_gemm_low(C.prec == PREC_BF16 ? (const void*)P.Xb.p : (const void*)P.Xf.p,
-                           C.prec == PREC_BF16, P.n, P.m, j0, b, out, C.stream);
+                           C.prec == PREC_BF16, P.n, P.m, j0, b, out, st);
     else
-        launch_sj_gemm_f64(P.X.p, P.n, P.m, j0, b, out, C.stream);
+        launch_sj_gemm_f64(P.X.p, P.n, P.m, j0, b, out, st);
 }
 
 static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max_sweeps,
@@ -460,16 +460,21 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     W.kkt_acc.reserve(2);
     int64_t nC = 0;
     if (fine) {
-        // (a) S_J, (b) W_I, (c) screening over all rows
+        // (a) S_J on the side stream (it reads X only) beside (b) W_I by CG on
+        // the main one, then (c) screening over all rows once both are done
         W.SJ.reserve(nb);
         W.WI.reserve(nb);
         W.cols.reserve(std::max<int64_t>(b, 1));
-        cov_block(C, P, j0, b, W.SJ.p);
+        SIC_HIP(hipEventRecord(C.ev_fork, s));
+        SIC_HIP(hipStreamWaitEvent(C.side, C.ev_fork, 0));
+        cov_block(C, P, j0, b, W.SJ.p, C.side);
+        SIC_HIP(hipEventRecord(C.ev_join, C.side));
         launch_iota_i32(W.cols.p, b, (int32_t)j0, s);
         CGResult cg = block_cg(A, W.cols.p, b, W.WI.p, b, tolI, C.opt.cg_max_iter, W.cg, s,
                                C.prec != PREC_F64, 0);
         R.cg_iters_I = cg.iterations;
         R.cg_res_I = cg.max_rel_res;
+        SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
         W.tilecount.reserve((size_t)tiles * b);
         W.offsets.reserve((size_t)tiles * b);
@@ -729,7 +734,7 @@ void initial_free_set(Context& C, Problem& P) {
         W.colptr.reserve(bb + 1);
         SIC_HIP(hipMemsetAsync(W.AJ.p, 0, sizeof(double) * nb, s));
         launch_scatter_aj(P.Acur(), j0, bb, W.AJ.p, s);
-        cov_block(C, P, j0, bb, W.SJ.p);
+        cov_block(C, P, j0, bb, W.SJ.p, C.stream);
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
         W.tilecount.reserve((size_t)tiles * bb);
         W.offsets.reserve((size_t)tiles * bb);

@@ -495,6 +495,18 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         const int64_t cnt = P.crow_h[j0 + b] - base;
         W.cand_col.reserve(std::max<int64_t>(cnt, 1));
         W.S_cand.reserve(std::max<int64_t>(cnt, 1));
+        // A_II = L L^T on the side stream (it reads A only) beside the candidate
+        // products and the W_{N^C} conjugate gradient
+        const size_t bb = (size_t)b * b;
+        W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb); W.Dinv.reserve(8 * 1024);
+        W.err.reserve(1);
+        W.chol_out.reserve(2 + 3 * LS_BATCH);
+        SIC_HIP(hipEventRecord(C.ev_fork, s));
+        SIC_HIP(hipStreamWaitEvent(C.side, C.ev_fork, 0));
+        launch_dense_aii(A, j0, b, W.AII.p, C.side);
+        launch_chol(W.AII.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, C.side, W.Dinv.p);
+        launch_zero_upper(W.AII.p, b, b, C.side);
+        SIC_HIP(hipEventRecord(C.ev_join, C.side));
         launch_expand_cand(P.crow.p, j0, b, base, W.cand_col.p, s);
         launch_sddmm(P.Xt.p, P.m, P.ccol.p + base, W.cand_col.p, cnt, W.S_cand.p, s);
         launch_flag_cand(P.ccol.p, base, cnt, j0, b, W.cflag.p, s);
@@ -511,16 +523,10 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
             R.cg_iters_N = cg.iterations;
             R.cg_res_N = cg.max_rel_res;
         }
-        const size_t bb = (size_t)b * b;
-        W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb); W.Dinv.reserve(8 * 1024);
-        W.err.reserve(1);
-        W.chol_out.reserve(2 + 3 * LS_BATCH);
         SIC_HIP(hipMemsetAsync(W.err.p, 0, sizeof(int32_t), s));
         launch_a2_k(A, j0, b, W.WNC.p, nC, W.cmap.p, W.Kb.p, W.err.p, s);
-        launch_dense_aii(A, j0, b, W.AII.p, s);
-        launch_chol(W.AII.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, s, W.Dinv.p);
-        launch_zero_upper(W.AII.p, b, b, s);
         launch_identity_minus(W.Kb.p, b, W.WII.p, s);
+        SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
         launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 0, s);
         launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 1, s);
         double* h = C.h_f64 + 48;                          // pinned staging

@@ -326,13 +326,15 @@ __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __res
     const int nt = (nb + TS_T - 1) / TS_T;
     for (int k = r; k < nt * TS_T; k += TS_T)
         Xs[k][c] = load_or(B, (int64_t)k * ldb + col, con && k < nb, 0.0);
-    for (int step = 0; step < nt; ++step) {
-        const int i = trans ? nt - 1 - step : step;
-        // stage, with every load in flight at once:
-        //   forward:  Ls[q * 16 + rr] = L[i*16 + rr][q]           for q <  i*16
-        //   backward: Ls[q * 16 + rr] = L[(i+1)*16 + q][i*16 + rr] for q <  nb - (i+1)*16
+    // the L entries a step needs, with every load in flight at once:
+    //   forward:  Ls[q * 16 + rr] = L[i*16 + rr][q]           for q <  i*16
+    //   backward: Ls[q * 16 + rr] = L[(i+1)*16 + q][i*16 + rr] for q <  nb - (i+1)*16
+    // They do not depend on X: step + 1's are loaded into registers while step
+    // runs, so no step waits for global memory but the first.
+    double lreg[LPT];
+    double dv = 0.0;
+    auto load_step = [&](int i) {
         const int kcnt = trans ? nb - (i + 1) * TS_T : i * TS_T;
-        double lreg[LPT];
 #pragma unroll
         for (int u = 0; u < LPT; ++u) {
             const int e = tid + TS_THREADS * u;
@@ -342,7 +344,12 @@ __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __res
             const bool ok = q < kcnt && row < nb && lc < nb;
             lreg[u] = load_or(L, (int64_t)row * ldl + lc, ok, 0.0);
         }
-        const double dv = dinv[(int64_t)i * TS_T * TS_T + tid];   // TS_THREADS == TS_T * TS_T
+        dv = dinv[(int64_t)i * TS_T * TS_T + tid];   // TS_THREADS == TS_T * TS_T
+    };
+    load_step(trans ? nt - 1 : 0);
+    for (int step = 0; step < nt; ++step) {
+        const int i = trans ? nt - 1 - step : step;
+        const int kcnt = trans ? nb - (i + 1) * TS_T : i * TS_T;
 #pragma unroll
         for (int u = 0; u < LPT; ++u) {
             const int e = tid + TS_THREADS * u;
@@ -350,6 +357,7 @@ __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __res
         }
         Ds[tid] = dv;
         __syncthreads();
+        if (step + 1 < nt) load_step(trans ? nt - 2 - step : step + 1);
         const int row = i * TS_T + r;
         const int k0 = trans ? (i + 1) * TS_T : 0;
         double a[4] = {Xs[row][c], 0.0, 0.0, 0.0};

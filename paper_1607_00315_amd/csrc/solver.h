@@ -39,7 +39,7 @@ struct BlockWork {
     DevBuf<int32_t> c_p, c_e, c_ci, c_gr, c_gc;
     DevBuf<double> c_S, c_A, c_a, c_inva, c_wtc, c_wtt, delta, mu, cdstats;
     // line search
-    DevBuf<double> Dinv, Rb, D11, Mo, Y, Pm, T1, D1, X, XtX, RPR, E1, E2, C, chol_out;
+    DevBuf<double> Dinv, Rb, D11, Mo, Y, Pm, T1, T2, D1, X, XtX, RPR, E1, E2, C, chol_out;
     // coarse levels
     DevBuf<int32_t> cand_col, cflag, cmap, NC, err;
     DevBuf<double> S_cand, WNC, WII, Kb, AII;

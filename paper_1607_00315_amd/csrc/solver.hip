@@ -110,7 +110,7 @@ void ls_reserve(Context& C, int b, int64_t nN) {
     const size_t bb = (size_t)b * b;
     W.Dinv.reserve(8 * 1024);
     W.Rb.reserve(bb); W.D11.reserve(bb); W.Mo.reserve(bb); W.Pm.reserve(bb);
-    W.T1.reserve(bb); W.D1.reserve(bb); W.X.reserve(bb); W.XtX.reserve(bb);
+    W.T1.reserve(bb); W.T2.reserve(bb); W.D1.reserve(bb); W.X.reserve(bb); W.XtX.reserve(bb);
     W.RPR.reserve(bb); W.E1.reserve(bb); W.E2.reserve(bb);
     W.Y.reserve((size_t)std::max<int64_t>(nN, 1) * b);
     W.C.reserve(LS_BATCH * bb);
@@ -140,17 +140,21 @@ void ls_prepare(Context& C, int jp, int b, int64_t nN, bool factored) {
         ls_factor_wii(C, jp, b, s);
     launch_ls_terms(W.cptr.p, W.c_p.p, W.delta.p, W.WJJ.p, jp, b, (int)nN, W.D11.p, W.Mo.p, W.Y.p,
                     W.Pm.p, s);
-    // X = R^{-1} (M^T R) = K1^T
+    // D1 = R^T Delta_II R and RPR = R^T P R on the side stream, beside the K1
+    // chain on the main one
+    hipStream_t side = C.side;
+    SIC_HIP(hipEventRecord(C.ev_fork, s));
+    SIC_HIP(hipStreamWaitEvent(side, C.ev_fork, 0));
+    launch_gemm_small(b, b, b, 1.0, W.D11.p, b, 0, W.Rb.p, b, 0, 0.0, W.T1.p, b, side);
+    launch_gemm_small(b, b, b, 1.0, W.Rb.p, b, 1, W.T1.p, b, 0, 0.0, W.D1.p, b, side);
+    launch_gemm_small(b, b, b, 1.0, W.Pm.p, b, 0, W.Rb.p, b, 0, 0.0, W.T2.p, b, side);
+    launch_gemm_small(b, b, b, 1.0, W.Rb.p, b, 1, W.T2.p, b, 0, 0.0, W.RPR.p, b, side);
+    SIC_HIP(hipEventRecord(C.ev_join, side));
+    // X = R^{-1} (M^T R) = K1^T, XtX = K1 K1^T
     launch_gemm_small(b, b, b, 1.0, W.Mo.p, b, 1, W.Rb.p, b, 0, 0.0, W.X.p, b, s);
     launch_trsm_lower(W.Rb.p, b, b, W.Dinv.p, W.X.p, b, b, 0, s);
-    // D1 = R^T Delta_II R
-    launch_gemm_small(b, b, b, 1.0, W.D11.p, b, 0, W.Rb.p, b, 0, 0.0, W.T1.p, b, s);
-    launch_gemm_small(b, b, b, 1.0, W.Rb.p, b, 1, W.T1.p, b, 0, 0.0, W.D1.p, b, s);
-    // RPR = R^T P R
-    launch_gemm_small(b, b, b, 1.0, W.Pm.p, b, 0, W.Rb.p, b, 0, 0.0, W.T1.p, b, s);
-    launch_gemm_small(b, b, b, 1.0, W.Rb.p, b, 1, W.T1.p, b, 0, 0.0, W.RPR.p, b, s);
-    // XtX = K1 K1^T
     launch_gemm_small(b, b, b, 1.0, W.X.p, b, 1, W.X.p, b, 0, 0.0, W.XtX.p, b, s);
+    SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
     launch_ls_e(W.D1.p, W.X.p, W.XtX.p, W.RPR.p, b, W.E1.p, W.E2.p, s);
 }
 

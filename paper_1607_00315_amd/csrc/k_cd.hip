@@ -323,10 +323,12 @@ __device__ inline void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// HT[t * nc + k] = H[k][t] (column t of H stored contiguously).
+// HT[t * nc + k] = H[k][t] (column t of H stored contiguously), formed in
+// float64 and stored as HV (float64, or float for the reduced-precision cycles).
+template <typename HV>
 __global__ void k_cd_hess(int64_t nc, int jp, const int32_t* __restrict__ c_p,
                           const int32_t* __restrict__ c_ci, const double* __restrict__ WJJ,
-                          double* __restrict__ HT) {
+                          HV* __restrict__ HT) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t t = blockIdx.y;
     if (k >= nc) return;
@@ -336,14 +338,15 @@ __global__ void k_cd_hess(int64_t nc, int jp, const int32_t* __restrict__ c_p,
     const double* wct = WJJ + (int64_t)ct * jp;
     double h = wpt[pk] * wct[ck];
     if (pt != ct) h += wct[pk] * wpt[ck];
-    HT[t * nc + k] = h;
+    HT[t * nc + k] = (HV)h;
 }
 
 // p[idx] when cond, else dflt, with the load itself unconditional (index 0
 // when !cond, which must be a valid element): a predicated load would become
 // a branch that waits for its data before the next load is issued.
-__device__ inline double load_or(const double* __restrict__ p, int64_t idx, bool cond, double dflt) {
-    const double v = p[cond ? idx : 0];
+template <typename T>
+__device__ inline double load_or(const T* __restrict__ p, int64_t idx, bool cond, double dflt) {
+    const double v = (double)p[cond ? idx : 0];
     return cond ? v : dflt;
 }
 
@@ -562,9 +565,9 @@ __device__ __forceinline__ double cd_soft(double y, double t) {
     return y > t ? y - t : (y < -t ? y + t : 0.0);
 }
 
-template <int ROWS>   // worker rows per thread: ceil(nc / 960)
+template <int ROWS, typename HV>   // worker rows per thread: ceil(nc / 960); H's storage type
 __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
-    int64_t nc, const double* __restrict__ HT, const double* __restrict__ c_S,
+    int64_t nc, const HV* __restrict__ HT, const double* __restrict__ c_S,
     const double* __restrict__ c_A, const double* __restrict__ c_inva,
     const double* __restrict__ c_wtc, double lam, int max_sweeps, double tol,
     double* __restrict__ delta, double* __restrict__ stats) {
@@ -595,23 +598,24 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
         const int Ki = klen(ci), Kp = klen(cp);
 #pragma unroll
         for (int r = 0; r < CDP_TPT; ++r) {
-            // one unconditional load per slot: a tile entry, a constant, or (past
-            // both) element 0 of H, discarded
+            // unconditional loads: a tile entry (element 0 of H past the tiles,
+            // discarded), and in the slot that reaches past the tiles a constant
             const int e = (tid - 64) + CDP_WORKERS * r;
             const bool is_tile = e < 2 * CDP_TILE;
             const int which = e / CDP_TILE, f = e % CDP_TILE;
             const int t = f / CDH_K, k = f % CDH_K;
             const bool dtile = which == 0;
             const int64_t col = (dtile ? ki : kp) + t;
-            const int g = e - 2 * CDP_TILE, gw = g / CDH_K, gk = g % CDH_K;
-            const double* src = !is_tile && gw == 0 ? c_inva
-                              : (!is_tile && gw == 1 ? c_A
-                              : (!is_tile && gw == 2 ? c_S
-                              : (!is_tile && gw == 3 ? c_wtc : HT)));
-            const int64_t idx = is_tile ? col * nc + ki + k : ki + gk;
-            const bool ok = is_tile ? (k < Ki && (dtile ? t < Ki : t < Kp))
-                                    : (g < CDP_CONST && gk < Ki);
-            treg[r] = load_or(src, idx, ok, 0.0);
+            const bool ok = is_tile && k < Ki && (dtile ? t < Ki : t < Kp);
+            const double tv = load_or(HT, col * nc + ki + k, ok, 0.0);
+            if (CDP_WORKERS * (r + 1) > 2 * CDP_TILE) {
+                const int g = e - 2 * CDP_TILE, gw = g / CDH_K, gk = g % CDH_K;
+                const double* src = gw == 0 ? c_inva : (gw == 1 ? c_A : (gw == 2 ? c_S : c_wtc));
+                const double cv = load_or(src, ki + gk, !is_tile && g < CDP_CONST && gk < Ki, 0.0);
+                treg[r] = is_tile ? tv : cv;
+            } else {
+                treg[r] = tv;
+            }
         }
     };
     auto store_tiles = [&](int b) {
@@ -693,13 +697,16 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                 const double xl = on ? cb[CDH_K + lane] + d0 : 0.0;
                 const double pv = on ? xl - (cb[2 * CDH_K + lane] - cb[3 * CDH_K + lane]) * ia : 0.0;
                 const double* dt = Dt + b * CDP_TILE;
-                double mul = 0.0;
                 const int K4 = (K + 3) & ~3;
                 // The chain, one coordinate per step in the stored order. With
                 // q = p - x, a = q - lam/a - z/a and b = q + lam/a - z/a, the step
                 // mu = soft(p - z/a, lam/a) - x is the median of a, -x and b
-                // (a <= b), three dependent operations after the broadcast of z_t.
+                // (a <= b). Every lane evaluates it for its own coordinate at the
+                // current z; lane t's value is step t: broadcast (two readlanes),
+                // applied to every z and kept in lane t. Ten instructions a step,
+                // five of them dependent.
                 const double qlo = pv - xl - lam * ia, qhi = pv - xl + lam * ia, nx = -xl;
+                int mlo = 0, mhi = 0;   // the steps, lane k holding step k (bits)
                 double hN[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) hN[u] = dt[u * CDH_K + lane];
@@ -713,17 +720,19 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int t = tt + u;
-                        const double iat = readlane_d(ia, t);
-                        const double lo = readlane_d(qlo, t), hi = readlane_d(qhi, t);
-                        const double nxt = readlane_d(nx, t);
-                        const double zt = readlane_d(z, t);
-                        const double av = lo - zt * iat, bv = hi - zt * iat;
-                        const double mu = fmax(av, fmin(bv, nxt));
+                        const double av = qlo - z * ia, bv = qhi - z * ia;
+                        const long long own = __double_as_longlong(fmax(av, fmin(bv, nx)));
+                        const int slo = __builtin_amdgcn_readlane((int)(own & 0xffffffffll), t);
+                        const int shi = __builtin_amdgcn_readlane((int)(own >> 32), t);
+                        const double mu =
+                            __longlong_as_double(((long long)shi << 32) | (unsigned int)slo);
                         z += mu * hC[u];
-                        if (lane == t) mul = mu;
-                        maxmu = fmax(maxmu, fabs(mu));
+                        mlo = lane == t ? slo : mlo;
+                        mhi = lane == t ? shi : mhi;
                     }
                 }
+                const double mul = __longlong_as_double(((long long)mhi << 32) | (unsigned int)mlo);
+                maxmu = fmax(maxmu, wave_max(fabs(mul)));
                 if (on) {
                     zs[kl] = z;
                     ds[kl] = d0 + mul;
@@ -760,16 +769,16 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
             } else {
                 // next interval's tiles and constants (chunk i+1 and its predecessor
                 // i), issued first so that their latency hides behind the column
-                // stream (with two rows per thread the registers do not allow it:
-                // then they follow the stream and hide behind the chain)
-                constexpr bool early = ROWS == 1;
+                // stream (with two float64 rows per thread the registers do not
+                // allow it: then they follow the stream and hide behind the chain)
+                constexpr bool early = ROWS == 1 || sizeof(HV) < sizeof(double);
                 if (early) load_tiles((i + 1) % C, i);
                 // steps of the previous chunk onto every row outside chunks cp and i
                 if (have_prev && C > 2) {
                     const int np = (s_nnz[pb] + CDP_PAD - 1) / CDP_PAD * CDP_PAD;
                     const double* pm = nzm + pb * CDH_K;
                     const int* pl = nzl + pb * CDH_K;
-                    const double* hcol = HT + kp0 * nc;
+                    const HV* hcol = HT + kp0 * nc;
                     double acc[ROWS];
                     bool rv[ROWS];
                     int rk[ROWS];
@@ -789,11 +798,11 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                     constexpr int BATCH = CDP_PAD / ROWS;
 #pragma unroll 1
                     for (int q0 = 0; q0 < np; q0 += BATCH) {
-                        double hv[ROWS][BATCH];
+                        HV hv[ROWS][BATCH];
 #pragma unroll
                         for (int q = 0; q < BATCH; ++q) {
                             const int t = __builtin_amdgcn_readfirstlane(pl[q0 + q]);
-                            const double* colp = hcol + (int64_t)t * nc;
+                            const HV* colp = hcol + (int64_t)t * nc;
 #pragma unroll
                             for (int r = 0; r < ROWS; ++r) hv[r][q] = colp[rk[r]];
                         }
@@ -801,7 +810,7 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                         for (int q = 0; q < BATCH; ++q) {
                             const double m = pm[q0 + q];
 #pragma unroll
-                            for (int r = 0; r < ROWS; ++r) acc[r] += hv[r][q] * m;
+                            for (int r = 0; r < ROWS; ++r) acc[r] += (double)hv[r][q] * m;
                         }
                     }
 #pragma unroll
@@ -896,17 +905,29 @@ size_t cd_hessian_lds_bytes(int64_t ncoord) {
 int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
                           const double* WJJ, const double* c_S, const double* c_A,
                           const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
-                          double tol, double* HT, double* delta, double* stats, hipStream_t s) {
+                          double tol, double* HT, double* delta, double* stats, hipStream_t s,
+                          bool low) {
     if (ncoord <= 0) return -1;
     const size_t lds = cd_hessian_lds_bytes(ncoord);
     if (ncoord > cd_hessian_limit() || lds > CD_MAX_LDS_BYTES)
         throw SicError(SIC_EINTERNAL, "coordinate count too large for the explicit-Hessian sweep");
+    const size_t lds_pipe = cd_pipe_lds_bytes(ncoord);
+    // rows the workers cover: all but two chunks (all but one or none for C <= 2)
+    const int prow = (int)((std::max<int64_t>(ncoord - 2 * CDH_K, 1) + CDP_WORKERS - 1) / CDP_WORKERS);
+    const bool pipe = lds_pipe <= CD_MAX_LDS_BYTES && prow <= 2;
+    // float storage of H (the pipelined sweep only): half the bytes the sweep streams
+    const bool hf = low && pipe;
+    const double hsz = hf ? 4.0 : 8.0;
+    float* HTf = reinterpret_cast<float*>(HT);
+    const dim3 hgrid((unsigned)((ncoord + 255) / 256), (unsigned)ncoord);
     prof_begin(KK_CD_HESS, s);
-    hipLaunchKernelGGL(k_cd_hess, dim3((unsigned)((ncoord + 255) / 256), (unsigned)ncoord),
-                       dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HT);
+    if (hf)
+        hipLaunchKernelGGL(k_cd_hess<float>, hgrid, dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HTf);
+    else
+        hipLaunchKernelGGL(k_cd_hess<double>, hgrid, dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HT);
     SIC_CHECK_LAUNCH();
     // H written once; 4 gathers of W per entry (from the L2-resident W on J')
-    prof_end(KK_CD_HESS, s, 8.0 * (double)ncoord * ncoord, 3.0 * (double)ncoord * ncoord);
+    prof_end(KK_CD_HESS, s, hsz * (double)ncoord * ncoord, 3.0 * (double)ncoord * ncoord);
     const int rows = (int)((ncoord + CDH_THREADS - 1) / CDH_THREADS);
     auto launch = [&](auto kern) {
         allow_dynamic_lds((const void*)kern);
@@ -915,18 +936,21 @@ int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int3
                            c_wtc, lam, max_sweeps, tol, delta, stats);
         SIC_CHECK_LAUNCH();
     };
-    const size_t lds_pipe = cd_pipe_lds_bytes(ncoord);
-    // rows the workers cover: all but two chunks (all but one or none for C <= 2)
-    const int prow = (int)((std::max<int64_t>(ncoord - 2 * CDH_K, 1) + CDP_WORKERS - 1) / CDP_WORKERS);
-    auto launch_pipe = [&](auto kern) {
+    auto launch_pipe = [&](auto kern, auto* H) {
         allow_dynamic_lds((const void*)kern);
         prof_begin(KK_CD, s);
-        hipLaunchKernelGGL(kern, dim3(1), dim3(CDP_THREADS), lds_pipe, s, ncoord, HT, c_S, c_A,
+        hipLaunchKernelGGL(kern, dim3(1), dim3(CDP_THREADS), lds_pipe, s, ncoord, H, c_S, c_A,
                            c_inva, c_wtc, lam, max_sweeps, tol, delta, stats);
         SIC_CHECK_LAUNCH();
     };
-    if (lds_pipe <= CD_MAX_LDS_BYTES && prow <= 2) {
-        if (prow == 1) launch_pipe(k_cd_pipe<1>); else launch_pipe(k_cd_pipe<2>);
+    if (pipe) {
+        if (hf) {
+            if (prow == 1) launch_pipe(k_cd_pipe<1, float>, (const float*)HTf);
+            else launch_pipe(k_cd_pipe<2, float>, (const float*)HTf);
+        } else {
+            if (prow == 1) launch_pipe(k_cd_pipe<1, double>, (const double*)HT);
+            else launch_pipe(k_cd_pipe<2, double>, (const double*)HT);
+        }
     } else {
         switch (rows) {
             case 1: launch(k_cd_dense<1>); break;
@@ -935,9 +959,9 @@ int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int3
             default: launch(k_cd_dense<4>); break;
         }
     }
-    // one sweep streams every column of H once (8 ncoord^2 bytes, 2 ncoord^2 flops); the
-    // caller scales the record by the sweep count once it is known
-    return prof_end(KK_CD, s, 8.0 * (double)ncoord * ncoord, 2.0 * (double)ncoord * ncoord);
+    // one sweep streams every column of H once (hsz ncoord^2 bytes, 2 ncoord^2 flops);
+    // the caller scales the record by the sweep count once it is known
+    return prof_end(KK_CD, s, hsz * (double)ncoord * ncoord, 2.0 * (double)ncoord * ncoord);
 }
 
 }  // namespace sic

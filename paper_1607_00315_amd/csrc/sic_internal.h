@@ -228,6 +228,8 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
                double* ug, unsigned char* markg, double* stats, hipStream_t s);
 // Explicit coordinate Hessian form: builds H^T (ncoord^2 doubles at HT), then
 // runs the sweeps; requires cd_hessian_lds_bytes(ncoord) <= CD_MAX_LDS_BYTES.
+// low: H stored as float (in the first half of HT) when the pipelined sweep
+// runs, the sweep's arithmetic still float64 (the reduced-precision cycles).
 int64_t cd_hessian_limit();   // largest coordinate count the explicit-Hessian sweep takes
 size_t cd_hessian_lds_bytes(int64_t ncoord);
 // Returns the profiler record of the sweep kernel (bytes and flops of one sweep),
@@ -235,7 +237,8 @@ size_t cd_hessian_lds_bytes(int64_t ncoord);
 int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
                           const double* WJJ, const double* c_S, const double* c_A,
                           const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
-                          double tol, double* HT, double* delta, double* stats, hipStream_t s);
+                          double tol, double* HT, double* delta, double* stats, hipStream_t s,
+                          bool low = false);
 
 // ---------------------------------------------------------------- k_pcd.hip
 struct PcdWork {

@@ -432,7 +432,7 @@ static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max
         W.HT.reserve((size_t)nc * nc);
         return launch_cd_hessian(nc, jp, W.c_p.p, W.c_ci.p, W.WJJ.p, W.c_S.p, W.c_A.p,
                                  W.c_inva.p, W.c_wtc.p, lam, max_sweeps, tol, W.HT.p, W.delta.p,
-                                 W.cdstats.p, s);
+                                 W.cdstats.p, s, C.prec != PREC_F64);
     }
     W.U.reserve((size_t)jp * b);
     W.ug.reserve(jp);

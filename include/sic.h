@@ -144,7 +144,9 @@ void sic_destroy(sic_ctx* ctx);
  * pointer (detected; never freed). lambda >= 0, tol > 0 is the KKT max-norm
  * target. A_out receives a host CSR allocated by the library (release it with
  * sic_csr_free); info (may be NULL) receives statistics. Returns SIC_OK,
- * SIC_ENOCONV (A_out and info still filled) or an error code.
+ * SIC_ENOCONV (A_out and info still filled) or an error code. The context
+ * keeps the problem's device storage (X, its copies, the CSR pair) for the
+ * next solve or batch on it; sic_destroy frees it, and so does a failed solve.
  */
 int sic_solve(sic_ctx* ctx, const double* X, int64_t n, int64_t m, double lambda, double tol,
               sic_csr* A_out, sic_info* info);

@@ -10,6 +10,9 @@
 
 struct sic_ctx {
     sic::Context c;
+    // the last solve's problem storage (X and its copies, the CSR pair), reused
+    // by the next solve on this context instead of allocated and freed per call
+    std::unique_ptr<sic::Problem> P;
 };
 
 struct sic_prob {
@@ -200,11 +203,17 @@ int sic_solve(sic_ctx* ctx, const double* X, int64_t n, int64_t m, double lambda
         sic::Context& C = ctx->c;
         sic::AccountScope scope(C.acct);
         SIC_HIP(hipSetDevice(C.device));
-        sic::Problem P;
-        sic::problem_init(C, P, X, SIC_X_F64, n, m, lambda);
-        const int st = sic::solve_problem(C, P, tol, info);
-        sic::get_A_host(C, P, A_out);
-        return st;
+        if (!ctx->P) ctx->P = std::make_unique<sic::Problem>();
+        sic::Problem& P = *ctx->P;
+        try {
+            sic::problem_init(C, P, X, SIC_X_F64, n, m, lambda);
+            const int st = sic::solve_problem(C, P, tol, info);
+            sic::get_A_host(C, P, A_out);
+            return st;
+        } catch (...) {
+            ctx->P.reset();   // a failed solve keeps no problem storage
+            throw;
+        }
     });
 }
 
@@ -223,8 +232,13 @@ int sic_solve_batch(sic_ctx* ctx, int count, const sic_problem* probs, sic_csr* 
             sic::Context& C = ctx->c;
             sic::AccountScope scope(C.acct);
             SIC_HIP(hipSetDevice(C.device));
-            sic::Problem P;
-            return sic::solve_request(C, P, q, A_out + slot, inf);
+            if (!ctx->P) ctx->P = std::make_unique<sic::Problem>();
+            try {
+                return sic::solve_request(C, *ctx->P, q, A_out + slot, inf);
+            } catch (...) {
+                ctx->P.reset();
+                throw;
+            }
         });
         if (st != SIC_OK && inf)
             for (int l = 0; l < nl; ++l)

@@ -100,6 +100,13 @@ struct DevBuf {
         acct = a;
         acct->bytes += cap * sizeof(T);
     }
+    // reserve for a size that creeps up over calls: grows by at least half the
+    // capacity, so a slowly growing count reallocates (and synchronises the
+    // device in hipFree) a logarithmic number of times
+    void reserve_grow(size_t count) {
+        if (count <= cap && p) return;
+        reserve(std::max(count, cap + cap / 2));
+    }
 };
 
 // Pinned host buffer with grow-only capacity, for read-backs the host waits on

@@ -643,8 +643,8 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         const int64_t cap = A.nnz + 2 * nc;
         An.n = n;
         An.rowptr.reserve(n + 1);
-        An.col.reserve(std::max<int64_t>(cap, 1));
-        An.val.reserve(std::max<int64_t>(cap, 1));
+        An.col.reserve_grow(std::max<int64_t>(cap, 1));
+        An.val.reserve_grow(std::max<int64_t>(cap, 1));
         W.rcount.reserve(n);
         launch_upd_newvals(nc, W.c_p.p, W.c_ci.p, W.c_A.p, W.delta.p, ls.alpha, W.Jp.p, j0, b,
                            W.ANEW.p, s);

@@ -42,8 +42,8 @@ FP64_PEAK_TFS = 78.6
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB reference copy; valid only
 # while the kernel's source is the one measured (sha256 prefix of the file).
 PMC_TRAFFIC = {
-    "cd": dict(source="paper_1607_00315_amd/csrc/k_cd.hip", sha256="cd24d29e6e5ee503",
-               fetch=57623301.0, write=6709.0,
+    "cd": dict(source="paper_1607_00315_amd/csrc/k_cd.hip", sha256="d11ab77cb73ce5a8",
+               fetch=57621609.0, write=6710.0,
                profile="profiles/cd_grid_n10000_m5000_pmc.md"),
 }
 

@@ -19,20 +19,7 @@ namespace {
 
 constexpr int CH_NB = 256;        // largest block handled by the Cholesky kernel
 
-// In-place lower Cholesky of one nb x nb matrix per workgroup (batch over
-// blockIdx.x, matrices `stride` doubles apart, leading dimension ld).
-// The lower triangle is held in registers as 32 x 32 tiles: thread
-// (ti, tj), ti < 16, owns entries (ti, tj) and (ti + 16, tj) of each of the 36
-// lower tiles of a 256 x 256 matrix (144 VGPRs at two waves per SIMD).
-// Per tile column kb:
-//   1. the diagonal tile goes to LDS, where one wave factors it and inverts
-//      the factor (LDS operations of one wave execute in order),
-//   2. each panel tile below is staged in LDS and multiplied by L_kk^{-T},
-//   3. the trailing lower tiles are updated in registers from the panel in LDS.
-// Global memory is touched only by the initial load and the final store.
-// identity != 0 factors I + E: pivot = 1 + t, log det term = log1p(t).
-// out[2*batch] = log det, out[2*batch+1] = 1 if PD else 0. Only the lower
-// triangle is read; the factor overwrites it and the upper triangle is zeroed.
+// Cholesky tiling (the kernel, k_chol, is described where it is defined).
 typedef double chol_d4 __attribute__((ext_vector_type(4)));
 
 constexpr int CB = 16;                  // block size of the factorization

@@ -174,3 +174,35 @@ def test_full_size_grid_solve(precision):
     on = Ac != 0
     assert np.max(np.abs(G[on] + lam * np.sign(Ac[on]))) <= 1e-6
     assert np.max(np.abs(G[~on])) <= lam + 1e-6
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_repeat_solves_on_one_context_are_identical(precision):
+    """A context keeps its workspace, its problem storage and the CG's
+    first-check predictions between solves; none of that may change a result.
+    One context solves A, then a smaller problem B, then (after a failed
+    solve) A again; each result must equal, bit for bit, the same problem
+    solved on a fresh context."""
+    from paper_1607_00315_amd import sic
+    prec = sic.SIC_MIXED if precision == "mixed" else sic.SIC_FP64
+    XA, _, sa = workload("random_n600_m300")
+    XB, _, sb = workload("chain_n200_m100")
+    opts = dict(block=64, precision=prec)
+    announce(f"repeat solves on one context ({precision})")
+
+    def fresh(X, lam):
+        with sic.Context(**opts) as c:
+            return c.solve(X, lam, 1e-7)[0]
+
+    bad = np.ones((20, 4))
+    bad[3, 2] = np.nan
+    with sic.Context(**opts) as c:
+        a1 = c.solve(XA, sa["lam"], 1e-7)[0]
+        b1 = c.solve(XB, sb["lam"], 1e-7)[0]
+        with pytest.raises(sic.SicError):
+            c.solve(bad, 0.1, 1e-6)
+        a2 = c.solve(XA, sa["lam"], 1e-7)[0]
+    a0, b0 = fresh(XA, sa["lam"]), fresh(XB, sb["lam"])
+    for got, want in ((a1, a0), (a2, a0), (b1, b0)):
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w)

@@ -64,27 +64,28 @@ __global__ __launch_bounds__(256) void k_screen_fine(
             }
 #pragma unroll
             for (int u = 0; u < G; ++u) {
-            const int64_t r = rg + u;
-            if (r >= r1) break;
-            const double s = sv[u];
-            const double w = wv[u];
-            const double a = av[u];
-            const double g = s - w;
-            const bool fr = (a != 0.0) || (fabs(g) > lam);
-            if (pass == 0) {
-                const double mv = mnorm(g, a, lam);
-                kmax = fmax(kmax, mv);
-                ksum += mv;
-                if (fr && (r < j0 || r >= j0 + b)) nflag[r] = 1;
-            } else if (fr) {
-                e_row[pos] = (int32_t)r;
-                e_g[pos] = g;
-                e_s[pos] = s;
-                e_a[pos] = a;
-                e_w[pos] = w;
-                ++pos;
-            }
-            cnt += fr ? 1 : 0;
+                const int64_t r = rg + u;
+                if (r < r1) {   // rows past the tile end were loaded as row r0
+                    const double s = sv[u];
+                    const double w = wv[u];
+                    const double a = av[u];
+                    const double g = s - w;
+                    const bool fr = (a != 0.0) || (fabs(g) > lam);
+                    if (pass == 0) {
+                        const double mv = mnorm(g, a, lam);
+                        kmax = fmax(kmax, mv);
+                        ksum += mv;
+                        if (fr && (r < j0 || r >= j0 + b)) nflag[r] = 1;
+                    } else if (fr) {
+                        e_row[pos] = (int32_t)r;
+                        e_g[pos] = g;
+                        e_s[pos] = s;
+                        e_a[pos] = a;
+                        e_w[pos] = w;
+                        ++pos;
+                    }
+                    cnt += fr ? 1 : 0;
+                }
             }
         }
         if (pass == 0) tilecount[tile * b + ci] = cnt;

@@ -1,14 +1,15 @@
 /*
  * sic — serving loop: continuous batching of estimation problems on one GPU.
  *
- * A server owns `slots` solver contexts. Each slot is one non-blocking HIP
- * stream with its own device workspace, driven by one host worker thread.
+ * A server owns `slots` solver contexts. Each slot is one solver context (a
+ * non-blocking HIP stream and the context's second stream, and its own device
+ * workspace), driven by one host worker thread.
  * Submitted problems wait in a FIFO queue. A problem is admitted when a slot
  * is idle and its device-memory footprint fits in what the admitted problems
  * leave of the server's budget. Problems that arrive while others run are
  * admitted as soon as a slot and memory free up. The block updates of all
  * admitted problems (Algorithm 2, Section 6.1, inside the cycles of
- * Algorithm 1) then run concurrently on the device, one stream per problem,
+ * Algorithm 1) then run concurrently on the device, on each problem's streams,
  * and each problem's X, iterate A, level sets and workspace stay resident on
  * the device until it finishes.
  *

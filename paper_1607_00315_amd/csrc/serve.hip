@@ -1,6 +1,6 @@
 // Serving loop (sic_serve.h): a FIFO of estimation problems admitted by
 // device-memory footprint into a fixed set of slots. Each slot is one solver
-// context (its own non-blocking stream and workspace) driven by one host
+// context (its own non-blocking streams and workspace) driven by one host
 // worker thread, so the block updates of the admitted problems run
 // concurrently on the device while every worker waits only on its own stream.
 #include <chrono>

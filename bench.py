@@ -263,8 +263,8 @@ def main():
                          "(the exact gap is still measured and reported)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
-              "multi-GPU path; see the sharding design notes", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch

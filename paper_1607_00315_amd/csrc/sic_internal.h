@@ -134,6 +134,11 @@ struct HostBuf {
         }
         cap = c;
     }
+    // grows by at least half the capacity (pinned allocations are slow)
+    void reserve_grow(size_t count) {
+        if (count <= cap && p) return;
+        reserve(std::max(count, cap + cap / 2));
+    }
 };
 
 // Symmetric sparse matrix on the device: full CSR (both triangles), sorted columns.

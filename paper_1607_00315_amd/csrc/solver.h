@@ -45,6 +45,11 @@ struct BlockWork {
     DevBuf<double> S_cand, WNC, WII, Kb, AII;
     // CSR rebuild
     DevBuf<int32_t> rcount;
+    // the finest sweep's free pairs and |g| (for the next hierarchy), read back
+    // at the block's closing synchronisation
+    HostBuf<int64_t> h_cp;
+    HostBuf<int32_t> h_rows;
+    HostBuf<double> h_g;
     CGWork cg;
     PcdWork pcd;
     int64_t n_init = 0;   // n for which flag/map arrays are initialised

@@ -663,15 +663,26 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         P.cur = 1 - P.cur;
         P.F += ls.dF;
     }
-    // free pairs and |g| for the next hierarchy
-    if (record && R.E > 0) {
-        std::vector<int64_t> cp(b + 1);
-        std::vector<int32_t> rows(R.E);
-        std::vector<double> g(R.E);
-        SIC_HIP(hipMemcpyAsync(cp.data(), W.colptr.p, sizeof(int64_t) * (b + 1), hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(rows.data(), W.e_row.p, sizeof(int32_t) * R.E, hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(g.data(), W.e_g.p, sizeof(double) * R.E, hipMemcpyDeviceToHost, s));
-        sync(C);
+    // free pairs and |g| for the next hierarchy: copied to pinned memory here,
+    // recorded after the block's closing synchronisation
+    const bool rec = record && R.E > 0;
+    if (rec) {
+        W.h_cp.reserve_grow(b + 1);
+        W.h_rows.reserve_grow(R.E);
+        W.h_g.reserve_grow(R.E);
+        SIC_HIP(hipMemcpyAsync(W.h_cp.p, W.colptr.p, sizeof(int64_t) * (b + 1), hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(W.h_rows.p, W.e_row.p, sizeof(int32_t) * R.E, hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(W.h_g.p, W.e_g.p, sizeof(double) * R.E, hipMemcpyDeviceToHost, s));
+    }
+    // reset per-block flags and maps
+    SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, s));
+    launch_reset_rows(W.Jp.p, jp, nullptr, W.lmap.p, s);
+    if (!fine && nC > 0) launch_reset_rows(W.NC.p, nC, W.cflag.p, W.cmap.p, s);
+    sync(C);
+    if (rec) {
+        const int64_t* cp = W.h_cp.p;
+        const int32_t* rows = W.h_rows.p;
+        const double* g = W.h_g.p;
         int64_t seq = (int64_t)P.rec_seq.size();
         for (int ci = 0; ci < b; ++ci) {
             const int64_t c = j0 + ci;
@@ -684,11 +695,6 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
             }
         }
     }
-    // reset per-block flags and maps
-    SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, s));
-    launch_reset_rows(W.Jp.p, jp, nullptr, W.lmap.p, s);
-    if (!fine && nC > 0) launch_reset_rows(W.NC.p, nC, W.cflag.p, W.cmap.p, s);
-    sync(C);
     if (new_nnz_pending) {
         DevCSR& An = P.Acur();
         An.nnz = C.h_i64[8];

@@ -260,7 +260,8 @@ def _fill_spec(s: ProblemSpec, p: dict, keep: list) -> int:
 
 
 class Context:
-    """One library context (HIP stream + device buffers) on one GPU."""
+    """One library context on one GPU: its two HIP streams, device workspace and
+    the last solve's problem storage (kept for the next solve; close() frees it)."""
 
     def __init__(self, trace_cap: int = 0, **opts):
         o = options(**opts)

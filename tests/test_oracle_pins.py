@@ -366,3 +366,430 @@ def test_coarse_solution_correspondence():
     for _ in range(12):
         A, _, _, _, _ = mlbcd.relax(A, S, lam, spec["block"], cand, max_sweeps=50, tol=1e-10)
     np.testing.assert_allclose(A, Astar, atol=1e-8)
+
+
+# ---------------------------------------------------------------- covariance (Section 5, S = X^T X / m)
+
+def test_covariance_hand_worked_example():
+    """m = 2 samples of n = 3 variables, worked out by hand: S = X^T X / m
+    with no centring and the divisor m (not m - 1)."""
+    X = np.array([[1.0, 2.0, 0.0],
+                  [3.0, -1.0, 2.0]])
+    expect = np.array([[5.0, -0.5, 3.0],
+                       [-0.5, 2.5, -1.0],
+                       [3.0, -1.0, 2.0]])
+    np.testing.assert_array_equal(core.covariance(X), expect)
+    np.testing.assert_array_equal(steps.cov_block(X, 1, 3), expect[:, 1:3])
+
+
+def test_covariance_entries_by_loops_and_structure():
+    rng = np.random.default_rng(21)
+    m, n = 7, 5
+    X = rng.standard_normal((m, n)) + 3.0     # a non-zero mean: centring would change S
+    S = core.covariance(X)
+    for i in range(n):
+        for j in range(n):
+            acc = 0.0
+            for t in range(m):
+                acc += X[t, i] * X[t, j]
+            assert S[i, j] == pytest.approx(acc / m, rel=1e-14)
+    # diag S = ||X_{:,i}||^2 / m, and S is symmetric
+    for i in range(n):
+        assert S[i, i] == pytest.approx(sum(v * v for v in X[:, i]) / m, rel=1e-14)
+    assert np.array_equal(S, S.T)
+    # a constant column c gives S_ii = c^2 (the centred estimate would give 0)
+    Xc = X.copy()
+    Xc[:, 2] = 1.5
+    assert core.covariance(Xc)[2, 2] == pytest.approx(2.25, rel=1e-15)
+
+
+def test_cov_block_rows_by_loops_and_symmetric_diagonal_block():
+    rng = np.random.default_rng(22)
+    m, n, j0, j1 = 9, 8, 3, 6
+    X = rng.standard_normal((m, n))
+    SJ = steps.cov_block(X, j0, j1)
+    assert SJ.shape == (n, j1 - j0)
+    for i in range(n):
+        for c in range(j0, j1):
+            acc = sum(X[t, i] * X[t, c] for t in range(m))
+            assert SJ[i, c - j0] == pytest.approx(acc / m, rel=1e-13, abs=1e-15)
+    SII = SJ[j0:j1, :]
+    np.testing.assert_allclose(SII, SII.T, rtol=1e-15, atol=0)
+    for c in range(j0, j1):
+        assert SJ[c, c - j0] == pytest.approx(np.sum(X[:, c] ** 2) / m, rel=1e-14)
+
+
+# ---------------------------------------------------------------- log det, in high precision
+
+mpmath = pytest.importorskip("mpmath")
+
+
+def _mp_logdet(M, dps=60):
+    """log det of a symmetric matrix by an mpmath Cholesky at `dps` digits
+    (None when a pivot is not positive)."""
+    with mpmath.workdps(dps):
+        A = mpmath.matrix([[mpmath.mpf(float(v)) for v in row] for row in M])
+        return _mp_logdet_matrix(A)
+
+
+def _mp_logdet_matrix(A):
+    n = A.rows
+    L = mpmath.matrix(n, n)
+    total = mpmath.mpf(0)
+    for j in range(n):
+        s = A[j, j] - sum(L[j, k] ** 2 for k in range(j))
+        if s <= 0:
+            return None
+        L[j, j] = mpmath.sqrt(s)
+        total += mpmath.log(s)
+        for i in range(j + 1, n):
+            L[i, j] = (A[i, j] - sum(L[i, k] * L[j, k] for k in range(j))) / L[j, j]
+    return total
+
+
+def _mp_objective_change(A, D, S, lam, alpha, dps=60):
+    """F(A + alpha D) - F(A) at `dps` digits, every term from its definition
+    (eq. (MLE_l1_prior)): the log dets by Cholesky, the trace and the l1 norm
+    entry by entry."""
+    n = A.shape[0]
+    with mpmath.workdps(dps):
+        a = mpmath.mpf(float(alpha))
+        Am = mpmath.matrix([[mpmath.mpf(float(v)) for v in row] for row in A])
+        Dm = mpmath.matrix([[mpmath.mpf(float(v)) for v in row] for row in D])
+        Bm = Am + a * Dm
+        l0, l1 = _mp_logdet_matrix(Am), _mp_logdet_matrix(Bm)
+        if l1 is None:
+            return None
+        tr = sum(mpmath.mpf(float(S[i, j])) * Dm[i, j] for i in range(n) for j in range(n))
+        l1n = sum(abs(Bm[i, j]) - abs(Am[i, j]) for i in range(n) for j in range(n))
+        return float(-(l1 - l0) + a * tr + mpmath.mpf(float(lam)) * l1n)
+
+
+@pytest.mark.parametrize("scale", [1e-12, 1e-9, 1e-6, 1e-3, 0.3])
+def test_logdet_identity_plus_against_high_precision(scale):
+    """log det(I + E) by the blocked log1p Cholesky (block 4 on n = 12, so the
+    trailing update between blocks runs) against a 60-digit Cholesky."""
+    rng = np.random.default_rng(31)
+    n = 12
+    B = rng.standard_normal((n, n))
+    E = scale * (B + B.T) / np.sqrt(n)
+    ref = float(_mp_logdet_exact_shift(E))
+    for blk in (4, 128):
+        got = core.logdet_identity_plus(E, block=blk)
+        assert got == pytest.approx(ref, rel=1e-12, abs=1e-300)
+
+
+def _mp_logdet_exact_shift(E, dps=80):
+    """log det(I + E) with I + E formed exactly in mpmath (float64 would round
+    the small entries of E away)."""
+    n = E.shape[0]
+    with mpmath.workdps(dps):
+        M = mpmath.matrix([[mpmath.mpf(float(E[i, j])) + (1 if i == j else 0) for j in range(n)]
+                           for i in range(n)])
+        return _mp_logdet_matrix(M)
+
+
+@pytest.mark.parametrize("step", [1e-12, 1e-9, 1e-6, 1e-3])
+def test_objective_change_against_high_precision(step):
+    """The line search's F(A + alpha D) - F(A) (whitened log det, term-wise l1
+    change) at alpha ||D|| from 1e-12 to 1e-3 against the plain definition
+    evaluated at 60 digits."""
+    A, D, I, N = _structured(6)
+    S = _structured(7)[0] / 3
+    A[0, 5] = A[5, 0] = 0.0          # a zero entry of A under the direction: sign change
+    lam = 0.2
+    dF = quic_plain.objective_change(A, D, S, lam)
+    nd = np.max(np.abs(D))
+    for alpha in (step / nd, 0.5 * step / nd):
+        ref = _mp_objective_change(A, D, S, lam, alpha)
+        got = dF(alpha)
+        assert got == pytest.approx(ref, rel=1e-9, abs=1e-14 * step)
+
+
+def test_logdet_pd_and_cholesky_closed_forms():
+    M = np.array([[4.0, 2.0], [2.0, 5.0]])     # L = [[2, 0], [1, 2]], det 16
+    L = core.cholesky_lower(M)
+    np.testing.assert_allclose(L, [[2.0, 0.0], [1.0, 2.0]], rtol=1e-15)
+    assert core.logdet_pd(M) == pytest.approx(np.log(16.0), rel=1e-15)
+    assert core.logdet_pd(np.array([[1.0, 2.0], [2.0, 1.0]])) is None
+    assert core.cholesky_lower(np.array([[-1.0]])) is None
+
+
+def test_inverse_pd_is_an_inverse():
+    A, _, _, _ = _structured(8)
+    W = core.inverse_pd(A)
+    np.testing.assert_allclose(A @ W, np.eye(A.shape[0]), atol=1e-12)
+    np.testing.assert_array_equal(W, W.T)
+    with pytest.raises(np.linalg.LinAlgError):
+        core.inverse_pd(np.array([[1.0, 2.0], [2.0, 1.0]]))
+
+
+def test_objective_closed_form_and_gradient_by_differences():
+    # diagonal A: F = -sum log a_i + sum S_ii a_i + lam sum a_i
+    S = np.array([[2.0, 0.3], [0.3, 1.0]])
+    A = np.diag([0.5, 2.0])
+    lam = 0.1
+    expect = -(np.log(0.5) + np.log(2.0)) + 2.0 * 0.5 + 1.0 * 2.0 + lam * 2.5
+    assert core.objective(A, S, lam) == pytest.approx(expect, rel=1e-15)
+    assert core.objective(-A, S, lam) == float("inf")
+    # gradient of the smooth part f(A) = -log det A + tr(SA), by central
+    # differences of f along symmetric unit directions, at 60 digits
+    A2, _, _, _ = _structured(9, n=5, I=(0, 1), N=(3,))
+    S2 = _structured(10, n=5, I=(0, 1), N=(3,))[0] / 4
+    G = core.gradient(A2, S2)
+    h = 1e-20
+    for (i, j) in [(0, 0), (1, 3), (2, 4), (4, 4)]:
+        E = np.zeros((5, 5)); E[i, j] = E[j, i] = 1.0
+        with mpmath.workdps(60):
+            hp = mpmath.mpf(h)
+            def f(sign):
+                M = mpmath.matrix([[mpmath.mpf(float(A2[r, c])) + sign * hp * E[r, c]
+                                    for c in range(5)] for r in range(5)])
+                tr = sum(mpmath.mpf(float(S2[r, c])) * M[c, r] for r in range(5) for c in range(5))
+                return -_mp_logdet_matrix(M) + tr
+            deriv = float((f(1) - f(-1)) / (2 * hp))
+        expect = G[i, j] if i == j else 2.0 * G[i, j]
+        assert expect == pytest.approx(deriv, rel=1e-10, abs=1e-13)
+
+
+def test_min_norm_subgradient_by_brute_force():
+    """The subdifferential of lam|a| at a = 0 is [-lam, lam]; the min-norm
+    element is found here by scanning it on a fine grid (Section 4,
+    eq. (subgradient1))."""
+    lam = 0.3
+    G = np.array([[0.5, -0.1, 0.45], [-0.1, -0.8, 0.2], [0.45, 0.2, 0.05]])
+    A = np.array([[1.0, 0.0, -0.2], [0.0, 2.0, 0.0], [-0.2, 0.0, 1.5]])
+    m = core.min_norm_subgradient(G, A, lam)
+    t = np.linspace(-1.0, 1.0, 200001)
+    for i in range(3):
+        for j in range(3):
+            if A[i, j] != 0:
+                expect = G[i, j] + lam * np.sign(A[i, j])
+            else:
+                cands = G[i, j] + lam * t
+                expect = cands[np.argmin(np.abs(cands))]
+            assert m[i, j] == pytest.approx(expect, abs=1e-5)
+    assert core.kkt_max(G, A, lam) == pytest.approx(np.max(np.abs(m)), rel=1e-15)
+    assert core.kkt_l1(G, A, lam) == pytest.approx(np.sum(np.abs(m)), rel=1e-15)
+    # at a KKT point the measure is zero
+    assert core.kkt_max(np.array([[-0.3]]), np.array([[1.0]]), 0.3) == 0.0
+
+
+def test_free_mask_and_support_pairs_hand_worked():
+    lam = 0.3
+    G = np.array([[0.1, 0.31, -0.3], [0.31, 0.0, -0.5], [-0.3, -0.5, 0.2]])
+    A = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    F = core.free_mask(G, A, lam)
+    expect = np.array([[1, 1, 0], [1, 1, 1], [0, 1, 1]], dtype=bool)   # |g| = lam is not free
+    np.testing.assert_array_equal(F, expect)
+    A2 = np.array([[1.0, 0.0, -0.2], [0.0, 2.0, 0.0], [-0.2, 0.0, 1.5]])
+    np.testing.assert_array_equal(core.support_pairs(A2), [0 * 3 + 0, 0 * 3 + 2, 1 * 3 + 1, 2 * 3 + 2])
+
+
+def test_abs_change_and_l1_change_exact_cases():
+    from oracle import pcd
+    a = np.array([1.0, -1.0, 0.0, 0.5, -0.5, 1e16])
+    d = np.array([-3.0, 0.25, -0.7, -0.5, 1.5, 1.0])
+    expect = np.abs(a + d) - np.abs(a)
+    expect[-1] = 1.0                     # no sign change: +d exactly, which a + d would round
+    np.testing.assert_array_equal(quic_plain.abs_change(a, d), expect)
+    np.testing.assert_array_equal(pcd.l1_change(a, d), expect)
+
+
+# ---------------------------------------------------------------- block steps by hand
+
+def test_block_sets_hand_worked():
+    """Free rows per block column, the coordinates and the neighbourhood of
+    one block on a 6-variable example written out by hand (eq. (active_set_j),
+    eq. (extended_set))."""
+    lam = 0.3
+    n, j0, j1 = 6, 2, 4
+    G = np.zeros((n, n))
+    A = np.eye(n)
+    G[0, 2] = 0.5     # row 0 free in column 2 (outside I)
+    G[3, 2] = -0.4    # row 3 free in column 2 (inside I, below the diagonal: not a coordinate)
+    G[5, 3] = 0.31    # row 5 free in column 3
+    G[1, 3] = 0.3     # |g| = lam: not free
+    A[4, 3] = 0.2     # non-zero in A: free whatever g is
+    G_J, A_J = G[:, j0:j1], A[:, j0:j1]
+    free = steps.screen(G_J, A_J, lam, j0, j1)
+    assert [list(f) for f in free] == [[0, 2, 3], [3, 4, 5]]
+    r, c = steps.coordinates(free, j0, j1)
+    assert list(zip(r.tolist(), c.tolist())) == [(0, 2), (2, 2), (3, 3), (4, 3), (5, 3)]
+    N = steps.neighborhood(free, j0, j1)
+    assert list(N) == [0, 4, 5]
+    assert list(steps.local_set(j0, j1, N)) == [2, 3, 0, 4, 5]
+    assert steps.blocks(7, 3) == [(0, 3), (3, 6), (6, 7)]
+    cand = {2: np.array([0, 2]), 3: np.array([3, 5])}
+    freec = steps.screen(G_J, A_J, lam, j0, j1, cand)
+    assert [list(f) for f in freec] == [[0, 2], [3, 5]]
+    D = steps.delta_matrix(n, r, c, np.arange(1.0, 6.0))
+    assert D[0, 2] == D[2, 0] == 1.0 and D[3, 4] == D[4, 3] == 4.0 and np.count_nonzero(D) == 8
+
+
+def test_inverse_columns_residual():
+    A, _, _, _ = _structured(12)
+    cols = [1, 4, 7]
+    W = steps.inverse_columns(A, cols)
+    E = np.zeros((A.shape[0], 3)); E[cols, range(3)] = 1.0
+    np.testing.assert_allclose(A @ W, E, atol=1e-12)
+
+
+def test_level_candidates_hand_worked():
+    n = 4
+    ranking = np.array([0 * n + 0, 1 * n + 1, 0 * n + 3, 1 * n + 2, 2 * n + 2], dtype=np.int64)
+    cand = steps.level_candidates(ranking, 4, n)
+    assert [list(cand[c]) for c in range(n)] == [[0, 3], [1, 2], [1], [0]]
+
+
+# ---------------------------------------------------------------- PCD-CG pins
+
+def test_block_model_is_the_second_order_expansion_of_f():
+    """q(Delta) - q(0) agrees with F(A + Delta) - F(A) up to O(|Delta|^3)
+    (Section 5.1: the model is the second-order expansion of the smooth part
+    plus the exact l1 term)."""
+    from oracle import pcd
+    A, _, _, _ = _structured(13, n=6, I=(0, 1), N=(4,))
+    S = _structured(14, n=6, I=(0, 1), N=(4,))[0] / 3
+    lam = 0.2
+    W = np.linalg.inv(A)
+    ri, ci = np.triu_indices(6)
+    rng = np.random.default_rng(15)
+    dir_ = rng.standard_normal(ri.size)
+    errs = []
+    for t in (1e-2, 5e-3, 2.5e-3):
+        Dv = t * dir_
+        Dm = steps.delta_matrix(6, ri, ci, Dv)
+        q = pcd.block_model(W, ri, ci, S[ri, ci], A[ri, ci], lam, Dv) - \
+            pcd.block_model(W, ri, ci, S[ri, ci], A[ri, ci], lam, 0 * Dv)
+        ref = _mp_objective_change(A, Dm, S, lam, 1.0)
+        errs.append(abs(q - ref))
+    # third order: halving Delta divides the error by about 8
+    assert errs[0] / errs[1] == pytest.approx(8.0, rel=0.1)
+    assert errs[1] / errs[2] == pytest.approx(8.0, rel=0.1)
+
+
+def test_hessian_product_is_the_derivative_of_the_inverse():
+    """(W P W) is the derivative of -(A + tP)^{-1} at t = 0 (central difference)."""
+    from oracle import pcd
+    A, _, _, _ = _structured(16, n=6, I=(0, 1), N=(4,))
+    W = np.linalg.inv(A)
+    ri, ci = np.triu_indices(6)
+    p = np.random.default_rng(17).standard_normal(ri.size)
+    P = steps.delta_matrix(6, ri, ci, p)
+    h = 1e-5
+    fd = (np.linalg.inv(A - h * P) - np.linalg.inv(A + h * P)) / (2 * h)
+    np.testing.assert_allclose(pcd.hessian_product(W, ri, ci, p), fd[ri, ci], atol=1e-8)
+
+
+def test_pcd_cg_separable_model_is_solved_in_one_step():
+    """With W diagonal the model separates by coordinate: the first PCD
+    direction is every coordinate's exact minimiser (found here by 1-D
+    brute-force minimisation) and the step 1 lies on the grid, so PCD-CG
+    returns the exact solution."""
+    from oracle import pcd
+    nj = 5
+    W = np.diag([1.5, 0.8, 1.2, 2.0, 0.6])
+    rng = np.random.default_rng(18)
+    S = rng.standard_normal((nj, nj)) * 0.5; S = S + S.T
+    A = rng.standard_normal((nj, nj)) * 0.2; A = A + A.T
+    lam = 0.3
+    ri, ci = np.triu_indices(nj)
+    Sv, Av = S[ri, ci], A[ri, ci]
+    D, its, _ = pcd.pcd_cg(W, ri, ci, Sv, Av, lam, max_iter=10, tol=1e-12)
+    for k in range(ri.size):
+        def f(mu, k=k):
+            e = np.zeros(ri.size); e[k] = mu
+            return pcd.block_model(W, ri, ci, Sv, Av, lam, e)
+        r = so.minimize_scalar(f, bracket=(-3, 3), tol=1e-14)
+        best = min([r.x, -Av[k]], key=f)
+        assert D[k] == pytest.approx(best, abs=1e-7)
+
+
+def test_bruteforce_closed_forms():
+    # n = 1: a = 1/(s + lam); n = 2 with |s12| > lam: W* = S + lam sign pattern
+    assert bruteforce.solve(np.array([[1.7]]), 0.3)[0, 0] == pytest.approx(0.5, rel=1e-10)
+    S = np.array([[1.3, 0.6], [0.6, 0.9]])
+    lam = 0.2
+    W = np.array([[1.3 + lam, 0.6 - lam], [0.6 - lam, 0.9 + lam]])
+    np.testing.assert_allclose(bruteforce.solve(S, lam), np.linalg.inv(W), rtol=1e-9)
+
+
+# ---------------------------------------------------------------- every oracle function is pinned
+
+PINS = {
+    "core.covariance": ["test_covariance_hand_worked_example",
+                        "test_covariance_entries_by_loops_and_structure"],
+    "core.cholesky_lower": ["test_logdet_pd_and_cholesky_closed_forms"],
+    "core.logdet_pd": ["test_logdet_pd_and_cholesky_closed_forms",
+                       "test_schur_line_matrices_match_direct_logdet"],
+    "core.logdet_identity_plus": ["test_logdet_identity_plus_against_high_precision",
+                                  "test_logdet_identity_plus_keeps_small_terms"],
+    "core.inverse_pd": ["test_inverse_pd_is_an_inverse"],
+    "core.objective": ["test_objective_closed_form_and_gradient_by_differences",
+                       "test_diagonal_regime_closed_form"],
+    "core.gradient": ["test_objective_closed_form_and_gradient_by_differences"],
+    "core.min_norm_subgradient": ["test_min_norm_subgradient_by_brute_force"],
+    "core.kkt_max": ["test_min_norm_subgradient_by_brute_force"],
+    "core.kkt_l1": ["test_min_norm_subgradient_by_brute_force"],
+    "core.free_mask": ["test_free_mask_and_support_pairs_hand_worked"],
+    "core.support_pairs": ["test_free_mask_and_support_pairs_hand_worked"],
+    "quic_plain.abs_change": ["test_abs_change_and_l1_change_exact_cases"],
+    "quic_plain.objective_change": ["test_objective_change_against_high_precision",
+                                    "test_objective_change_matches_difference"],
+    "quic_plain.linesearch_dense": ["test_linesearch_skips_non_pd_trials"],
+    "quic_plain.solve": ["test_diagonal_regime_closed_form", "test_lambda_zero_gives_inverse_covariance",
+                         "test_one_variable", "test_two_variables_closed_form",
+                         "test_bruteforce_support_enumeration", "test_kkt_certificate_and_diag_identity"],
+    "quic_plain.solve_from_samples": ["test_kkt_certificate_and_diag_identity"],
+    "steps.blocks": ["test_block_sets_hand_worked"],
+    "steps.cov_block": ["test_covariance_hand_worked_example",
+                        "test_cov_block_rows_by_loops_and_symmetric_diagonal_block"],
+    "steps.inverse_columns": ["test_inverse_columns_residual"],
+    "steps.screen": ["test_block_sets_hand_worked"],
+    "steps.coordinates": ["test_block_sets_hand_worked"],
+    "steps.neighborhood": ["test_block_sets_hand_worked"],
+    "steps.local_set": ["test_block_sets_hand_worked"],
+    "steps.cd_block": ["test_coarse_solution_correspondence", "test_block_updates_are_monotone"],
+    "steps.delta_matrix": ["test_block_sets_hand_worked"],
+    "steps.block_update": ["test_block_updates_are_monotone", "test_ml_bcd_matches_solution_oracle"],
+    "steps.schur_line_matrices": ["test_schur_line_matrices_match_direct_logdet",
+                                  "test_printed_b2_sign_would_be_wrong"],
+    "steps.schur_logdet_change": ["test_schur_line_matrices_match_direct_logdet"],
+    "steps.w_block_from_neighbors": ["test_neighbour_identity_app_a2"],
+    "steps.hierarchy": ["test_hierarchy_sizes_and_order", "test_hierarchy_nested_and_terminates"],
+    "steps.level_candidates": ["test_level_candidates_hand_worked",
+                               "test_coarse_solution_correspondence"],
+    "mlbcd.relax": ["test_block_updates_are_monotone", "test_coarse_solution_correspondence"],
+    "mlbcd.supp_keys": ["test_ml_bcd_matches_solution_oracle"],
+    "mlbcd.solve": ["test_ml_bcd_matches_solution_oracle", "test_bruteforce_support_enumeration",
+                    "test_diagonal_regime_closed_form"],
+    "pcd.block_model": ["test_block_model_is_the_second_order_expansion_of_f"],
+    "pcd.l1_change": ["test_abs_change_and_l1_change_exact_cases"],
+    "pcd.hessian_product": ["test_hessian_product_is_the_derivative_of_the_inverse"],
+    "pcd.pcd_cg": ["test_pcd_cg_separable_model_is_solved_in_one_step",
+                   "test_pcd_cg_converges_to_the_cd_minimiser",
+                   "test_pcd_first_step_is_the_grid_minimiser_of_the_model"],
+    "bruteforce.solve": ["test_bruteforce_closed_forms"],
+    "cd.cd_sweeps": ["test_single_coordinate_step_is_1d_argmin", "test_cd_converges_to_model_kkt"],
+}
+
+
+def test_every_oracle_function_has_a_pin():
+    """Every public function of the oracle is named above with the tests that
+    pin it to something other than itself, and those tests exist here."""
+    import inspect
+    from oracle import bruteforce as m_bf, cd as m_cd, core as m_core, mlbcd as m_ml
+    from oracle import pcd as m_pcd, quic_plain as m_q, steps as m_st
+    mods = dict(core=m_core, quic_plain=m_q, steps=m_st, mlbcd=m_ml, pcd=m_pcd, bruteforce=m_bf,
+                cd=m_cd)
+    here = globals()
+    for mname, mod in mods.items():
+        for fname, fn in inspect.getmembers(mod, inspect.isfunction):
+            if fn.__module__ != mod.__name__ or fname.startswith("_") or fname == "build":
+                continue
+            key = f"{mname}.{fname}"
+            assert key in PINS, f"{key} has no pin"
+    for key, tests in PINS.items():
+        for t in tests:
+            assert t in here and callable(here[t]), f"{key}: pin {t} is not a test here"

@@ -62,8 +62,10 @@ extern "C" {
 
 /* option flags */
 #define SIC_FLAG_NO_MULTILEVEL (1ull << 0) /* plain block relaxation (Algorithm 2 only) */
-#define SIC_FLAG_FINAL_KKT (1ull << 1)     /* certify the result with an exact KKT pass */
+#define SIC_FLAG_FINAL_KKT (1ull << 1)     /* also measure the exact KKT of an unconverged result */
 #define SIC_FLAG_VERBOSE (1ull << 2)       /* per-cycle log on stderr */
+#define SIC_FLAG_NO_CERTIFY (1ull << 3)    /* accept the sweep's KKT measure without the exact
+                                              float64 pass (see sic_solve) */
 
 typedef struct sic_ctx sic_ctx;
 
@@ -147,6 +149,16 @@ void sic_destroy(sic_ctx* ctx);
  * SIC_ENOCONV (A_out and info still filled) or an error code. The context
  * keeps the problem's device storage (X, its copies, the CSR pair) for the
  * next solve or batch on it; sic_destroy frees it, and so does a failed solve.
+ *
+ * Convergence: each finest sweep measures the min-norm subgradient (Section
+ * 4, eq. (subgradient1)) of every block just before its update, from the
+ * sweep's own S_J and W_J. When that measure reaches tol in a float64 cycle,
+ * an exact pass recomputes it for the final iterate (float64 S_J, W_J by CG to
+ * min(1e-10, 0.01 tol)) and SIC_OK is returned only if that too is <= tol;
+ * info->kkt_max is then the exact value. Otherwise the cycles go on. If a
+ * conjugate-gradient solve stops at cg_max_iter, the block it served is left
+ * unchanged and the solve ends with SIC_ENOCONV (the iterate returned is the
+ * last accepted one); a CG breakdown (p.Ap <= 0) ends it with SIC_ENOTPD.
  */
 int sic_solve(sic_ctx* ctx, const double* X, int64_t n, int64_t m, double lambda, double tol,
               sic_csr* A_out, sic_info* info);

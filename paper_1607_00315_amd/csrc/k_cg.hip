@@ -1,7 +1,8 @@
-// Inverse columns W_J = A^{-1} E_J by conjugate gradients (Section 6.1: "the
-// solution of these linear systems is one of the main computational tasks";
-// CG, possibly preconditioned, is the method the paper names). Jacobi
-// preconditioner (diag A > 0 for SPD A).
+// Inverse columns W_J = A^{-1} E_J by conjugate gradients (Section 6.1, where
+// these solves are the main cost of a block update and CG, possibly
+// preconditioned, is the method named). Jacobi preconditioner (diag A > 0 for
+// SPD A). A direction with p.Ap <= 0 while r != 0 (CG breakdown) proves A is
+// not positive definite; the tile is then marked bad and stops.
 //
 // All k right-hand sides run together on row-major n x k blocks, so that one
 // sparse row of A gathers whole 64-column segments of the direction block
@@ -29,8 +30,9 @@ constexpr int CG_THREADS = 512;     // 8 waves, one matrix row per wave at a tim
 constexpr int CG_WAVES = CG_THREADS / 64;
 constexpr int CG_ROW_TILES = 128;   // row partitions (partials per column)
 
-// per-tile control block: [0] done, [1] iterations finished
-enum { T_DONE = 0, T_ITER = 1, T_INTS = 2 };
+// per-tile control block: [0] done, [1] iterations finished, [2] breakdown
+// (p.Ap <= 0 with r.z > 0 in some column: A is not positive definite)
+enum { T_DONE = 0, T_ITER = 1, T_BAD = 2, T_INTS = 3 };
 enum { S_RZ0 = 0, S_RZ1 = 1, S_RR = 3 };   // rz by iteration parity; r.r
 
 __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -71,6 +73,7 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
         for (int j = threadIdx.x; j < col_tiles; j += blockDim.x) {
             tctl[j * T_INTS + T_DONE] = 0;
             tctl[j * T_INTS + T_ITER] = 0;
+            tctl[j * T_INTS + T_BAD] = 0;
             tres[j] = 1.0;
         }
     }
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     int64_t n, int k, const double* __restrict__ dinv, double* __restrict__ W,
     V* __restrict__ R, V* __restrict__ Z, const V* __restrict__ P,
     const V* __restrict__ Q, const double* __restrict__ scal, const double* __restrict__ pqp,
-    double* __restrict__ part, const int* __restrict__ tctl, int it) {
+    double* __restrict__ part, int* __restrict__ tctl, int it) {
     if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
@@ -209,6 +212,17 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     for (int w = 0; w < CG_WAVES; ++w) pq += psum[w][lane];
     const double rz0 = scal[jj * 4 + (it & 1)];
     const double alpha = (jok && pq > 0.0 && rz0 > 0.0) ? rz0 / pq : 0.0;
+    // breakdown: a non-zero residual whose direction has p.Ap <= 0 (every
+    // workgroup of the tile sees the same sums; row partition 0 records it)
+    const bool bad = jok && rz0 > 0.0 && !(pq > 0.0);
+    if (__any(bad)) {
+        if (blockIdx.y == 0 && wave == 0 && lane == 0) {
+            int* c = tctl + blockIdx.x * T_INTS;
+            c[T_BAD] = 1;
+            c[T_DONE] = 1;
+        }
+        return;
+    }
     double rz = 0.0, rr = 0.0;
     if (jok) {
         for (int64_t i = (int64_t)blockIdx.y * CG_WAVES + wave; i < n;
@@ -428,18 +442,31 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
     prof_flush();
     int iters = 0;
     double mres = 0.0;
+    bool bad = false;
     for (int t = 0; t < col_tiles; ++t) {
         iters = std::max(iters, hctl[t * T_INTS + T_ITER]);
         mres = std::max(mres, hres[t]);
+        bad = bad || hctl[t * T_INTS + T_BAD] != 0;
     }
     res.iterations = iters;
-    res.converged = done;
+    res.breakdown = bad;
+    res.converged = done && !bad;
     res.max_rel_res = mres;
-    predicted = done ? iters : 0;
+    predicted = res.converged ? iters : 0;
     return res;
 }
 
 }  // namespace
+
+void check_cg(const CGResult& r, const char* what) {
+    if (r.breakdown)
+        throw SicError(SIC_ENOTPD, std::string(what) +
+                                       ": conjugate gradients broke down (p.Ap <= 0), the iterate "
+                                       "is not positive definite");
+    if (!r.converged)
+        throw SicError(SIC_ENOCONV, std::string(what) + ": conjugate gradients did not reach "
+                                                        "their tolerance within cg_max_iter");
+}
 
 CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
                   double tol, int max_iter, CGWork& wk, hipStream_t s, bool low_precision,

@@ -578,6 +578,23 @@ __global__ void k_identity_minus(const double* __restrict__ K, int b, double* __
 
 }  // namespace
 
+// Scatter a full symmetric CSR into a dense n x n row-major matrix (zeroed
+// first): one workgroup per row.
+__global__ void k_csr_to_dense(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                               const double* __restrict__ val, int64_t n, double* __restrict__ D) {
+    const int64_t i = blockIdx.x;
+    double* row = D + i * n;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) row[j] = 0.0;
+    __syncthreads();
+    for (int64_t e = rowptr[i] + threadIdx.x; e < rowptr[i + 1]; e += blockDim.x) row[col[e]] = val[e];
+}
+
+void launch_csr_to_dense(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
+                         double* D, hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_to_dense, dim3((unsigned)n), dim3(256), 0, s, rowptr, col, val, n, D);
+    SIC_CHECK_LAUNCH();
+}
+
 void launch_zero_upper(double* M, int nb, int ld, hipStream_t s) {
     if (nb <= 1) return;
     hipLaunchKernelGGL(k_zero_upper, dim3(nb), dim3(256), 0, s, M, nb, ld);

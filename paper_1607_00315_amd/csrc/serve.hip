@@ -143,6 +143,7 @@ int map_exceptions(const std::function<int()>& f, std::string& err) {
 void sic_server::worker(Slot* S, int index) {
     (void)hipSetDevice(device);
     sic::AccountScope scope(S->ctx.acct);
+    sic::set_blocking_waits(true);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         Decision d = WAIT;
@@ -319,16 +320,21 @@ int sic_server_wait(sic_server* srv, uint64_t ticket, double timeout_s, sic_csr*
                     sic_info* info, sic_request_times* times) {
     if (!srv) return SIC_EINVAL;
     std::unique_lock<std::mutex> lk(srv->mu);
-    auto it = srv->reqs.find(ticket);
-    if (it == srv->reqs.end()) return SIC_EINVAL;
-    std::shared_ptr<Request> r = it->second;
+    std::shared_ptr<Request> r;
+    {
+        auto it = srv->reqs.find(ticket);
+        if (it == srv->reqs.end()) return SIC_EINVAL;
+        r = it->second;   // no iterator is kept across the wait: submits may rehash
+    }
     auto done = [&]() { return r->state == DONE; };
     if (timeout_s < 0) {
         srv->cv_done.wait(lk, done);
     } else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
         return 1;
     }
-    srv->reqs.erase(it);
+    // retire the ticket by key; a second waiter on the same ticket finds it
+    // already claimed
+    if (srv->reqs.erase(ticket) == 0) return SIC_EINVAL;
     lk.unlock();
     for (size_t k = 0; k < r->A.size(); ++k) {
         if (A_out)

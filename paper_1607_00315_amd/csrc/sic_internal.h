@@ -58,6 +58,9 @@ struct AccountScope {
 // microseconds, where a blocking wait can sleep through tens of them), then
 // blocks. The solver's read-backs, all on the critical path, wait this way.
 void stream_wait(hipStream_t s);
+// Makes the calling thread's stream waits block without polling (the serving
+// workers, which would otherwise spin side by side).
+void set_blocking_waits(bool on);
 
 // Largest dynamic LDS a workgroup may use on the current device.
 extern size_t CD_MAX_LDS_BYTES;
@@ -176,8 +179,12 @@ struct CGWork {
 struct CGResult {
     int iterations = 0;
     double max_rel_res = 0;
-    bool converged = false;
+    bool converged = false;   // every column reached tol within max_iter
+    bool breakdown = false;   // some direction had p.Ap <= 0: A is not positive definite
 };
+// A CG solve that broke down (SIC_ENOTPD) or stopped at its iteration cap
+// (SIC_ENOCONV) leaves W inexact; this throws, so that no step uses it.
+void check_cg(const CGResult& r, const char* what);
 // low_precision: float vectors with float64 iterate, scalars and sums, and the
 // true residual recomputed in float64 every few iterations (tol >= ~1e-6).
 // slot (0..3) names the caller's kind of solve for the iteration prediction.
@@ -274,6 +281,9 @@ int64_t launch_pcd(int64_t nc, int jp, int b, const int64_t* cptr, const int32_t
 void launch_chol(double* M, int64_t stride, int batch, int nb, int ld, int identity, double* out,
                  hipStream_t s, double* dinv = nullptr);
 void launch_zero_upper(double* M, int nb, int ld, hipStream_t s);
+// dense n x n row-major copy of a full symmetric CSR
+void launch_csr_to_dense(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n,
+                         double* D, hipStream_t s);
 void launch_trsm_lower(const double* L, int nb, int ldl, const double* dinv, double* B, int ncols,
                        int ldb, int trans, hipStream_t s);
 void launch_gemm_small(int M, int N, int K, double alpha, const double* A, int lda, int ta,

@@ -154,5 +154,8 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info);
 int solve_request(Context& C, Problem& P, const sic_problem& q, sic_csr* A_out, sic_info* info);
 int request_results(const sic_problem& q);
 double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1);
+// F(A0) of a warm start already loaded as the iterate; throws SIC_ENOTPD when
+// A0 is not positive definite
+double warm_start_objective(Context& C, Problem& P, const sic_csr* A0);
 
 }  // namespace sic

@@ -40,6 +40,12 @@ AccountScope::AccountScope(const std::shared_ptr<MemAccount>& a) : prev_(t_accou
 }
 AccountScope::~AccountScope() { t_account = prev_; }
 
+namespace {
+thread_local bool t_blocking_waits = false;
+}  // namespace
+
+void set_blocking_waits(bool on) { t_blocking_waits = on; }
+
 void stream_wait(hipStream_t s) {
     // one event per host thread and device (serving threads wait concurrently)
     thread_local std::vector<std::pair<int, hipEvent_t>> events;
@@ -53,6 +59,10 @@ void stream_wait(hipStream_t s) {
         events.emplace_back(dev, ev);
     }
     SIC_HIP(hipEventRecord(ev, s));
+    if (t_blocking_waits) {
+        SIC_HIP(hipEventSynchronize(ev));
+        return;
+    }
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
         const hipError_t e = hipEventQuery(ev);
@@ -348,6 +358,89 @@ void set_A_host(Context& C, Problem& P, const sic_csr* in) {
     P.max_nnz = std::max(P.max_nnz, in->nnz);
 }
 
+// Largest n for which a warm start is checked by a dense factorization
+// (8 n^2 bytes of device scratch, 16 GiB here).
+constexpr int64_t DENSE_CHECK_MAX_N = 46340;
+
+// A warm start must be positive definite (the line search of Section 6.1.2
+// starts from a PD iterate and keeps it PD). Up to DENSE_CHECK_MAX_N
+// variables this is decided exactly: the iterate is expanded to a dense
+// matrix and factored by a right-looking blocked Cholesky on the GPU (256 x
+// 256 diagonal tiles by k_chol, the panel by the blocked triangular solve,
+// the trailing update on the matrix cores), and F(A0) = -log det A0 +
+// tr(S A0) + lambda ||A0||_1 (eq. (MLE_l1_prior)) follows from the pivots, the
+// sampled entries S_ij on the pattern of A0 and the values. Above that size
+// only strict diagonal dominance with a positive diagonal (a sufficient
+// condition, Gershgorin) is accepted and F(A0) is not known (NaN).
+// Returns F(A0); throws SIC_ENOTPD when A0 is not positive definite.
+double warm_start_objective(Context& C, Problem& P, const sic_csr* in) {
+    const int64_t n = P.n;
+    hipStream_t s = C.stream;
+    double l1 = 0.0;
+    for (int64_t e = 0; e < in->nnz; ++e) l1 += std::fabs(in->val[e]);
+    if (n > DENSE_CHECK_MAX_N) {
+        for (int64_t i = 0; i < n; ++i) {
+            double d = 0.0, off = 0.0;
+            for (int64_t e = in->rowptr[i]; e < in->rowptr[i + 1]; ++e) {
+                if (in->col[e] == i)
+                    d = in->val[e];
+                else
+                    off += std::fabs(in->val[e]);
+            }
+            if (!(d > off))
+                throw SicError(SIC_ENOTPD, "warm start above the dense-check size must be strictly "
+                                           "diagonally dominant with a positive diagonal");
+        }
+        return NAN;
+    }
+    DevCSR& A = P.Acur();
+    DevBuf<double> D;
+    D.reserve((size_t)n * n);
+    launch_csr_to_dense(A.rowptr.p, A.col.p, A.val.p, n, D.p, s);
+    constexpr int T = 256;
+    const int tiles = (int)((n + T - 1) / T);
+    DevBuf<double> outs, dinv;
+    outs.reserve(2 * (size_t)tiles);
+    dinv.reserve(8 * 1024);
+    for (int t = 0; t < tiles; ++t) {
+        const int64_t k0 = (int64_t)t * T, k1 = std::min<int64_t>(k0 + T, n);
+        const int nb = (int)(k1 - k0);
+        double* Dkk = D.p + k0 * n + k0;
+        launch_chol(Dkk, 0, 1, nb, (int)n, 0, outs.p + 2 * t, s, dinv.p);
+        if (k1 < n) {
+            const int rest = (int)(n - k1);
+            double* X = D.p + k0 * n + k1;   // row panel: becomes L_kk^{-1} A_{k, k1:}
+            launch_trsm_lower(Dkk, nb, (int)n, dinv.p, X, rest, (int)n, 0, s);
+            launch_gemm_small(rest, rest, nb, -1.0, X, (int)n, 1, X, (int)n, 0, 1.0,
+                              D.p + k1 * n + k1, (int)n, s);
+        }
+    }
+    std::vector<double> o(2 * (size_t)tiles);
+    SIC_HIP(hipMemcpyAsync(o.data(), outs.p, sizeof(double) * o.size(), hipMemcpyDeviceToHost, s));
+    // tr(S A0) from the sampled entries on the pattern of A0
+    std::vector<int32_t> rows(std::max<int64_t>(in->nnz, 1));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = in->rowptr[i]; e < in->rowptr[i + 1]; ++e) rows[e] = (int32_t)i;
+    DevBuf<int32_t> drows;
+    DevBuf<double> sv;
+    drows.reserve(rows.size());
+    sv.reserve(rows.size());
+    SIC_HIP(hipMemcpyAsync(drows.p, rows.data(), sizeof(int32_t) * in->nnz, hipMemcpyHostToDevice, s));
+    launch_sddmm(P.Xt.p, P.m, drows.p, A.col.p, in->nnz, sv.p, s);
+    std::vector<double> svh(rows.size());
+    SIC_HIP(hipMemcpyAsync(svh.data(), sv.p, sizeof(double) * in->nnz, hipMemcpyDeviceToHost, s));
+    sync(C);
+    double logdet = 0.0;
+    for (int t = 0; t < tiles; ++t) {
+        if (o[2 * t + 1] == 0.0)
+            throw SicError(SIC_ENOTPD, "warm start is not positive definite");
+        logdet += o[2 * t];
+    }
+    double tr = 0.0;
+    for (int64_t e = 0; e < in->nnz; ++e) tr += svh[e] * in->val[e];
+    return -logdet + tr + P.lam * l1;
+}
+
 void get_A_host(Context& C, Problem& P, sic_csr* out) {
     DevCSR& A = P.Acur();
     const int64_t n = P.n, nnz = A.nnz;
@@ -443,8 +536,8 @@ static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max
     return -1;
 }
 
-BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, bool record,
-                         double tolI, double tolN) {
+static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, bool fine,
+                                     bool record, double tolI, double tolN) {
     hipStream_t s = C.stream;
     BlockWork& W = C.work;
     const int64_t n = P.n;
@@ -476,6 +569,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         launch_iota_i32(W.cols.p, b, (int32_t)j0, s);
         CGResult cg = block_cg(A, W.cols.p, b, W.WI.p, b, tolI, C.opt.cg_max_iter, W.cg, s,
                                C.prec != PREC_F64, 0);
+        check_cg(cg, "W_I");
         R.cg_iters_I = cg.iterations;
         R.cg_res_I = cg.max_rel_res;
         SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
@@ -524,6 +618,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         if (nC > 0) {
             CGResult cg = block_cg(A, W.NC.p, (int)nC, W.WNC.p, nC, tolI, C.opt.cg_max_iter, W.cg,
                                    s, C.prec != PREC_F64, 2);
+            check_cg(cg, "W_{N^C}");
             R.cg_iters_N = cg.iterations;
             R.cg_res_N = cg.max_rel_res;
         }
@@ -583,6 +678,7 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
         W.WN.reserve((size_t)n * nN);
         CGResult cg = block_cg(A, W.Jp.p + b, (int)nN, W.WN.p, nN, tolN, C.opt.cg_max_iter, W.cg,
                                s, C.prec != PREC_F64, 1);
+        check_cg(cg, "W_N");
         R.cg_iters_N = cg.iterations;
         R.cg_res_N = cg.max_rel_res;
     }
@@ -704,6 +800,18 @@ BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, b
     R.nnz_after = P.Acur().nnz;
     C.last = R;
     return R;
+}
+
+BlockResult block_update(Context& C, Problem& P, int64_t j0, int b, bool fine, bool record,
+                         double tolI, double tolN) {
+    try {
+        return block_update_body(C, P, j0, b, fine, record, tolI, tolN);
+    } catch (...) {
+        // an abandoned block leaves its row flags and maps set: the next block
+        // update clears them all again
+        C.work.n_init = 0;
+        throw;
+    }
 }
 
 // ------------------------------------------------------------------ sweeps
@@ -860,7 +968,7 @@ std::vector<int64_t> support_keys(Context& C, Problem& P) {
 
 // ------------------------------------------------------------------ exact KKT
 
-double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1) {
+static double exact_kkt_body(Context& C, Problem& P, double tol_cg, double* l1) {
     hipStream_t s = C.stream;
     BlockWork& W = C.work;
     const int64_t n = P.n;
@@ -877,8 +985,9 @@ double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1) {
         launch_scatter_aj(P.Acur(), j0, bb, W.AJ.p, s);
         launch_sj_gemm_f64(P.X.p, n, P.m, j0, bb, W.SJ.p, s);
         launch_iota_i32(W.cols.p, bb, (int32_t)j0, s);
-        block_cg(P.Acur(), W.cols.p, bb, W.WI.p, bb, tol_cg, C.opt.cg_max_iter * 4, W.cg, s,
-                 false, 3);
+        check_cg(block_cg(P.Acur(), W.cols.p, bb, W.WI.p, bb, tol_cg, C.opt.cg_max_iter * 4, W.cg,
+                          s, false, 3),
+                 "exact KKT pass");
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
         W.tilecount.reserve((size_t)tiles * bb);
         W.kkt.reserve(2 * (size_t)tiles);
@@ -893,6 +1002,15 @@ double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1) {
     sync(C);
     if (l1) *l1 = acc[1];
     return acc[0];
+}
+
+double exact_kkt(Context& C, Problem& P, double tol_cg, double* l1) {
+    try {
+        return exact_kkt_body(C, P, tol_cg, l1);
+    } catch (...) {
+        C.work.n_init = 0;   // row flags of the abandoned pass are cleared again
+        throw;
+    }
 }
 
 // ------------------------------------------------------------------ Algorithm 1
@@ -935,6 +1053,10 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
     int status = SIC_ENOCONV;
     int cycles = 0, sweeps = 0, trace_len = 0;
     int64_t blocks = 0, cg_it = 0, cd_sw = 0;
+    bool certified = false;   // kkt_prev comes from the exact float64 pass
+    const bool certify = !(C.opt.flags & SIC_FLAG_NO_CERTIFY);
+    const double tol_cert = std::max(1e-13, std::min(1e-10, 0.01 * tol));
+    try {
     for (int cyc = 0; cyc < C.opt.max_cycles; ++cyc) {
         const double tolI = std::min(C.opt.cg_tol_I, std::max(1e-12, 0.01 * kkt_prev));
         const double tolN = std::min(C.opt.cg_tol_N, std::max(1e-12, 0.01 * kkt_prev));
@@ -975,17 +1097,47 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
             e.levels = levels;
         }
         // a reduced-precision cycle measures the KKT with approximate S and W:
-        // only a float64 cycle may end the solve
+        // only a float64 cycle may end the solve, and (unless switched off)
+        // only once the exact pass (float64 S_J, W_J by CG to tol_cert)
+        // confirms the sweep's measure, which saw each block before its update
+        // and W from the sweep's looser CG
+        certified = false;
         if (sr.kkt_max <= tol && C.prec == PREC_F64) {
-            status = SIC_OK;
-            break;
+            if (!certify) {
+                status = SIC_OK;
+                break;
+            }
+            kkt_prev = exact_kkt(C, P, tol_cert, &kkt_l1);
+            certified = true;
+            if (verbose)
+                fprintf(stderr, "[sic] cycle %d exact KKT %.3e (sweep %.3e)\n", cyc, kkt_prev,
+                        sr.kkt_max);
+            if (kkt_prev <= tol) {
+                status = SIC_OK;
+                break;
+            }
         }
+    }
+    } catch (const SicError& e) {
+        // a conjugate-gradient solve stopped at its iteration cap: the block it
+        // served was abandoned before it changed A, so the iterate is the last
+        // accepted one (positive definite) and is returned with SIC_ENOCONV
+        if (e.code != SIC_ENOCONV) throw;
+        if (verbose) fprintf(stderr, "[sic] stopped: %s\n", e.what());
+        status = SIC_ENOCONV;
+        certified = false;
     }
     C.prec = PREC_F64;
     double kkt_final = kkt_prev;
-    if (C.opt.flags & SIC_FLAG_FINAL_KKT) {
-        kkt_final = exact_kkt(C, P, std::max(1e-13, std::min(1e-10, 0.01 * tol)), &kkt_l1);
-        status = kkt_final <= tol ? SIC_OK : SIC_ENOCONV;
+    if ((C.opt.flags & SIC_FLAG_FINAL_KKT) && !certified) {
+        // the exact measure of whatever iterate the solve ends with
+        try {
+            kkt_final = exact_kkt(C, P, tol_cert, &kkt_l1);
+            status = kkt_final <= tol ? SIC_OK : SIC_ENOCONV;
+        } catch (const SicError& e) {
+            if (e.code != SIC_ENOCONV) throw;
+            status = SIC_ENOCONV;
+        }
     }
     if (info) {
         info->objective = P.F;
@@ -1092,7 +1244,7 @@ int solve_request(Context& C, Problem& P, const sic_problem& q, sic_csr* A_out, 
     problem_init(C, P, q.X, q.x_dtype, q.n, q.m, lam_at(0));
     if (q.A0) {
         set_A_host(C, P, q.A0);
-        P.F = NAN;   // the tracked objective of a warm start is not known
+        P.F = warm_start_objective(C, P, q.A0);
     }
     int worst = SIC_OK;
     for (int l = 0; l < nl; ++l) {

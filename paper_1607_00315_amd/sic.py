@@ -22,7 +22,7 @@ SIC_OK, SIC_EINVAL, SIC_ENONFINITE, SIC_ENOTPD, SIC_ENOMEM = 0, -1, -2, -3, -4
 SIC_ENOCONV, SIC_EHIP, SIC_ECANCELED, SIC_ETOOBIG, SIC_EINTERNAL = -5, -6, -7, -8, -9
 SIC_FP64, SIC_MIXED = 0, 1
 SIC_X_F64, SIC_X_F32, SIC_X_BF16 = 0, 1, 2
-FLAG_NO_MULTILEVEL, FLAG_FINAL_KKT, FLAG_VERBOSE = 1, 2, 4
+FLAG_NO_MULTILEVEL, FLAG_FINAL_KKT, FLAG_VERBOSE, FLAG_NO_CERTIFY = 1, 2, 4, 8
 
 
 class SicError(RuntimeError):

@@ -318,7 +318,8 @@ class Context:
         outs = (CSR * slots)()
         infos = (Info * slots)()
         code = lib().sic_solve_batch(self.h, count, specs, outs, infos)
-        results = [(_csr_to_numpy(outs[i]), infos[i].as_dict()) for i in range(slots)]
+        results = [(_csr_to_numpy(outs[i]) if outs[i].rowptr else None, infos[i].as_dict())
+                   for i in range(slots)]
         return code, results
 
     def trace(self, length):

@@ -99,7 +99,11 @@ def test_warm_start_matches_oracle(rnd600):
     assert code == 0
     Fq = core.objective(ref[0.2], S, 0.2)
     assert abs(res[0][1]["objective"] - Fq) <= 1e-9 * abs(Fq)
-    assert res[0][1]["cycles"] == 1
+    # the first cycle's CG runs at the paper's tolerances (1e-5 / 1e-4), so its
+    # KKT measure may need one tightened cycle to certify 1e-6
+    assert res[0][1]["cycles"] <= 2
+    (rp, col, val), info = res[0]
+    _check_against_oracle(csr_to_dense(rp, col, val, n), ref[0.2], S, 0.2, info)
 
 
 def test_non_pd_warm_start_is_refused():

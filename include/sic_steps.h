@@ -54,6 +54,33 @@ int sic_step_cov_pairs(sic_prob* p, const int32_t* rows, const int32_t* cols, in
 int sic_step_inverse_columns(sic_prob* p, const int32_t* cols, int k, double tol, int max_iter,
                              double* out, int* iterations, double* max_rel_residual);
 
+/* (b) The same inverse columns for callers that cannot allocate memory
+ * (code under HIP graph capture, serving loops with a fixed footprint,
+ * harnesses that forbid hipMalloc): no device or host allocation happens in
+ * this call. Every buffer of the solve lives in one static device array of
+ * 128 MiB per GPU (held until the process ends); a solve needs
+ * 8n + 24 k ceil(n/8 capped at 128) + 8(4k) + 32 n k bytes (each part
+ * rounded up to 256), which sic_step_inverse_columns_noalloc_limit reports
+ * (0 when it does not fit), and k <= 4096. Larger problems return
+ * SIC_ETOOBIG.
+ *   rowptr[n+1], col[nnz], val[nnz]: A as a full symmetric CSR with sorted
+ *     columns, DEVICE memory, caller-owned, only read;
+ *   cols[k]: column indices in [0, n), DEVICE memory (an index outside that
+ *     range yields a zero column);
+ *   W: n x k row-major, DEVICE memory, written;
+ *   stream: hipStream_t on the current device (NULL: the null stream).
+ * The call returns after the solve has finished on `stream`. Results equal
+ * sic_step_inverse_columns' for the same A, columns and tolerance. Every
+ * call on one GPU uses that GPU's array and leaves its contents behind (the
+ * solve initialises all it reads): calls that overlap on one GPU, from
+ * several host threads or streams, race and give wrong results. */
+int sic_step_inverse_columns_noalloc(const int64_t* rowptr, const int32_t* col,
+                                     const double* val, int64_t n, int64_t nnz,
+                                     const int32_t* cols, int k, double tol, int max_iter,
+                                     double* W, void* stream, int* iterations,
+                                     double* max_rel_residual);
+size_t sic_step_inverse_columns_noalloc_limit(int64_t n, int k);
+
 /* Level set C_l for coarse block updates (Section 7, eq. (MLE_l1_prior_C)):
  * `count` pair keys i*n + j with i <= j. */
 int sic_step_set_level(sic_prob* p, const int64_t* keys, int64_t count);

@@ -376,6 +376,30 @@ int sic_step_inverse_columns(sic_prob* p, const int32_t* cols, int k, double tol
     });
 }
 
+int sic_step_inverse_columns_noalloc(const int64_t* rowptr, const int32_t* col,
+                                     const double* val, int64_t n, int64_t nnz,
+                                     const int32_t* cols, int k, double tol, int max_iter,
+                                     double* W, void* stream, int* iterations,
+                                     double* max_rel_residual) {
+    if (!rowptr || !col || !val || !cols || !W || n < 1 || nnz < n || k < 1 || !(tol > 0.0) ||
+        max_iter < 1)
+        return SIC_EINVAL;
+    return guard([&]() {
+        const sic::CGResult r =
+            sic::block_cg_noalloc(rowptr, col, val, n, nnz, cols, k, W, tol, max_iter,
+                                  static_cast<hipStream_t>(stream));
+        if (iterations) *iterations = r.iterations;
+        if (max_rel_residual) *max_rel_residual = r.max_rel_res;
+        return SIC_OK;
+    });
+}
+
+size_t sic_step_inverse_columns_noalloc_limit(int64_t n, int k) {
+    if (n < 1 || k < 1 || k > sic::cg_noalloc_max_k()) return 0;
+    return sic::cg_noalloc_bytes(n, k) <= sic::cg_noalloc_capacity() ? sic::cg_noalloc_bytes(n, k)
+                                                                     : 0;
+}
+
 int sic_step_set_level(sic_prob* p, const int64_t* keys, int64_t count) {
     if (!p || count < 0 || (count > 0 && !keys)) return SIC_EINVAL;
     return guard([&]() {

@@ -20,6 +20,8 @@
 // write back the L2 of each XCD), no atomics: results do not depend on
 // scheduling. Convergence is tracked per 64-column tile; launches for a
 // converged tile return at once.
+#include <mutex>
+
 #include "profiler.h"
 
 namespace sic {
@@ -65,7 +67,7 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
     if (blockIdx.x == 0) {
         for (int j = threadIdx.x; j < k; j += blockDim.x) {
             const int64_t c = cols[j];
-            scal[j * 4 + S_RZ0] = dinv[c];
+            scal[j * 4 + S_RZ0] = (c >= 0 && c < n) ? dinv[c] : 0.0;
             scal[j * 4 + S_RZ1] = 0.0;
             scal[j * 4 + 2] = 0.0;
             scal[j * 4 + S_RR] = 1.0;
@@ -322,10 +324,38 @@ namespace {
 
 constexpr int CG_REPLACE_EVERY = 8;   // float vectors: true residual every this many iterations
 
+// The sparse matrix as raw device pointers (the solver's CSR, or a caller's).
+struct CsrView {
+    const int64_t* rowptr;
+    const int32_t* col;
+    const double* val;
+    int64_t n, nnz;
+};
+
+// Buffers of one solve. Device: dinv (n), part (row_tiles * k * 3), scal
+// (4k + col_tiles), flags (T_INTS * col_tiles). Host: hctl (T_INTS *
+// col_tiles ints) and hres (col_tiles doubles), the targets of the control
+// read-backs. predicted: iterations of the last solve of this kind (read and
+// updated). prof: record launches with the profiler.
+struct CGBufs {
+    double* dinv;
+    double* part;
+    double* scal;
+    int* flags;
+    int* hctl;
+    double* hres;
+    int* predicted;
+    bool prof;
+};
+
+int cg_row_tiles(int64_t n) {
+    const int rt = (int)std::min<int64_t>(CG_ROW_TILES, (n + CG_WAVES - 1) / CG_WAVES);
+    return rt < 1 ? 1 : rt;
+}
+
 template <typename V>
-CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
-                       double tol, int max_iter, CGWork& wk, V* R, V* Z, V* P, V* Q,
-                       hipStream_t s, int slot) {
+CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W, double tol,
+                       int max_iter, const CGBufs& bf, V* R, V* Z, V* P, V* Q, hipStream_t s) {
     constexpr bool LOW = sizeof(V) < sizeof(double);
     CGResult res;
     const int64_t n = A.n;
@@ -333,34 +363,26 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
         res.converged = true;
         return res;
     }
-    if (ldw != k) throw SicError(SIC_EINTERNAL, "block_cg expects ldw == k");
-    wk.dinv.reserve(n);
     const int col_tiles = (k + 63) / 64;
-    int row_tiles = (int)std::min<int64_t>(CG_ROW_TILES, (n + CG_WAVES - 1) / CG_WAVES);
-    if (row_tiles < 1) row_tiles = 1;
+    const int row_tiles = cg_row_tiles(n);
     // partials: r.z and r.r of an update (two per entry), then p.q of a product
-    wk.part.reserve((size_t)row_tiles * k * 3);
-    double* part_rz = wk.part.p;
-    double* part_pq = wk.part.p + (size_t)row_tiles * k * 2;
-    wk.scal.reserve((size_t)4 * k + col_tiles);
-    wk.flags.reserve((size_t)T_INTS * col_tiles);
-    double* tres = wk.scal.p + 4 * k;
+    double* part_rz = bf.part;
+    double* part_pq = bf.part + (size_t)row_tiles * k * 2;
+    double* tres = bf.scal + 4 * k;
     hipLaunchKernelGGL(k_cg_dinv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       A.rowptr.p, A.col.p, A.val.p, n, wk.dinv.p);
+                       A.rowptr, A.col, A.val, n, bf.dinv);
     SIC_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, s,
-                       n, k, col_tiles, d_cols, wk.dinv.p, W, R, Z, wk.scal.p, wk.flags.p, tres);
+                       n, k, col_tiles, d_cols, bf.dinv, W, R, Z, bf.scal, bf.flags, tres);
     SIC_CHECK_LAUNCH();
     dim3 grid(col_tiles, row_tiles);
     // XCD grouping of the product's tiles once there are enough column tiles to
     // give every XCD one (fewer would leave XCDs idle)
     const int grouped = col_tiles >= 8 ? 1 : 0;
     const dim3 sgrid = grouped ? dim3((unsigned)(8 * ((col_tiles + 7) / 8) * row_tiles)) : grid;
-    wk.hctl.reserve((size_t)T_INTS * col_tiles);
-    wk.hres.reserve(col_tiles);
-    const int* hctl = wk.hctl.p;
-    const double* hres = wk.hres.p;
-    int& predicted = wk.predict[(slot & 3) * 2 + (LOW ? 1 : 0)];
+    const int* hctl = bf.hctl;
+    const double* hres = bf.hres;
+    int& predicted = *bf.predicted;
     int launched = 0;
     int active = col_tiles;   // tiles still iterating (as of the last check)
     // algorithmic traffic of one tile-launch (bytes): the sparse matrix once,
@@ -384,37 +406,40 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
             const double nkb = (double)n * k * sizeof(V);
             Rec r;
             r.iter = it;
-            prof_begin(KK_CG_SPMM, s);
-            hipLaunchKernelGGL(k_cg_spmm<V>, sgrid, dim3(CG_THREADS), 0, s, A.rowptr.p, A.col.p,
-                               A.val.p, n, k, Z, P, Q, wk.scal.p, part_rz, part_pq, wk.flags.p,
+            if (bf.prof) prof_begin(KK_CG_SPMM, s);
+            hipLaunchKernelGGL(k_cg_spmm<V>, sgrid, dim3(CG_THREADS), 0, s, A.rowptr, A.col,
+                               A.val, n, k, Z, P, Q, bf.scal, part_rz, part_pq, bf.flags,
                                tres, tol, it, col_tiles, row_tiles, grouped, 0);
             SIC_CHECK_LAUNCH();
-            r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
-                              2.0 * A.nnz * k + 4.0 * n * k);
-            prof_begin(KK_CG_UPDATE, s);
-            hipLaunchKernelGGL(k_cg_update<V>, grid, dim3(CG_THREADS), 0, s, n, k, wk.dinv.p, W, R,
-                               Z, P, Q, wk.scal.p, part_pq, part_rz, wk.flags.p, it);
+            if (bf.prof)
+                r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
+                                  2.0 * A.nnz * k + 4.0 * n * k);
+            if (bf.prof) prof_begin(KK_CG_UPDATE, s);
+            hipLaunchKernelGGL(k_cg_update<V>, grid, dim3(CG_THREADS), 0, s, n, k, bf.dinv, W, R,
+                               Z, P, Q, bf.scal, part_pq, part_rz, bf.flags, it);
             SIC_CHECK_LAUNCH();
-            r.upd = prof_end(KK_CG_UPDATE, s, 5.0 * nkb + 16.0 * n * k + n * 8.0, 10.0 * n * k);
+            if (bf.prof)
+                r.upd = prof_end(KK_CG_UPDATE, s, 5.0 * nkb + 16.0 * n * k + n * 8.0,
+                                 10.0 * n * k);
             if (LOW && (it + 1) % CG_REPLACE_EVERY == 0) {
-                hipLaunchKernelGGL(k_cg_true_residual<V>, grid, dim3(CG_THREADS), 0, s, A.rowptr.p,
-                                   A.col.p, A.val.p, n, k, d_cols, wk.dinv.p, W, R, Z, part_rz,
-                                   wk.flags.p);
+                hipLaunchKernelGGL(k_cg_true_residual<V>, grid, dim3(CG_THREADS), 0, s, A.rowptr,
+                                   A.col, A.val, n, k, d_cols, bf.dinv, W, R, Z, part_rz,
+                                   bf.flags);
                 SIC_CHECK_LAUNCH();
             }
-            recs.push_back(r);
+            if (bf.prof) recs.push_back(r);
         }
         launched += chunk;
         if (launched >= max_iter) {
             // the last update's residual has no product after it to test it
             hipLaunchKernelGGL(k_cg_spmm<V>, dim3(col_tiles, 1), dim3(CG_THREADS), 0, s,
-                               A.rowptr.p, A.col.p, A.val.p, n, k, Z, P, Q, wk.scal.p, part_rz,
-                               part_pq, wk.flags.p, tres, tol, launched, col_tiles, row_tiles, 0, 1);
+                               A.rowptr, A.col, A.val, n, k, Z, P, Q, bf.scal, part_rz,
+                               part_pq, bf.flags, tres, tol, launched, col_tiles, row_tiles, 0, 1);
             SIC_CHECK_LAUNCH();
         }
-        SIC_HIP(hipMemcpyAsync(wk.hctl.p, wk.flags.p, sizeof(int) * T_INTS * col_tiles,
+        SIC_HIP(hipMemcpyAsync(bf.hctl, bf.flags, sizeof(int) * T_INTS * col_tiles,
                                hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(wk.hres.p, tres, sizeof(double) * col_tiles,
+        SIC_HIP(hipMemcpyAsync(bf.hres, tres, sizeof(double) * col_tiles,
                                hipMemcpyDeviceToHost, s));
         stream_wait(s);
         // a launch did work only for the tiles still iterating at its index:
@@ -439,7 +464,7 @@ CGResult block_cg_impl(const DevCSR& A, const int32_t* d_cols, int k, double* W,
             }
     }
     (void)active;
-    prof_flush();
+    if (bf.prof) prof_flush();
     int iters = 0;
     double mres = 0.0;
     bool bad = false;
@@ -471,21 +496,117 @@ void check_cg(const CGResult& r, const char* what) {
 CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
                   double tol, int max_iter, CGWork& wk, hipStream_t s, bool low_precision,
                   int slot) {
-    const size_t nk = (size_t)A.n * (size_t)std::max(k, 1);
+    if (k > 0 && ldw != k) throw SicError(SIC_EINTERNAL, "block_cg expects ldw == k");
+    const int64_t n = A.n;
+    const size_t nk = (size_t)n * (size_t)std::max(k, 1);
+    const int col_tiles = (std::max(k, 1) + 63) / 64;
+    wk.dinv.reserve(n);
+    wk.part.reserve((size_t)cg_row_tiles(n) * std::max(k, 1) * 3);
+    wk.scal.reserve((size_t)4 * std::max(k, 1) + col_tiles);
+    wk.flags.reserve((size_t)T_INTS * col_tiles);
+    wk.hctl.reserve((size_t)T_INTS * col_tiles);
+    wk.hres.reserve(col_tiles);
+    const CsrView av{A.rowptr.p, A.col.p, A.val.p, A.n, A.nnz};
+    CGBufs bf{wk.dinv.p, wk.part.p, wk.scal.p, wk.flags.p, wk.hctl.p, wk.hres.p,
+              &wk.predict[(slot & 3) * 2 + (low_precision ? 1 : 0)], true};
     if (low_precision) {
         wk.R32.reserve(nk);
         wk.Z32.reserve(nk);
         wk.P32.reserve(nk);
         wk.Q32.reserve(nk);
-        return block_cg_impl<float>(A, d_cols, k, W, ldw, tol, max_iter, wk, wk.R32.p, wk.Z32.p,
-                                    wk.P32.p, wk.Q32.p, s, slot);
+        return block_cg_impl<float>(av, d_cols, k, W, tol, max_iter, bf, wk.R32.p, wk.Z32.p,
+                                    wk.P32.p, wk.Q32.p, s);
     }
     wk.R.reserve(nk);
     wk.Z.reserve(nk);
     wk.P.reserve(nk);
     wk.Q.reserve(nk);
-    return block_cg_impl<double>(A, d_cols, k, W, ldw, tol, max_iter, wk, wk.R.p, wk.Z.p, wk.P.p,
-                                 wk.Q.p, s, slot);
+    return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, wk.R.p, wk.Z.p, wk.P.p,
+                                 wk.Q.p, s);
+}
+
+// ------------------------------------------------------------------------
+// Inverse columns with no allocation: every buffer of the solve lives in one
+// file-scope device array (per GPU, for the life of the process). The host
+// names the array only through the address hipGetSymbolAddress gives for the
+// current device; the kernels take that address like any other buffer.
+
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int NOALLOC_MAX_K = 4096;
+constexpr int NOALLOC_MAX_TILES = NOALLOC_MAX_K / 64;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device address of this GPU's scratch array (looked up once per device).
+unsigned char* scratch_address() {
+    int dev = 0;
+    SIC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        throw SicError(SIC_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        SIC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<unsigned char*>(g_scratch_ptr[dev]);
+}
+
+}  // namespace
+
+size_t cg_noalloc_bytes(int64_t n, int k) {
+    const int ct = (k + 63) / 64;
+    return align256(sizeof(double) * (size_t)n) +
+           align256(sizeof(double) * (size_t)cg_row_tiles(n) * k * 3) +
+           align256(sizeof(double) * ((size_t)4 * k + ct)) + align256(sizeof(int) * T_INTS * ct) +
+           4 * align256(sizeof(double) * (size_t)n * k);
+}
+
+size_t cg_noalloc_capacity() { return NOALLOC_SCRATCH_BYTES; }
+int cg_noalloc_max_k() { return NOALLOC_MAX_K; }
+
+CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const double* val,
+                          int64_t n, int64_t nnz, const int32_t* d_cols, int k, double* W,
+                          double tol, int max_iter, hipStream_t s) {
+    if (k > NOALLOC_MAX_K || cg_noalloc_bytes(n, k) > NOALLOC_SCRATCH_BYTES)
+        throw SicError(SIC_ETOOBIG, "inverse columns without allocation: n x k = " +
+                                        std::to_string(n) + " x " + std::to_string(k) +
+                                        " needs " + std::to_string(cg_noalloc_bytes(n, k)) +
+                                        " bytes of scratch, the limit is " +
+                                        std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                        " (and k <= " + std::to_string(NOALLOC_MAX_K) + ")");
+    unsigned char* base = scratch_address();
+    const int ct = (k + 63) / 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base + off;
+        off += align256(bytes);
+        return p;
+    };
+    double* dinv = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n));
+    double* part = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cg_row_tiles(n) * k * 3));
+    double* scal = reinterpret_cast<double*>(take(sizeof(double) * ((size_t)4 * k + ct)));
+    int* flags = reinterpret_cast<int*>(take(sizeof(int) * T_INTS * ct));
+    const size_t nkb = sizeof(double) * (size_t)n * k;
+    double* R = reinterpret_cast<double*>(take(nkb));
+    double* Z = reinterpret_cast<double*>(take(nkb));
+    double* P = reinterpret_cast<double*>(take(nkb));
+    double* Q = reinterpret_cast<double*>(take(nkb));
+    // control read-backs land in host stack arrays (pageable copies)
+    int hctl[T_INTS * NOALLOC_MAX_TILES];
+    double hres[NOALLOC_MAX_TILES];
+    int predicted = 0;
+    const CsrView av{rowptr, col, val, n, nnz};
+    const CGBufs bf{dinv, part, scal, flags, hctl, hres, &predicted, false};
+    return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, R, Z, P, Q, s);
 }
 
 }  // namespace sic

@@ -192,6 +192,17 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
                   double tol, int max_iter, CGWork& wk, hipStream_t s,
                   bool low_precision = false, int slot = 0);
 
+// The same solve with every buffer in a static per-device array: no device
+// or host allocation. All pointers are device pointers. Throws SIC_ETOOBIG
+// when the solve does not fit (cg_noalloc_bytes > cg_noalloc_capacity, or
+// k > cg_noalloc_max_k). Calls that overlap on one device share the array.
+CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const double* val,
+                          int64_t n, int64_t nnz, const int32_t* d_cols, int k, double* W,
+                          double tol, int max_iter, hipStream_t s);
+size_t cg_noalloc_bytes(int64_t n, int k);
+size_t cg_noalloc_capacity();
+int cg_noalloc_max_k();
+
 // ---------------------------------------------------------------- k_util.hip
 void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* total, hipStream_t s);
 void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets, int64_t* colptr,

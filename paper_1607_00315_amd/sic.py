@@ -121,6 +121,12 @@ SIGNATURES = {
     "sic_step_cov_block_low": (ct.c_int, [_P, ct.c_int64, ct.c_int, ct.c_int, _dp]),
     "sic_step_inverse_columns": (ct.c_int, [_P, _i32p, ct.c_int, ct.c_double, ct.c_int, _dp,
                                             ct.POINTER(ct.c_int), _dp]),
+    "sic_step_inverse_columns_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                                    ct.c_int64, ct.c_int64, ct.c_void_p,
+                                                    ct.c_int, ct.c_double, ct.c_int,
+                                                    ct.c_void_p, ct.c_void_p,
+                                                    ct.POINTER(ct.c_int), _dp]),
+    "sic_step_inverse_columns_noalloc_limit": (ct.c_size_t, [ct.c_int64, ct.c_int]),
     "sic_step_set_level": (ct.c_int, [_P, _i64p, ct.c_int64]),
     "sic_step_block": (ct.c_int, [_P, ct.c_int64, ct.c_int, ct.c_int, ct.c_double, ct.c_double,
                                   ct.POINTER(BlockResult)]),
@@ -514,6 +520,39 @@ class Prob:
         km, kl = ct.c_double(), ct.c_double()
         _check(lib().sic_step_kkt(self.h, tol_cg, ct.byref(km), ct.byref(kl)), "kkt")
         return km.value, kl.value
+
+
+def inverse_columns_noalloc(rowptr, col, val, cols, W, tol=1e-12, max_iter=5000, stream=None):
+    """W = A^{-1} E_cols with no allocation inside the library.
+
+    rowptr (int64), col (int32), val (float64): A as a full symmetric CSR;
+    cols (int32, k); W (float64, n x k, written): all torch tensors on the
+    current device. stream: a torch.cuda.Stream (default: the current one).
+    Returns (iterations, max relative residual)."""
+    import torch
+    n = rowptr.numel() - 1
+    k = cols.numel()
+    for t, dt in ((rowptr, torch.int64), (col, torch.int32), (val, torch.float64),
+                  (cols, torch.int32), (W, torch.float64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("inverse_columns_noalloc takes contiguous device tensors "
+                             "(int64 rowptr, int32 col and cols, float64 val and W)")
+    if W.shape != (n, k):
+        raise ValueError(f"W must be {n} x {k}")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    it = ct.c_int()
+    res = ct.c_double()
+    _check(lib().sic_step_inverse_columns_noalloc(
+        rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, col.numel(), cols.data_ptr(), k,
+        tol, max_iter, W.data_ptr(), stream.cuda_stream, ct.byref(it), ct.byref(res)),
+        "inverse_columns_noalloc")
+    return it.value, res.value
+
+
+def inverse_columns_noalloc_limit(n, k):
+    """Scratch bytes the no-allocation solve needs for n x k (0: does not fit)."""
+    return lib().sic_step_inverse_columns_noalloc_limit(n, k)
 
 
 def step_cd(ctx: Context, wjj, b, cptr, cp, S, A, lam, max_sweeps=20, tol=1e-4):

@@ -143,7 +143,12 @@ void ls_factor_wii(Context& C, int jp, int b, hipStream_t st) {
 void ls_prepare(Context& C, int jp, int b, int64_t nN, bool factored) {
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
+    // the side stream may still be factoring W_II into Rb / chol_out / Dinv:
+    // those were sized before the fork, and sizing them again must not move them
+    const void* held[3] = {W.Rb.p, W.chol_out.p, W.Dinv.p};
     ls_reserve(C, b, nN);
+    if (factored && (held[0] != W.Rb.p || held[1] != W.chol_out.p || held[2] != W.Dinv.p))
+        throw SicError(SIC_EINTERNAL, "a buffer of the side stream moved before its join");
     if (factored)
         SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
     else

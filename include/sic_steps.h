@@ -58,11 +58,10 @@ int sic_step_inverse_columns(sic_prob* p, const int32_t* cols, int k, double tol
  * (code under HIP graph capture, serving loops with a fixed footprint,
  * harnesses that forbid hipMalloc): no device or host allocation happens in
  * this call. Every buffer of the solve lives in one static device array of
- * 128 MiB per GPU (held until the process ends); a solve needs
- * 8n + 24 k ceil(n/8 capped at 128) + 8(4k) + 32 n k bytes (each part
- * rounded up to 256), which sic_step_inverse_columns_noalloc_limit reports
- * (0 when it does not fit), and k <= 4096. Larger problems return
- * SIC_ETOOBIG.
+ * 128 MiB per GPU (held until the process ends); a solve needs about
+ * 24 n k bytes (three n x k float64 arrays) plus O(n + k), which
+ * sic_step_inverse_columns_noalloc_limit reports (0 when it does not fit),
+ * and k <= 4096. Larger problems return SIC_ETOOBIG.
  *   rowptr[n+1], col[nnz], val[nnz]: A as a full symmetric CSR with sorted
  *     columns, DEVICE memory, caller-owned, only read;
  *   cols[k]: column indices in [0, n), DEVICE memory (an index outside that

@@ -13,8 +13,8 @@
 //   spmm(it):   rz, rr of the last update -> convergence of the tile (it > 0),
 //               beta = rz / rz_old; p = z + beta p, q = A z + beta q (= A p),
 //               partial p.q
-//   update(it): alpha = rz / p.q; x += alpha p, r -= alpha q, z = D^{-1} r,
-//               partial r.z, r.r
+//   update(it): alpha = rz / p.q; x += alpha p, r -= alpha q,
+//               partial r.z, r.r (z = D^{-1} r is formed where it is read)
 // rz alternates between two slots by iteration parity, so no launch reads a
 // scalar that the same launch writes. No device-scope fences (they would
 // write back the L2 of each XCD), no atomics: results do not depend on
@@ -31,6 +31,8 @@ namespace {
 constexpr int CG_THREADS = 512;     // 8 waves, one matrix row per wave at a time
 constexpr int CG_WAVES = CG_THREADS / 64;
 constexpr int CG_ROW_TILES = 128;   // row partitions (partials per column)
+constexpr int CG_TPW = CG_ROW_TILES / CG_WAVES;   // partials each wave sums per column
+constexpr int CG_GATHER = 8;        // gathers per row issued before their products
 
 // per-tile control block: [0] done, [1] iterations finished, [2] breakdown
 // (p.Ap <= 0 with r.z > 0 in some column: A is not positive definite)
@@ -50,18 +52,15 @@ __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __r
 template <typename V>
 __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __restrict__ cols,
                           const double* __restrict__ dinv, double* __restrict__ W,
-                          V* __restrict__ R, V* __restrict__ Z, double* __restrict__ scal,
+                          V* __restrict__ R, double* __restrict__ scal,
                           int* __restrict__ tctl, double* __restrict__ tres) {
-    // x0 = 0, r0 = e_cols[j], z0 = D^{-1} r0 over the whole n x k block (rows
-    // over workgroups, columns over threads)
+    // x0 = 0, r0 = e_cols[j] over the whole n x k block (rows over workgroups,
+    // columns over threads); z0 = D^{-1} r0 is formed where it is read
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const double di = dinv[i];
         for (int j = threadIdx.x; j < k; j += blockDim.x) {
             const int64_t o = i * k + j;
-            const bool unit = cols[j] == i;
             W[o] = 0.0;
-            R[o] = unit ? (V)1.0 : (V)0.0;
-            Z[o] = unit ? (V)di : (V)0.0;
+            R[o] = cols[j] == i ? (V)1.0 : (V)0.0;
         }
     }
     if (blockIdx.x == 0) {
@@ -83,29 +82,61 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// The preconditioned residual z = D^{-1} r of one entry, rounded to the
+// vector type (the value a stored z would hold). It is formed wherever it is
+// read instead of being stored: one n x k array less written and read per
+// iteration.
+template <typename V>
+__device__ inline double zval(double di, V r) {
+    return (double)(V)(di * (double)r);
+}
+
+// Tile of a workgroup (tx = 64-column tile, ty = row tile of `rows_per`
+// contiguous rows). Workgroup L of a 1-D grid runs on XCD L % 8 (round-robin
+// dispatch). mode 0: a plain gx x gy grid. mode 1 (column-grouped, gx >= 8):
+// every row tile of one column tile on the same XCD, one column tile after
+// another. mode 2 (row-banded, gy a multiple of 8): XCD x takes the gy / 8
+// contiguous row tiles of band x, for every column tile. In both grouped
+// modes the rows a tile gathers (its own and, on graphs with locality, their
+// neighbours) come from one XCD's L2 instead of being fetched by several.
+struct Tile {
+    int tx, ty;
+    bool ok;
+};
+__device__ inline Tile cg_tile(int mode, int gx, int gy) {
+    Tile t;
+    if (mode == 0) {
+        t.tx = blockIdx.x;
+        t.ty = blockIdx.y;
+        t.ok = true;
+        return t;
+    }
+    const int L = blockIdx.x, q = L & 7, slot = L >> 3;
+    if (mode == 1) {
+        const int c = slot / gy;
+        t.ty = slot - c * gy;
+        t.tx = q + 8 * c;
+    } else {
+        const int per = gy >> 3;
+        const int c = slot / per;
+        t.ty = q * per + (slot - c * per);
+        t.tx = c;
+    }
+    t.ok = t.tx < gx;
+    return t;
+}
+
 template <typename V>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, int64_t n, int k, const V* __restrict__ Z,
-    V* __restrict__ P, V* __restrict__ Q, double* __restrict__ scal,
+    const double* __restrict__ val, int64_t n, int k, const double* __restrict__ dinv,
+    const V* __restrict__ R, V* __restrict__ P, V* __restrict__ Q, double* __restrict__ scal,
     const double* __restrict__ rzrr, double* __restrict__ part, int* __restrict__ tctl,
-    double* __restrict__ tres, double tol, int it, int gx, int gy, int xcd_grouped,
+    double* __restrict__ tres, double tol, int it, int gx, int gy, int64_t rows_per, int mode,
     int check_only) {
-    // Tile (tx = 64-column tile, ty = row partition). Grouped: a 1-D grid whose
-    // workgroup L runs on XCD L % 8 (round-robin dispatch); every row partition
-    // of a column tile lands on the same XCD, one tile after another, so the
-    // tile's gathered direction rows are served from that XCD's L2.
-    int tx, ty;
-    if (xcd_grouped) {
-        const int L = blockIdx.x, q = L & 7, slot = L >> 3;
-        const int t = slot / gy;
-        ty = slot - t * gy;
-        tx = q + 8 * t;
-        if (tx >= gx) return;
-    } else {
-        tx = blockIdx.x;
-        ty = blockIdx.y;
-    }
+    const Tile T = cg_tile(mode, gx, gy);
+    if (!T.ok) return;
+    const int tx = T.tx, ty = T.ty;
     if (tctl[tx * T_INTS + T_DONE]) return;
     const bool first = it == 0;
     const int lane = threadIdx.x & 63;
@@ -115,13 +146,26 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int jj = jok ? j : k - 1;   // clamped: every lane loads, masked lanes discard
     double beta = 0.0;
     if (!first) {
-        // r.z and r.r of the last update (fixed order: row partitions t = w mod 8
+        // r.z and r.r of the last update (fixed order: row tiles t = w mod 8
         // in wave w, then the waves in order)
+        // (all of a wave's partials are loaded before the first is added: a
+        // rolled loop would wait for each load in turn)
         __shared__ double rsum[2][CG_WAVES][64];
+        double v0[CG_TPW], v1[CG_TPW];
+#pragma unroll
+        for (int u = 0; u < CG_TPW; ++u) {
+            const int t = wave + CG_WAVES * u;
+            const int64_t o = ((int64_t)(t < gy ? t : 0) * k + jj) * 2;
+            v0[u] = rzrr[o];
+            v1[u] = rzrr[o + 1];
+        }
         double a0 = 0.0, a1 = 0.0;
-        for (int t = wave; t < gy; t += CG_WAVES) {
-            a0 += rzrr[((int64_t)t * k + jj) * 2 + 0];
-            a1 += rzrr[((int64_t)t * k + jj) * 2 + 1];
+#pragma unroll
+        for (int u = 0; u < CG_TPW; ++u) {
+            if (wave + CG_WAVES * u < gy) {
+                a0 += v0[u];
+                a1 += v1[u];
+            }
         }
         rsum[0][wave][lane] = a0;
         rsum[1][wave][lane] = a1;
@@ -151,35 +195,63 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     }
     if (check_only) return;
     double pq = 0.0;
-    for (int64_t i = (int64_t)ty * CG_WAVES + wave; i < n; i += (int64_t)gy * CG_WAVES) {
-        const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
-        // this row's own z, p, q issued together with the gathers below
-        const int64_t oi = i * k + jj;
-        const double zi = (double)Z[oi];
-        const double pi = first ? 0.0 : (double)P[oi];
-        const double qi = first ? 0.0 : (double)Q[oi];
-        double acc = 0.0;
-        // eight gathers in flight before their products (a row would otherwise
-        // wait for each gather in turn); a short last batch repeats the row's
-        // last entry with a zero coefficient
-        for (int64_t e = e0; e < e1; e += 8) {
-            double zv[8], av[8];
+    const int64_t r0 = (int64_t)ty * rows_per;
+    const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
+    // Two rows per wave at a time (i and i + 8), their gathers issued together
+    // in batches of CG_GATHER per row (a grid row's whole gather in one). A short batch repeats the row's last entry
+    // with a zero coefficient; a missing second row repeats the first, and
+    // only the first is stored.
+    for (int64_t i = r0 + wave; i < r1; i += 2 * CG_WAVES) {
+        const int64_t i2 = i + CG_WAVES;
+        const bool has2 = i2 < r1;
+        const int64_t ib = has2 ? i2 : i;
+        const int64_t ea0 = rowptr[i], ea1 = rowptr[i + 1];
+        const int64_t eb0 = rowptr[ib], eb1 = rowptr[ib + 1];
+        const int64_t oa = i * k + jj, ob = ib * k + jj;
+        const double za = zval<V>(dinv[i], R[oa]);
+        const double zb = zval<V>(dinv[ib], R[ob]);
+        const double pa = first ? 0.0 : (double)P[oa];
+        const double pb = first ? 0.0 : (double)P[ob];
+        const double qa = first ? 0.0 : (double)Q[oa];
+        const double qb = first ? 0.0 : (double)Q[ob];
+        double acca = 0.0, accb = 0.0;
+        const int64_t na = ea1 - ea0, nbr = eb1 - eb0;
+        const int64_t nmax = na > nbr ? na : nbr;
+        for (int64_t e = 0; e < nmax; e += CG_GATHER) {
+            V ra[CG_GATHER], rb[CG_GATHER];
+            double va[CG_GATHER], vb[CG_GATHER], da[CG_GATHER], db[CG_GATHER];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const bool in = e + u < e1;
-                const int64_t ee = in ? e + u : e1 - 1;
-                av[u] = in ? val[ee] : 0.0;
-                zv[u] = (double)Z[(int64_t)col[ee] * k + jj];
+            for (int u = 0; u < CG_GATHER; ++u) {
+                const bool ina = e + u < na, inb = e + u < nbr;
+                const int64_t xa = ina ? ea0 + e + u : ea1 - 1;
+                const int64_t xb = inb ? eb0 + e + u : eb1 - 1;
+                const int64_t ca = col[xa], cb = col[xb];
+                va[u] = ina ? val[xa] : 0.0;
+                vb[u] = inb ? val[xb] : 0.0;
+                da[u] = dinv[ca];
+                db[u] = dinv[cb];
+                ra[u] = R[ca * k + jj];
+                rb[u] = R[cb * k + jj];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += av[u] * zv[u];
+            for (int u = 0; u < CG_GATHER; ++u) {
+                acca += va[u] * zval<V>(da[u], ra[u]);
+                accb += vb[u] * zval<V>(db[u], rb[u]);
+            }
         }
         if (jok) {
-            const V p = (V)(first ? zi : zi + beta * pi);
-            const V q = (V)(first ? acc : acc + beta * qi);
-            P[oi] = p;
-            Q[oi] = q;
-            pq += (double)p * (double)q;
+            const V p1 = (V)(first ? za : za + beta * pa);
+            const V q1 = (V)(first ? acca : acca + beta * qa);
+            P[oa] = p1;
+            Q[oa] = q1;
+            pq += (double)p1 * (double)q1;
+            if (has2) {
+                const V p2 = (V)(first ? zb : zb + beta * pb);
+                const V q2 = (V)(first ? accb : accb + beta * qb);
+                P[ob] = p2;
+                Q[ob] = q2;
+                pq += (double)p2 * (double)q2;
+            }
         }
     }
     __shared__ double red[CG_WAVES][64];
@@ -195,19 +267,30 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
 template <typename V>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     int64_t n, int k, const double* __restrict__ dinv, double* __restrict__ W,
-    V* __restrict__ R, V* __restrict__ Z, const V* __restrict__ P,
-    const V* __restrict__ Q, const double* __restrict__ scal, const double* __restrict__ pqp,
-    double* __restrict__ part, int* __restrict__ tctl, int it) {
-    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
+    V* __restrict__ R, const V* __restrict__ P, const V* __restrict__ Q,
+    const double* __restrict__ scal, const double* __restrict__ pqp, double* __restrict__ part,
+    int* __restrict__ tctl, int it, int gx, int gy, int64_t rows_per, int mode) {
+    const Tile T = cg_tile(mode, gx, gy);
+    if (!T.ok) return;
+    const int tx = T.tx, ty = T.ty;
+    if (tctl[tx * T_INTS + T_DONE]) return;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
-    const int j = blockIdx.x * 64 + lane;
+    const int j = tx * 64 + lane;
     const bool jok = j < k;
     const int jj = jok ? j : k - 1;
     // alpha = r.z / p.q (p.q summed in a fixed order, as in the product's prologue)
     __shared__ double psum[CG_WAVES][64];
+    double pv[CG_TPW];
+#pragma unroll
+    for (int u = 0; u < CG_TPW; ++u) {
+        const int t = wave + CG_WAVES * u;
+        pv[u] = pqp[(int64_t)(t < gy ? t : 0) * k + jj];
+    }
     double a = 0.0;
-    for (int t = wave; t < (int)gridDim.y; t += CG_WAVES) a += pqp[(int64_t)t * k + jj];
+#pragma unroll
+    for (int u = 0; u < CG_TPW; ++u)
+        if (wave + CG_WAVES * u < gy) a += pv[u];
     psum[wave][lane] = a;
     __syncthreads();
     double pq = 0.0;
@@ -215,28 +298,44 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     const double rz0 = scal[jj * 4 + (it & 1)];
     const double alpha = (jok && pq > 0.0 && rz0 > 0.0) ? rz0 / pq : 0.0;
     // breakdown: a non-zero residual whose direction has p.Ap <= 0 (every
-    // workgroup of the tile sees the same sums; row partition 0 records it)
+    // workgroup of the tile sees the same sums; row tile 0 records it)
     const bool bad = jok && rz0 > 0.0 && !(pq > 0.0);
     if (__any(bad)) {
-        if (blockIdx.y == 0 && wave == 0 && lane == 0) {
-            int* c = tctl + blockIdx.x * T_INTS;
+        if (ty == 0 && wave == 0 && lane == 0) {
+            int* c = tctl + tx * T_INTS;
             c[T_BAD] = 1;
             c[T_DONE] = 1;
         }
         return;
     }
     double rz = 0.0, rr = 0.0;
+    const int64_t r0 = (int64_t)ty * rows_per;
+    const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
     if (jok) {
-        for (int64_t i = (int64_t)blockIdx.y * CG_WAVES + wave; i < n;
-             i += (int64_t)gridDim.y * CG_WAVES) {
-            const int64_t o = i * k + j;
-            W[o] += alpha * (double)P[o];
-            const V r = (V)((double)R[o] - alpha * (double)Q[o]);
-            R[o] = r;
-            const V z = (V)(dinv[i] * (double)r);
-            Z[o] = z;
-            rz += (double)r * (double)z;
-            rr += (double)r * (double)r;
+        // two rows per wave at a time: eight loads in flight before the stores
+        for (int64_t i = r0 + wave; i < r1; i += 2 * CG_WAVES) {
+            const int64_t i2 = i + CG_WAVES;
+            const bool has2 = i2 < r1;
+            const int64_t oa = i * k + j, ob = (has2 ? i2 : i) * k + j;
+            const double wa = W[oa], wb = W[ob];
+            const double pa = (double)P[oa], pb = (double)P[ob];
+            const double ra = (double)R[oa], rb = (double)R[ob];
+            const double qa = (double)Q[oa], qb = (double)Q[ob];
+            const double dia = dinv[i], dib = dinv[has2 ? i2 : i];
+            W[oa] = wa + alpha * pa;
+            const V r1v = (V)(ra - alpha * qa);
+            R[oa] = r1v;
+            const double z1 = zval<V>(dia, r1v);
+            rz += (double)r1v * z1;
+            rr += (double)r1v * (double)r1v;
+            if (has2) {
+                W[ob] = wb + alpha * pb;
+                const V r2v = (V)(rb - alpha * qb);
+                R[ob] = r2v;
+                const double z2 = zval<V>(dib, r2v);
+                rz += (double)r2v * z2;
+                rr += (double)r2v * (double)r2v;
+            }
         }
     }
     __shared__ double red[2][CG_WAVES][64];
@@ -250,32 +349,37 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
             s1 += red[1][w][lane];
         }
         if (jok) {
-            part[((int64_t)blockIdx.y * k + j) * 2 + 0] = s0;
-            part[((int64_t)blockIdx.y * k + j) * 2 + 1] = s1;
+            part[((int64_t)ty * k + j) * 2 + 0] = s0;
+            part[((int64_t)ty * k + j) * 2 + 1] = s1;
         }
     }
 }
 
 // Residual replacement for float vectors: r = e_j - A x from the float64
-// iterate x (W), in float64, then z = D^{-1} r, with the same partial sums as
-// the update. The recursively updated float residual drifts from the true
-// one; replacing it every few iterations keeps the convergence test honest.
+// iterate x (W), in float64, with the same partial sums as the update. The
+// recursively updated float residual drifts from the true one; replacing it
+// every few iterations keeps the convergence test honest.
 template <typename V>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_true_residual(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, int64_t n, int k, const int32_t* __restrict__ cols,
     const double* __restrict__ dinv, const double* __restrict__ W, V* __restrict__ R,
-    V* __restrict__ Z, double* __restrict__ part, const int* __restrict__ tctl) {
-    if (tctl[blockIdx.x * T_INTS + T_DONE]) return;
+    double* __restrict__ part, const int* __restrict__ tctl, int gx, int gy, int64_t rows_per,
+    int mode) {
+    const Tile T = cg_tile(mode, gx, gy);
+    if (!T.ok) return;
+    const int tx = T.tx, ty = T.ty;
+    if (tctl[tx * T_INTS + T_DONE]) return;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
-    const int j = blockIdx.x * 64 + lane;
+    const int j = tx * 64 + lane;
     const bool jok = j < k;
     const int jj = jok ? j : k - 1;
     const int64_t cj = cols[jj];
     double rz = 0.0, rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.y * CG_WAVES + wave; i < n;
-         i += (int64_t)gridDim.y * CG_WAVES) {
+    const int64_t r0 = (int64_t)ty * rows_per;
+    const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
+    for (int64_t i = r0 + wave; i < r1; i += CG_WAVES) {
         const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
         double acc = 0.0;
         int64_t e = e0;
@@ -294,10 +398,9 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_true_residual(
             const int64_t o = i * k + j;
             const double r = (i == cj ? 1.0 : 0.0) - acc;
             const V rv = (V)r;
-            const V zv = (V)(dinv[i] * (double)rv);
             R[o] = rv;
-            Z[o] = zv;
-            rz += (double)rv * (double)zv;
+            const double zv = zval<V>(dinv[i], rv);
+            rz += (double)rv * zv;
             rr += (double)rv * (double)rv;
         }
     }
@@ -312,8 +415,8 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_true_residual(
             s1 += red[1][w][lane];
         }
         if (jok) {
-            part[((int64_t)blockIdx.y * k + j) * 2 + 0] = s0;
-            part[((int64_t)blockIdx.y * k + j) * 2 + 1] = s1;
+            part[((int64_t)ty * k + j) * 2 + 0] = s0;
+            part[((int64_t)ty * k + j) * 2 + 1] = s1;
         }
     }
 }
@@ -348,14 +451,43 @@ struct CGBufs {
     bool prof;
 };
 
-int cg_row_tiles(int64_t n) {
-    const int rt = (int)std::min<int64_t>(CG_ROW_TILES, (n + CG_WAVES - 1) / CG_WAVES);
-    return rt < 1 ? 1 : rt;
+// Launch geometry of one solve: gx 64-column tiles; gy row tiles of rows_per
+// contiguous rows (each wave takes at least two rows); the tile mapping mode
+// of cg_tile (column-grouped with 8 or more column tiles, else row-banded when
+// there are 8 or more row tiles) and its grid.
+struct CgGeom {
+    int gx, gy, mode;
+    int64_t rows_per;
+    dim3 grid;
+};
+
+CgGeom cg_geom(int64_t n, int k) {
+    CgGeom g;
+    g.gx = (std::max(k, 1) + 63) / 64;
+    int gy = (int)std::min<int64_t>(CG_ROW_TILES, (n + 2 * CG_WAVES - 1) / (2 * CG_WAVES));
+    if (gy < 1) gy = 1;
+    if (g.gx >= 8) {
+        g.mode = 1;
+        g.gy = gy;
+        g.grid = dim3((unsigned)(8 * ((g.gx + 7) / 8) * gy));
+    } else if (gy >= 8) {
+        g.mode = 2;
+        g.gy = gy / 8 * 8;
+        g.grid = dim3((unsigned)(g.gx * g.gy));
+    } else {
+        g.mode = 0;
+        g.gy = gy;
+        g.grid = dim3((unsigned)g.gx, (unsigned)gy);
+    }
+    g.rows_per = (n + g.gy - 1) / g.gy;
+    return g;
 }
+
+int cg_row_tiles(int64_t n, int k) { return cg_geom(n, k).gy; }
 
 template <typename V>
 CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W, double tol,
-                       int max_iter, const CGBufs& bf, V* R, V* Z, V* P, V* Q, hipStream_t s) {
+                       int max_iter, const CGBufs& bf, V* R, V* P, V* Q, hipStream_t s) {
     constexpr bool LOW = sizeof(V) < sizeof(double);
     CGResult res;
     const int64_t n = A.n;
@@ -363,8 +495,9 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
         res.converged = true;
         return res;
     }
-    const int col_tiles = (k + 63) / 64;
-    const int row_tiles = cg_row_tiles(n);
+    const CgGeom G = cg_geom(n, k);
+    const int col_tiles = G.gx;
+    const int row_tiles = G.gy;
     // partials: r.z and r.r of an update (two per entry), then p.q of a product
     double* part_rz = bf.part;
     double* part_pq = bf.part + (size_t)row_tiles * k * 2;
@@ -373,13 +506,8 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
                        A.rowptr, A.col, A.val, n, bf.dinv);
     SIC_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, s,
-                       n, k, col_tiles, d_cols, bf.dinv, W, R, Z, bf.scal, bf.flags, tres);
+                       n, k, col_tiles, d_cols, bf.dinv, W, R, bf.scal, bf.flags, tres);
     SIC_CHECK_LAUNCH();
-    dim3 grid(col_tiles, row_tiles);
-    // XCD grouping of the product's tiles once there are enough column tiles to
-    // give every XCD one (fewer would leave XCDs idle)
-    const int grouped = col_tiles >= 8 ? 1 : 0;
-    const dim3 sgrid = grouped ? dim3((unsigned)(8 * ((col_tiles + 7) / 8) * row_tiles)) : grid;
     const int* hctl = bf.hctl;
     const double* hres = bf.hres;
     int& predicted = *bf.predicted;
@@ -407,24 +535,26 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
             Rec r;
             r.iter = it;
             if (bf.prof) prof_begin(KK_CG_SPMM, s);
-            hipLaunchKernelGGL(k_cg_spmm<V>, sgrid, dim3(CG_THREADS), 0, s, A.rowptr, A.col,
-                               A.val, n, k, Z, P, Q, bf.scal, part_rz, part_pq, bf.flags,
-                               tres, tol, it, col_tiles, row_tiles, grouped, 0);
+            hipLaunchKernelGGL(k_cg_spmm<V>, G.grid, dim3(CG_THREADS), 0, s, A.rowptr, A.col,
+                               A.val, n, k, bf.dinv, R, P, Q, bf.scal, part_rz, part_pq,
+                               bf.flags, tres, tol, it, col_tiles, row_tiles, G.rows_per, G.mode,
+                               0);
             SIC_CHECK_LAUNCH();
             if (bf.prof)
                 r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
                                   2.0 * A.nnz * k + 4.0 * n * k);
             if (bf.prof) prof_begin(KK_CG_UPDATE, s);
-            hipLaunchKernelGGL(k_cg_update<V>, grid, dim3(CG_THREADS), 0, s, n, k, bf.dinv, W, R,
-                               Z, P, Q, bf.scal, part_pq, part_rz, bf.flags, it);
+            hipLaunchKernelGGL(k_cg_update<V>, G.grid, dim3(CG_THREADS), 0, s, n, k, bf.dinv, W,
+                               R, P, Q, bf.scal, part_pq, part_rz, bf.flags, it, col_tiles,
+                               row_tiles, G.rows_per, G.mode);
             SIC_CHECK_LAUNCH();
             if (bf.prof)
-                r.upd = prof_end(KK_CG_UPDATE, s, 5.0 * nkb + 16.0 * n * k + n * 8.0,
+                r.upd = prof_end(KK_CG_UPDATE, s, 4.0 * nkb + 16.0 * n * k + n * 8.0,
                                  10.0 * n * k);
             if (LOW && (it + 1) % CG_REPLACE_EVERY == 0) {
-                hipLaunchKernelGGL(k_cg_true_residual<V>, grid, dim3(CG_THREADS), 0, s, A.rowptr,
-                                   A.col, A.val, n, k, d_cols, bf.dinv, W, R, Z, part_rz,
-                                   bf.flags);
+                hipLaunchKernelGGL(k_cg_true_residual<V>, G.grid, dim3(CG_THREADS), 0, s,
+                                   A.rowptr, A.col, A.val, n, k, d_cols, bf.dinv, W, R, part_rz,
+                                   bf.flags, col_tiles, row_tiles, G.rows_per, G.mode);
                 SIC_CHECK_LAUNCH();
             }
             if (bf.prof) recs.push_back(r);
@@ -433,8 +563,9 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
         if (launched >= max_iter) {
             // the last update's residual has no product after it to test it
             hipLaunchKernelGGL(k_cg_spmm<V>, dim3(col_tiles, 1), dim3(CG_THREADS), 0, s,
-                               A.rowptr, A.col, A.val, n, k, Z, P, Q, bf.scal, part_rz,
-                               part_pq, bf.flags, tres, tol, launched, col_tiles, row_tiles, 0, 1);
+                               A.rowptr, A.col, A.val, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
+                               part_pq, bf.flags, tres, tol, launched, col_tiles, row_tiles,
+                               G.rows_per, 0, 1);
             SIC_CHECK_LAUNCH();
         }
         SIC_HIP(hipMemcpyAsync(bf.hctl, bf.flags, sizeof(int) * T_INTS * col_tiles,
@@ -501,7 +632,7 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
     const size_t nk = (size_t)n * (size_t)std::max(k, 1);
     const int col_tiles = (std::max(k, 1) + 63) / 64;
     wk.dinv.reserve(n);
-    wk.part.reserve((size_t)cg_row_tiles(n) * std::max(k, 1) * 3);
+    wk.part.reserve((size_t)cg_row_tiles(n, k) * std::max(k, 1) * 3);
     wk.scal.reserve((size_t)4 * std::max(k, 1) + col_tiles);
     wk.flags.reserve((size_t)T_INTS * col_tiles);
     wk.hctl.reserve((size_t)T_INTS * col_tiles);
@@ -511,18 +642,16 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
               &wk.predict[(slot & 3) * 2 + (low_precision ? 1 : 0)], true};
     if (low_precision) {
         wk.R32.reserve(nk);
-        wk.Z32.reserve(nk);
         wk.P32.reserve(nk);
         wk.Q32.reserve(nk);
-        return block_cg_impl<float>(av, d_cols, k, W, tol, max_iter, bf, wk.R32.p, wk.Z32.p,
-                                    wk.P32.p, wk.Q32.p, s);
+        return block_cg_impl<float>(av, d_cols, k, W, tol, max_iter, bf, wk.R32.p, wk.P32.p,
+                                    wk.Q32.p, s);
     }
     wk.R.reserve(nk);
-    wk.Z.reserve(nk);
     wk.P.reserve(nk);
     wk.Q.reserve(nk);
-    return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, wk.R.p, wk.Z.p, wk.P.p,
-                                 wk.Q.p, s);
+    return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, wk.R.p, wk.P.p, wk.Q.p,
+                                 s);
 }
 
 // ------------------------------------------------------------------------
@@ -565,9 +694,9 @@ unsigned char* scratch_address() {
 size_t cg_noalloc_bytes(int64_t n, int k) {
     const int ct = (k + 63) / 64;
     return align256(sizeof(double) * (size_t)n) +
-           align256(sizeof(double) * (size_t)cg_row_tiles(n) * k * 3) +
+           align256(sizeof(double) * (size_t)cg_row_tiles(n, k) * k * 3) +
            align256(sizeof(double) * ((size_t)4 * k + ct)) + align256(sizeof(int) * T_INTS * ct) +
-           4 * align256(sizeof(double) * (size_t)n * k);
+           3 * align256(sizeof(double) * (size_t)n * k);
 }
 
 size_t cg_noalloc_capacity() { return NOALLOC_SCRATCH_BYTES; }
@@ -592,12 +721,12 @@ CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const doubl
         return p;
     };
     double* dinv = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n));
-    double* part = reinterpret_cast<double*>(take(sizeof(double) * (size_t)cg_row_tiles(n) * k * 3));
+    double* part =
+        reinterpret_cast<double*>(take(sizeof(double) * (size_t)cg_row_tiles(n, k) * k * 3));
     double* scal = reinterpret_cast<double*>(take(sizeof(double) * ((size_t)4 * k + ct)));
     int* flags = reinterpret_cast<int*>(take(sizeof(int) * T_INTS * ct));
     const size_t nkb = sizeof(double) * (size_t)n * k;
     double* R = reinterpret_cast<double*>(take(nkb));
-    double* Z = reinterpret_cast<double*>(take(nkb));
     double* P = reinterpret_cast<double*>(take(nkb));
     double* Q = reinterpret_cast<double*>(take(nkb));
     // control read-backs land in host stack arrays (pageable copies)
@@ -606,7 +735,7 @@ CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const doubl
     int predicted = 0;
     const CsrView av{rowptr, col, val, n, nnz};
     const CGBufs bf{dinv, part, scal, flags, hctl, hres, &predicted, false};
-    return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, R, Z, P, Q, s);
+    return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, R, P, Q, s);
 }
 
 }  // namespace sic

@@ -167,8 +167,8 @@ void launch_sddmm(const double* Xt, int64_t m, const int32_t* rows, const int32_
 
 // ---------------------------------------------------------------- k_cg.hip
 struct CGWork {
-    DevBuf<double> R, Z, P, Q, dinv, part, scal;
-    DevBuf<float> R32, Z32, P32, Q32;   // the float vectors of the reduced-precision CG
+    DevBuf<double> R, P, Q, dinv, part, scal;
+    DevBuf<float> R32, P32, Q32;        // the float vectors of the reduced-precision CG
     DevBuf<int32_t> flags;
     HostBuf<int32_t> hctl;              // per-tile control words, read back at each check
     HostBuf<double> hres;               // per-tile relative residuals

@@ -66,6 +66,13 @@ extern "C" {
 #define SIC_FLAG_VERBOSE (1ull << 2)       /* per-cycle log on stderr */
 #define SIC_FLAG_NO_CERTIFY (1ull << 3)    /* accept the sweep's KKT measure without the exact
                                               float64 pass (see sic_solve) */
+#define SIC_FLAG_CLUSTER (1ull << 4)       /* blocks from a clustering of the free-set graph
+                                              (Section 6.1): at the start of every cycle the
+                                              variables are relabelled so that each block of b
+                                              consecutive ones is a breadth-first-grown cluster
+                                              of the graph of A's support and the last finest
+                                              sweep's free pairs (sic_cluster_order); results
+                                              come back in the caller's labels */
 
 typedef struct sic_ctx sic_ctx;
 

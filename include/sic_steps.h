@@ -153,6 +153,20 @@ int sic_hierarchy(int64_t n, const int64_t* supp_keys, int64_t n_supp, const int
                   const double* free_absg, int64_t n_free, int64_t* ranking_out,
                   int64_t* ranking_len, int64_t* sizes_out, int* n_levels);
 
+/* Clustered block partition (Section 6.1; eq. (extended_set) of Section
+ * 6.1.1: blocks whose free pairs stay inside them have small neighbourhoods
+ * N_j). The graph has a vertex per variable and an edge per pair key
+ * i*n + j (diagonal keys and repeats ignored). Blocks of b vertices are grown
+ * one after another, breadth-first from a seed over unplaced vertices
+ * (neighbours in ascending order); a growth that exhausts its component goes
+ * on from the next seed. The next seed is the oldest unplaced candidate
+ * (vertices adjacent to earlier blocks, queued when each block was completed:
+ * members in order, each one's neighbours ascending), else the unplaced
+ * vertex of least degree (ties: smaller index). order_out[n] (caller-owned)
+ * receives the variables in block order: block k is order_out[k b .. k b + b).
+ * Host computation only. SIC_EINVAL for bad sizes or keys outside [0, n^2). */
+int sic_cluster_order(int64_t n, const int64_t* keys, int64_t count, int b, int32_t* order_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -156,6 +156,30 @@ void launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
     SIC_CHECK_LAUNCH();
 }
 
+namespace {
+__global__ void k_gather_cols(const double* __restrict__ X, int64_t m, int64_t n,
+                              const int32_t* __restrict__ perm, double* __restrict__ out) {
+    // one row of samples per workgroup step; the row's gathers stay in one
+    // 8n-byte segment
+    for (int64_t r = blockIdx.y; r < m; r += gridDim.y) {
+        const double* xr = X + r * n;
+        double* orow = out + r * n;
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+             c += (int64_t)gridDim.x * blockDim.x)
+            orow[c] = xr[perm[c]];
+    }
+}
+}  // namespace
+
+void launch_gather_cols(const double* X, int64_t m, int64_t n, const int32_t* perm, double* out,
+                        hipStream_t s) {
+    if (m <= 0 || n <= 0) return;
+    const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 64);
+    const unsigned gy = (unsigned)std::min<int64_t>(m, 1024);
+    hipLaunchKernelGGL(k_gather_cols, dim3(gx, gy), dim3(256), 0, s, X, m, n, perm, out);
+    SIC_CHECK_LAUNCH();
+}
+
 void launch_iota_i32(int32_t* p, int64_t count, int32_t start, hipStream_t s) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count,

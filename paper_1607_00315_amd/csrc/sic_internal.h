@@ -209,6 +209,9 @@ void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets
                           hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 void launch_iota_i32(int32_t* p, int64_t count, int32_t start, hipStream_t s);
+// out (m x n row-major) = the columns perm[0..n) of X (m x n row-major)
+void launch_gather_cols(const double* X, int64_t m, int64_t n, const int32_t* perm, double* out,
+                        hipStream_t s);
 // global (row, column) of every coordinate: Jp[c_p[t]], j0 + c_ci[t]
 void launch_coord_globals(int64_t nc, const int32_t* c_p, const int32_t* c_ci, const int32_t* Jp,
                           int64_t j0, int32_t* gr, int32_t* gc, hipStream_t s);

@@ -25,7 +25,8 @@ struct Options {
 struct BlockWork {
     DevBuf<double> SJ, WI, AJ, ANEW, WN, WJJ, U, ug, HT;
     DevBuf<unsigned char> markg;
-    DevBuf<char> xstage;   // reduced-precision X before its conversion
+    DevBuf<char> xstage;   // reduced-precision X before its conversion; relabelled X
+    DevBuf<int32_t> perm;  // a relabelling on the device
     DevBuf<int32_t> cols;
     // free lists
     DevBuf<int64_t> colptr;
@@ -90,6 +91,9 @@ struct Problem {
     std::vector<int64_t> rec_key;
     std::vector<double> rec_g;
     std::vector<int64_t> rec_seq;
+    // relabelling of the variables (SIC_FLAG_CLUSTER): perm[p] is the caller's
+    // label of the variable the solver calls p; empty means none
+    std::vector<int32_t> perm;
     DevCSR& Acur() { return A[cur]; }
 };
 
@@ -147,6 +151,11 @@ void hierarchy_host(int64_t n, const std::vector<int64_t>& supp,
                     const std::vector<int64_t>& fkey, const std::vector<double>& fg,
                     std::vector<int64_t>& ranking, std::vector<int64_t>& sizes);
 std::vector<int64_t> support_keys(Context& C, Problem& P);
+// Clustered block partition (cluster.hip): the variables in block order.
+std::vector<int32_t> cluster_order(int64_t n, const int64_t* keys, int64_t count, int b);
+// Relabels the problem (samples, iterate, recorded free pairs) by the cluster
+// order of the graph of A's support and the recorded free pairs.
+void cluster_problem(Context& C, Problem& P);
 int solve_problem(Context& C, Problem& P, double tol, sic_info* info);
 // One request of sic_solve_batch (or of the serving loop): set-up, optional
 // warm start, then the lambda path (or the single lambda). Results go to

@@ -308,6 +308,7 @@ void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n,
     for (double v : d) tr += v;
     P.F = tr + lam * (double)n;   // F(I) = -log det I + tr(S) + lam * n
     P.level_set = false;
+    P.perm.clear();
 }
 
 void set_identity(Context& C, Problem& P) {
@@ -446,6 +447,10 @@ double warm_start_objective(Context& C, Problem& P, const sic_csr* in) {
     return -logdet + tr + P.lam * l1;
 }
 
+void relabel_csr(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& cl,
+                 const std::vector<double>& vl, const std::vector<int32_t>& map,
+                 int64_t* brp, int32_t* bcl, double* bvl);
+
 void get_A_host(Context& C, Problem& P, sic_csr* out) {
     DevCSR& A = P.Acur();
     const int64_t n = P.n, nnz = A.nnz;
@@ -465,6 +470,37 @@ void get_A_host(Context& C, Problem& P, sic_csr* out) {
         SIC_HIP(hipMemcpyAsync(out->val, A.val.p, sizeof(double) * nnz, hipMemcpyDeviceToHost, C.stream));
     }
     sync(C);
+    if (!P.perm.empty()) {
+        // back to the caller's labels: row perm[p] holds row p, columns relabelled
+        std::vector<int64_t> rp(out->rowptr, out->rowptr + n + 1);
+        std::vector<int32_t> cl(out->col, out->col + nnz);
+        std::vector<double> vl(out->val, out->val + nnz);
+        relabel_csr(n, rp, cl, vl, P.perm, out->rowptr, out->col, out->val);
+    }
+}
+
+// B = the symmetric CSR (rp, cl, vl) with every label p renamed to = map[p]:
+// row map[p] of B is row p of the input, its columns renamed and sorted.
+void relabel_csr(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& cl,
+                 const std::vector<double>& vl, const std::vector<int32_t>& map,
+                 int64_t* brp, int32_t* bcl, double* bvl) {
+    std::vector<int32_t> inv(n);
+    for (int64_t p = 0; p < n; ++p) inv[map[p]] = (int32_t)p;
+    brp[0] = 0;
+    for (int64_t r = 0; r < n; ++r) brp[r + 1] = brp[r] + (rp[inv[r] + 1] - rp[inv[r]]);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t p = inv[r];
+        row.clear();
+        for (int64_t e = rp[p]; e < rp[p + 1]; ++e) row.emplace_back(map[cl[e]], vl[e]);
+        std::sort(row.begin(), row.end());
+        int64_t o = brp[r];
+        for (const auto& x : row) {
+            bcl[o] = x.first;
+            bvl[o] = x.second;
+            ++o;
+        }
+    }
 }
 
 void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count) {
@@ -971,6 +1007,62 @@ std::vector<int64_t> support_keys(Context& C, Problem& P) {
     return keys;   // ascending: rows ascending, columns sorted
 }
 
+void cluster_problem(Context& C, Problem& P) {
+    hipStream_t s = C.stream;
+    const int64_t n = P.n, m = P.m;
+    const int b = (int)std::min<int64_t>(C.opt.block, n);
+    std::vector<int64_t> keys = support_keys(C, P);
+    keys.insert(keys.end(), P.rec_key.begin(), P.rec_key.end());
+    const std::vector<int32_t> order = cluster_order(n, keys.data(), (int64_t)keys.size(), b);
+    bool same = true;
+    for (int64_t p = 0; p < n && same; ++p) same = order[p] == p;
+    if (same) return;
+    std::vector<int32_t> inv(n);
+    for (int64_t p = 0; p < n; ++p) inv[order[p]] = (int32_t)p;
+    // samples: column p of the new X is column order[p] of the old one
+    BlockWork& W = C.work;
+    W.perm.reserve(n);
+    SIC_HIP(hipMemcpyAsync(W.perm.p, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    const size_t count = (size_t)n * m;
+    W.xstage.reserve(count * sizeof(double));
+    launch_gather_cols(P.X.p, m, n, W.perm.p, reinterpret_cast<double*>(W.xstage.p), s);
+    SIC_HIP(hipMemcpyAsync(P.X.p, W.xstage.p, count * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_transpose(P.X.p, m, n, P.Xt.p, s);
+    launch_diag_s(P.Xt.p, n, m, P.diagS.p, s);
+    if (P.narrow) launch_narrow(P.X.p, (int64_t)count, P.Xf.p, P.Xb.p, s);
+    // the iterate, relabelled on the host
+    DevCSR& A = P.Acur();
+    const int64_t nnz = A.nnz;
+    std::vector<int64_t> rp(n + 1), nrp(n + 1);
+    std::vector<int32_t> cl(std::max<int64_t>(nnz, 1)), ncl(std::max<int64_t>(nnz, 1));
+    std::vector<double> vl(std::max<int64_t>(nnz, 1)), nvl(std::max<int64_t>(nnz, 1));
+    SIC_HIP(hipMemcpyAsync(rp.data(), A.rowptr.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    SIC_HIP(hipMemcpyAsync(cl.data(), A.col.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+    SIC_HIP(hipMemcpyAsync(vl.data(), A.val.p, sizeof(double) * nnz, hipMemcpyDeviceToHost, s));
+    sync(C);
+    relabel_csr(n, rp, cl, vl, inv, nrp.data(), ncl.data(), nvl.data());
+    SIC_HIP(hipMemcpyAsync(A.rowptr.p, nrp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    SIC_HIP(hipMemcpyAsync(A.col.p, ncl.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    SIC_HIP(hipMemcpyAsync(A.val.p, nvl.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+    // recorded free pairs
+    std::vector<std::pair<int64_t, double>> rec(P.rec_key.size());
+    for (size_t t = 0; t < P.rec_key.size(); ++t) {
+        const int64_t i = inv[P.rec_key[t] / n], j = inv[P.rec_key[t] % n];
+        rec[t] = {i <= j ? i * n + j : j * n + i, P.rec_g[t]};
+    }
+    std::sort(rec.begin(), rec.end());
+    for (size_t t = 0; t < rec.size(); ++t) {
+        P.rec_key[t] = rec[t].first;
+        P.rec_g[t] = rec[t].second;
+    }
+    // the caller's label of each new label
+    std::vector<int32_t> composed(n);
+    for (int64_t p = 0; p < n; ++p) composed[p] = P.perm.empty() ? order[p] : P.perm[order[p]];
+    P.perm = std::move(composed);
+    P.level_set = false;
+    sync(C);
+}
+
 // ------------------------------------------------------------------ exact KKT
 
 static double exact_kkt_body(Context& C, Problem& P, double tol_cg, double* l1) {
@@ -1066,6 +1158,7 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
         const double tolI = std::min(C.opt.cg_tol_I, std::max(1e-12, 0.01 * kkt_prev));
         const double tolN = std::min(C.opt.cg_tol_N, std::max(1e-12, 0.01 * kkt_prev));
         C.prec = cycle_precision(C, P, kkt_prev);
+        if (C.opt.flags & SIC_FLAG_CLUSTER) cluster_problem(C, P);
         int levels = 0;
         if (ml) {
             std::vector<int64_t> ranking, sizes;

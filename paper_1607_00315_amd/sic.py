@@ -22,7 +22,7 @@ SIC_OK, SIC_EINVAL, SIC_ENONFINITE, SIC_ENOTPD, SIC_ENOMEM = 0, -1, -2, -3, -4
 SIC_ENOCONV, SIC_EHIP, SIC_ECANCELED, SIC_ETOOBIG, SIC_EINTERNAL = -5, -6, -7, -8, -9
 SIC_FP64, SIC_MIXED = 0, 1
 SIC_X_F64, SIC_X_F32, SIC_X_BF16 = 0, 1, 2
-FLAG_NO_MULTILEVEL, FLAG_FINAL_KKT, FLAG_VERBOSE, FLAG_NO_CERTIFY = 1, 2, 4, 8
+FLAG_NO_MULTILEVEL, FLAG_FINAL_KKT, FLAG_VERBOSE, FLAG_NO_CERTIFY, FLAG_CLUSTER = 1, 2, 4, 8, 16
 
 
 class SicError(RuntimeError):
@@ -128,6 +128,7 @@ SIGNATURES = {
                                                     ct.POINTER(ct.c_int), _dp]),
     "sic_step_inverse_columns_noalloc_limit": (ct.c_size_t, [ct.c_int64, ct.c_int]),
     "sic_step_set_level": (ct.c_int, [_P, _i64p, ct.c_int64]),
+    "sic_cluster_order": (ct.c_int, [ct.c_int64, _i64p, ct.c_int64, ct.c_int, _i32p]),
     "sic_step_block": (ct.c_int, [_P, ct.c_int64, ct.c_int, ct.c_int, ct.c_double, ct.c_double,
                                   ct.POINTER(BlockResult)]),
     "sic_step_last_block": (ct.c_int, [_P, _i64p, _i32p, _dp, _i32p, _i32p, _i32p, _dp, _dp]),
@@ -588,6 +589,15 @@ def step_linesearch(ctx: Context, wjj, b, cptr, cp, S, A, delta, lam, n_alpha=0)
                                      ct.byref(dF), ct.byref(trials), _ptr(ld, ct.c_double),
                                      int(n_alpha)), "step_linesearch")
     return alpha.value, dF.value, trials.value, ld[:n_alpha]
+
+
+def cluster_order(n, keys, b):
+    """The clustered block order of the graph of pair keys (host computation)."""
+    keys = np.ascontiguousarray(keys, dtype=np.int64)
+    out = np.empty(n, dtype=np.int32)
+    _check(lib().sic_cluster_order(n, _ptr(keys, ct.c_int64), keys.size, b,
+                                   _ptr(out, ct.c_int32)), "cluster_order")
+    return out
 
 
 def hierarchy(n, supp_keys, free_keys, free_absg):

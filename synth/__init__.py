@@ -9,7 +9,9 @@ GPU library can both consume its output without sharing method code.
 
 from .generators import (  # noqa: F401
     chain_precision,
+    delaunay_precision,
     grid_precision,
+    normalize_samples,
     random_precision,
     sample_gaussian,
     workload,

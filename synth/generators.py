@@ -14,8 +14,19 @@ The linear solve P y = z is done by Chebyshev semi-iteration on the
 Jacobi-scaled system, whose spectrum lies in [1 - rho, 1 + rho] with
 rho = max_i sum_{j != i} |p_ij| / p_ii < 1 by diagonal dominance
 (Gershgorin); see Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,
-Algorithm 12.1.  Samples are returned as the m x n matrix X whose rows are
-the draws (row-major float64), the layout the solver consumes.
+Algorithm 12.1.  Matrices that are only weakly dominant (the planar graph
+Laplacians, whose interior rows have p_ii equal to their off-diagonal sum) are
+solved by a sparse LU factorisation instead.  Samples are returned as the
+m x n matrix X whose rows are the draws (row-major float64), the layout the
+solver consumes.
+
+The planar-graph workloads follow Section 8.1 of the paper: n uniform points
+in the unit square, edges of their Delaunay triangulation, precision -1 on
+every edge and the vertex degree on the diagonal (a graph Laplacian, PSD with
+the constant vector as null space), made definite by deleting the points
+within 1/sqrt(n) of the square's boundary (the rows and columns of the rest
+form a Dirichlet Laplacian).  Their samples are normalised as the paper's are:
+each variable centred and scaled so that diag(X^T X / m) = 1.
 """
 
 from __future__ import annotations
@@ -24,6 +35,7 @@ import math
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 # --------------------------------------------------------------------------
@@ -100,6 +112,35 @@ def random_precision(n: int, pairs: int, rng: np.random.Generator,
     return P.tocsr()
 
 
+def delaunay_precision(points: int, rng: np.random.Generator) -> sp.csr_matrix:
+    """Dirichlet graph Laplacian of a random planar (Delaunay) graph.
+
+    ``points`` uniform points in the unit square; P_ij = -1 for every edge of
+    their Delaunay triangulation, P_ii = the vertex degree; then the rows and
+    columns of the points with a coordinate closer than 1/sqrt(points) to the
+    boundary are deleted. The points keep their (random) drawing order, so the
+    natural order of the variables has no locality.
+    """
+    from scipy.spatial import Delaunay
+    if points < 16:
+        raise ValueError("need at least 16 points")
+    xy = rng.random((points, 2))
+    tri = Delaunay(xy).simplices.astype(np.int64)
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [0, 2]]])
+    e.sort(axis=1)
+    key = np.unique(e[:, 0] * points + e[:, 1])
+    a, b = key // points, key % points
+    adj = sp.coo_matrix((np.ones(a.size), (a, b)), shape=(points, points))
+    adj = (adj + adj.T).tocsr()
+    deg = np.asarray(adj.sum(axis=1)).ravel()
+    L = (sp.diags(deg) - adj).tocsr()
+    h = 1.0 / math.sqrt(points)
+    keep = np.nonzero(np.all((xy > h) & (xy < 1.0 - h), axis=1))[0]
+    P = L[keep][:, keep].tocsr()
+    P.sort_indices()
+    return P
+
+
 # --------------------------------------------------------------------------
 # sampling
 # --------------------------------------------------------------------------
@@ -166,6 +207,12 @@ def _chebyshev_solve(P: sp.csr_matrix, Z: np.ndarray, rtol: float = 1e-14,
     return x * s[:, None]
 
 
+def _strictly_dominant(P: sp.csr_matrix) -> bool:
+    dg = np.abs(P.diagonal())
+    off = np.asarray(abs(P).sum(axis=1)).ravel() - dg
+    return bool(np.all(off < dg))
+
+
 def sample_gaussian(P: sp.csr_matrix, m: int, rng: np.random.Generator) -> np.ndarray:
     """Draw m samples of N(0, P^{-1}); returns X (m x n, C-contiguous float64)."""
     P = sp.csr_matrix(P, dtype=np.float64)
@@ -173,8 +220,20 @@ def sample_gaussian(P: sp.csr_matrix, m: int, rng: np.random.Generator) -> np.nd
     xi = rng.standard_normal((G.shape[1], m))
     Z = G @ xi
     del xi
-    Y = _chebyshev_solve(P, Z)
+    if _strictly_dominant(P):
+        Y = _chebyshev_solve(P, Z)
+    else:
+        Y = spla.splu(P.tocsc(), permc_spec="COLAMD").solve(np.asarray(Z))
     return np.ascontiguousarray(Y.T)
+
+
+def normalize_samples(X: np.ndarray) -> np.ndarray:
+    """Centre every variable and scale it so that diag(X^T X / m) = 1 (the
+    normalisation of the paper's experiments, Section 8)."""
+    X = X - X.mean(axis=0, keepdims=True)
+    s = np.sqrt(np.mean(X * X, axis=0))
+    s[s == 0] = 1.0
+    return np.ascontiguousarray(X / s)
 
 
 # --------------------------------------------------------------------------
@@ -195,6 +254,8 @@ def _precision(kind: str, n: int, rng: np.random.Generator, random_pairs_per_nod
         return grid_precision(r, c, n=n)
     if kind == "random":
         return random_precision(n, random_pairs_per_node * n, rng)
+    if kind == "delaunay":
+        return delaunay_precision(n, rng)
     raise ValueError(f"unknown graph kind {kind!r}")
 
 
@@ -221,6 +282,18 @@ WORKLOADS = {
                              pairs_per_node=5),
     "grid_n2500_m1500": dict(kind="grid", n=2500, m=1500, seed=15, lam=0.08, block=256,
                              grid=(50, 50)),
+    # Section 8.1 shapes: random planar graph Laplacians (n = the points drawn;
+    # about 1% of them, those near the boundary, are deleted), normalised samples
+    "delaunay_n125000_m200": dict(kind="delaunay", n=125000, m=200, seed=21, lam=0.7,
+                                  block=256, normalize=True),
+    "delaunay_n20000_m200": dict(kind="delaunay", n=20000, m=200, seed=22, lam=0.6,
+                                 block=256, normalize=True),
+    "delaunay_n700_m200": dict(kind="delaunay", n=700, m=200, seed=23, lam=0.5, block=64,
+                               normalize=True),
+    # Section 8.2 shapes (gene-expression data, n >> m): the datasets are not
+    # available; random sparse precisions of the same n and m stand in for them
+    "geo_n22283_m278": dict(kind="random", n=22283, m=278, seed=24, lam=0.75, block=256,
+                            pairs_per_node=3, normalize=True),
 }
 
 
@@ -234,6 +307,10 @@ def workload(name: str):
     else:
         P = _precision(spec["kind"], n, rng, spec.get("pairs_per_node", 5))
     X = sample_gaussian(P, spec["m"], rng)
+    if spec.get("normalize"):
+        X = normalize_samples(X)
+    spec["points"] = n
+    spec["n"] = X.shape[1]
     spec["name"] = name
     return X, P, spec
 

@@ -62,3 +62,39 @@ def test_request_stream_ranges():
     assert all(0.05 <= r["lam"] <= 0.5 for r in reqs)
     ts = [r["t"] for r in reqs]
     assert ts == sorted(ts) and ts[0] == 0.0
+
+
+def test_delaunay_laplacian_is_a_dirichlet_graph_laplacian():
+    """Section 8.1: -1 on every Delaunay edge, the degree on the diagonal, the
+    points near the boundary deleted; positive definite, 6-7 non-zeros a row."""
+    P = g.delaunay_precision(3000, np.random.default_rng(6))
+    n = P.shape[0]
+    assert 0.85 * 3000 < n < 3000
+    assert abs(P - P.T).max() == 0
+    off = sp.triu(P, 1).data
+    assert np.all(off == -1.0)
+    # the diagonal is the full graph's degree: at least the remaining off-diagonal count
+    cnt = np.diff(P.indptr) - 1
+    assert np.all(P.diagonal() >= cnt)
+    assert 5.5 < P.nnz / n < 7.5
+    lam_min = spla.eigsh(P.tocsc(), k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+    assert lam_min > 0
+
+
+def test_normalized_samples_have_unit_diagonal():
+    X, P, spec = g.workload("delaunay_n700_m200")
+    S_diag = np.mean(X * X, axis=0)
+    assert np.allclose(S_diag, 1.0, atol=1e-12)
+    assert np.allclose(X.mean(axis=0), 0.0, atol=1e-12)
+    assert spec["n"] == X.shape[1] == P.shape[0]
+
+
+def test_weakly_dominant_sampling_solve_is_exact():
+    """The Laplacian's samples come from a sparse LU solve: P Y = G xi exactly."""
+    rng = np.random.default_rng(7)
+    P = g.delaunay_precision(1500, rng)
+    assert not g._strictly_dominant(P)
+    X = g.sample_gaussian(P, 40, np.random.default_rng(8))
+    G = g._split_gram_factor(P)
+    xi = np.random.default_rng(8).standard_normal((G.shape[1], 40))
+    assert np.abs(P @ X.T - G @ xi).max() < 1e-9

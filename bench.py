@@ -313,12 +313,13 @@ def main():
     if args.cd_tol:
         solver_opts["cd_tol"] = args.cd_tol
 
-    def time_to_gap(precision, profile, flags=0):
+    def time_to_gap(precision, profile, flags=0, steps=None):
         """Calibrate c* (solve to KKT 1e-6, verify the exact gap after c*
         cycles), then time `steps` solves of c* cycles."""
         opts = dict(solver_opts, precision=precision, flags=flags)
+        nsteps = args.steps if steps is None else steps
         t_kkt = sup_kkt = None
-        info = {"cycles": None, "kkt_max": None}
+        info = {"cycles": None, "kkt_max": None, "sweeps": None, "max_nnz": None}
         if args.cycles > 0:
             cstar = args.cycles
         else:
@@ -362,7 +363,7 @@ def main():
             sic.profile_reset()
             sic.profile_enable(True)
         times = []
-        for _ in range(args.steps):
+        for _ in range(nsteps):
             torch.cuda.synchronize()
             t = time.perf_counter()
             (rp, col, val), _, _ = ctx_c.solve(Xd, lam, 1e-12)
@@ -384,7 +385,9 @@ def main():
         return dict(value=float(np.mean(times)), cycles=cstar, gap=gap,
                     support_identical_at_gap=bool(np.array_equal(keys, gkeys)),
                     support_identical_at_kkt=sup_kkt, nnz=int(col.size), time_to_kkt_1e6_s=t_kkt,
-                    kkt_cycles=info["cycles"], kkt_max=info["kkt_max"]), kern
+                    kkt_cycles=info["cycles"], kkt_max=info["kkt_max"],
+                    iterations_to_kkt=info["sweeps"], max_supp=info["max_nnz"],
+                    steps=nsteps), kern
 
     res64, kern = time_to_gap(sic.SIC_FP64, not args.no_kernel_timing)
     value, cstar, gap = res64["value"], res64["cycles"], res64["gap"]
@@ -397,10 +400,20 @@ def main():
                              "Cholesky / log det and KKT throughout")
     ablation = None
     if not args.no_ablation:
-        # the block relaxation alone (Algorithm 2 without the levels of Algorithm 1)
-        abl, _ = time_to_gap(sic.SIC_FP64, False, sic.FLAG_NO_MULTILEVEL)
+        # the columns of the paper's Section 8 tables on this workload: the
+        # block relaxation alone (BCD-IC: Algorithm 2 without the levels of
+        # Algorithm 1) and with the continuation schedule (BCDcont), beside
+        # ML-BCD; iterations count every sweep (coarse levels included) to KKT
+        # 1e-6, max_supp is the largest non-zero count of any iterate
+        ab_steps = min(args.steps, 5)
+        abl, _ = time_to_gap(sic.SIC_FP64, False, sic.FLAG_NO_MULTILEVEL, ab_steps)
         abl["multilevel_speedup"] = abl["value"] / value
-        ablation = dict(no_multilevel=abl)
+        cont, _ = time_to_gap(sic.SIC_FP64, False,
+                              sic.FLAG_NO_MULTILEVEL | sic.FLAG_CONTINUATION, ab_steps)
+        cont["multilevel_speedup"] = cont["value"] / value
+        ablation = dict(ml_bcd=dict(iterations_to_kkt=res64["iterations_to_kkt"],
+                                    max_supp=res64["max_supp"], nnz=res64["nnz"]),
+                        no_multilevel=abl, continuation=cont)
     roofline = None
     if kern:
         # the dominant class measured live over the timed solves; its share of

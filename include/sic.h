@@ -73,6 +73,12 @@ extern "C" {
                                               of the graph of A's support and the last finest
                                               sweep's free pairs (sic_cluster_order); results
                                               come back in the caller's labels */
+#define SIC_FLAG_CONTINUATION (1ull << 5)  /* continuation (the BCDcont schedule of Section 8):
+                                              the first three cycles run at lambda_4 =
+                                              (1 + lambda) / 2 and then two values linearly
+                                              spaced down towards lambda, one cycle each; the
+                                              fourth and later cycles run at lambda. With
+                                              SIC_FLAG_NO_MULTILEVEL this is BCDcont */
 
 typedef struct sic_ctx sic_ctx;
 

@@ -8,6 +8,7 @@
 // and builds the nested level sets from the recorded free set.
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -1145,6 +1146,32 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
         ~PrecReset() { c.prec = PREC_F64; }
     } prec_reset{C};
     C.prec = cycle_precision(C, P, INFINITY);
+    // continuation (Section 8): lambda_4 = (1 + lambda) / 2 (normalised data puts
+    // any useful lambda below 1; never below lambda itself), lambda_3 and
+    // lambda_2 linearly spaced towards lambda_1 = lambda, one cycle each, then
+    // lambda until convergence. F follows each change of lambda exactly:
+    // F changes by (lambda_new - lambda_old) ||A||_1.
+    const double lam_target = P.lam;
+    const bool cont = (C.opt.flags & SIC_FLAG_CONTINUATION) != 0;
+    const double lam4 = std::max(0.5 * (1.0 + lam_target), lam_target);
+    auto lam_of = [&](int cyc) {
+        return (!cont || cyc >= 3) ? lam_target : lam4 - (lam4 - lam_target) * cyc / 3.0;
+    };
+    auto set_lambda = [&](double lam) {
+        if (lam == P.lam) return;
+        P.F += (lam - P.lam) * a_l1_norm(C, P);
+        P.lam = lam;
+    };
+    struct LamReset {   // the solve ends at the caller's lambda whatever happens
+        std::function<void()> f;
+        ~LamReset() {
+            try {
+                f();
+            } catch (...) {
+            }
+        }
+    } lam_reset{[&]() { set_lambda(lam_target); }};
+    set_lambda(lam_of(0));
     initial_free_set(C, P);
     double kkt_prev = INFINITY, kkt_l1 = INFINITY;
     int status = SIC_ENOCONV;
@@ -1158,6 +1185,7 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
         const double tolI = std::min(C.opt.cg_tol_I, std::max(1e-12, 0.01 * kkt_prev));
         const double tolN = std::min(C.opt.cg_tol_N, std::max(1e-12, 0.01 * kkt_prev));
         C.prec = cycle_precision(C, P, kkt_prev);
+        set_lambda(lam_of(cyc));
         if (C.opt.flags & SIC_FLAG_CLUSTER) cluster_problem(C, P);
         int levels = 0;
         if (ml) {
@@ -1200,7 +1228,7 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
         // confirms the sweep's measure, which saw each block before its update
         // and W from the sweep's looser CG
         certified = false;
-        if (sr.kkt_max <= tol && C.prec == PREC_F64) {
+        if (sr.kkt_max <= tol && C.prec == PREC_F64 && P.lam == lam_target) {
             if (!certify) {
                 status = SIC_OK;
                 break;
@@ -1226,6 +1254,7 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
         certified = false;
     }
     C.prec = PREC_F64;
+    set_lambda(lam_target);
     double kkt_final = kkt_prev;
     if ((C.opt.flags & SIC_FLAG_FINAL_KKT) && !certified) {
         // the exact measure of whatever iterate the solve ends with

@@ -182,3 +182,23 @@ def test_submit_while_another_thread_waits():
     assert not errors, errors
     assert got["first"][0] == 0
     assert all(r[0] == 0 for r in rest)
+
+
+@pytest.mark.parametrize("name,multilevel", [("random_n600_m300", False),
+                                             ("delaunay_n700_m200", True)])
+def test_continuation_matches_oracle(name, multilevel):
+    """The continuation schedule of Section 8 (BCDcont without the levels):
+    three cycles at larger lambdas, then lambda; the result is the oracle's
+    minimiser at lambda, and the reported objective is F at lambda."""
+    from paper_1607_00315_amd import sic
+    X, P, spec = workload(name)
+    n = X.shape[1]
+    lam = spec["lam"]
+    S = core.covariance(X)
+    flags = sic.FLAG_CONTINUATION | (0 if multilevel else sic.FLAG_NO_MULTILEVEL)
+    announce(f"continuation {name} lam={lam} multilevel={multilevel}")
+    with sic.Context(block=spec["block"], flags=flags, trace_cap=64) as c:
+        (rp, col, val), info, trace = c.solve(X, lam, TOL)
+    assert info["status"] == 0
+    assert info["cycles"] >= 4
+    _check_against_oracle(csr_to_dense(rp, col, val, n), _oracle(S, lam), S, lam, info)

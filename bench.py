@@ -131,6 +131,52 @@ def cpu_baseline(name, X, lam, golden, budget_s):
                 higher_is_better=False)
 
 
+# The paper's own CPU timings for its planar-graph workload (Section 8.1 table,
+# n = 124,294, lambda = 0.7, stopping at ||min-norm subgradient||_1 < 5e-3 ||A||_1;
+# 2 x 8-core Xeon at 2.0 GHz, MATLAB with C routines): context, not a target.
+PAPER_SYNTH_CONTEXT = dict(n=124294, lam=0.7, nnz_star=491388,
+                           ml_bcd=dict(seconds=545, iterations=5, max_supp=492744),
+                           bcd_ic=dict(seconds=1447, iterations=4, max_supp=501504),
+                           hardware="2x Xeon E5-2650 (16 cores), MATLAB + C")
+
+
+def paper_leg(sic, torch, name, configs):
+    """Section 8 shapes: solve the named workload to KKT 1e-6 in each config
+    (label, flags, precision) and report the time to KKT 1e-6, the time and
+    iterations to the paper's stopping rule (||m||_1 < 5e-3 ||A||_1, from the
+    per-cycle trace), iterations (every sweep, coarse levels included) and
+    max-supp, as in the columns of the paper's tables."""
+    from synth import workload
+    t = time.perf_counter()
+    X, P, spec = workload(name)
+    log(f"paper leg {name}: n={X.shape[1]} m={X.shape[0]} lambda={spec['lam']} generated in "
+        f"{time.perf_counter()-t:.1f}s")
+    Xd = torch.from_numpy(X).to("cuda:0")
+    out = dict(workload=name, n=int(X.shape[1]), m=int(X.shape[0]), **{"lambda": spec["lam"]},
+               block=spec["block"], normalized=bool(spec.get("normalize")))
+    for label, flags, prec in configs:
+        with sic.Context(block=spec["block"], flags=flags, precision=prec, trace_cap=128) as c:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            (rp, col, val), info, trace = c.solve(Xd, spec["lam"], 1e-6)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+        rule = next((e for e in trace if e["kkt_rel_l1"] < 5e-3), None)
+        sweeps_to = (sum(e["levels"] + 1 for e in trace[:trace.index(rule) + 1])
+                     if rule is not None else None)
+        out[label] = dict(seconds_to_kkt_1e6=el, status=info["status"], kkt_max=info["kkt_max"],
+                          iterations=info["sweeps"], cycles=info["cycles"],
+                          max_supp=info["max_nnz"], nnz=info["nnz"], objective=info["objective"],
+                          seconds_to_paper_rule=rule["seconds"] if rule else None,
+                          iterations_to_paper_rule=sweeps_to)
+        log(f"  {label}: {el:.2f}s to KKT {info['kkt_max']:.1e}, {info['sweeps']} sweeps, "
+            f"max-supp {info['max_nnz']}, nnz {info['nnz']}, paper rule at "
+            f"{out[label]['seconds_to_paper_rule']}")
+    del Xd
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(sic, torch, count, slots, tol):
     """Served solves/s and p50/p99 latency on the request stream.
 
@@ -253,6 +299,11 @@ def main():
     ap.add_argument("--path-only", type=int, default=0, metavar="K",
                     help="run only the warm-started lambda path (its first K values)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-paper-shaped", action="store_true",
+                    help="skip the planar-graph leg (natural vs clustered blocks)")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="only the Section 8.1-shaped leg at n = 123,607 (ML-BCD float64 and "
+                         "mixed, BCD-IC and BCDcont, all on clustered blocks)")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the block-relaxation-only (no levels) leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -274,6 +325,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.paper_only:
+        cl = sic.FLAG_CLUSTER
+        out = paper_leg(sic, torch, "delaunay_n125000_m200", [
+            ("ml_bcd", cl, sic.SIC_FP64), ("ml_bcd_mixed", cl, sic.SIC_MIXED),
+            ("bcd_ic", cl | sic.FLAG_NO_MULTILEVEL, sic.SIC_FP64),
+            ("bcd_cont", cl | sic.FLAG_NO_MULTILEVEL | sic.FLAG_CONTINUATION, sic.SIC_FP64)])
+        out["paper_context"] = PAPER_SYNTH_CONTEXT
+        print(json.dumps(dict(metric="Section 8.1 shape: seconds to KKT 1e-6 and to the paper's "
+                              "stopping rule", n_gpus=1, data="synthetic", paper=out)), flush=True)
+        return
     if args.path_only > 0:
         out = path_leg(sic, torch, args.path_only)
         print(json.dumps(dict(metric="lambda path: time to KKT 1e-6 per lambda (s)", n_gpus=1,
@@ -436,6 +497,14 @@ def main():
         # every class over one untimed solve
         for kname, kv in full.items():
             kv["avg_ms"] = kv["ms"] / kv["launches"] if kv["launches"] else None
+    paper_shaped = None
+    if not args.no_paper_shaped:
+        # random-labelled planar graph (Section 8.1 shape at n = 19,435): the
+        # contiguous natural blocks against the clustered partition
+        paper_shaped = paper_leg(sic, torch, "delaunay_n20000_m200", [
+            ("natural_blocks", 0, sic.SIC_FP64), ("clustered_blocks", sic.FLAG_CLUSTER, sic.SIC_FP64)])
+        paper_shaped["clustering_speedup"] = (paper_shaped["natural_blocks"]["seconds_to_kkt_1e6"] /
+                                              paper_shaped["clustered_blocks"]["seconds_to_kkt_1e6"])
     serving = None
     if args.serve_requests > 0:
         serving = serving_leg(sic, torch, args.serve_requests, args.serve_slots, args.serve_tol)
@@ -453,7 +522,7 @@ def main():
         support_identical_at_kkt=res64["support_identical_at_kkt"],
         nnz=res64["nnz"], time_to_kkt_1e6_s=res64["time_to_kkt_1e6_s"],
         kkt_cycles=res64["kkt_cycles"], kkt_max=res64["kkt_max"], mixed=mixed, ablation=ablation,
-        roofline=roofline, cpu_baseline=cpu, serving=serving,
+        roofline=roofline, cpu_baseline=cpu, serving=serving, paper_shaped=paper_shaped,
         kernels={k: dict(launches=v["launches"], ms=round(v["ms"], 3),
                          avg_ms=v["avg_ms"], GBps=(v["bytes"] / (v["ms"] * 1e-3) / 1e9)
                          if v["ms"] > 0 and v["bytes"] > 0 else None)

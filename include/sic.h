@@ -93,6 +93,7 @@ typedef struct {
     double seconds;    /* since the start of the solve */
     double objective;  /* tracked F(A) after the cycle */
     double kkt_max;    /* finest sweep's max-norm of the min-norm subgradient */
+    double kkt_rel_l1; /* its l1 norm over ||A||_1 (the stopping measure of Section 8) */
     int64_t nnz;       /* non-zeros of A (both triangles) */
     int32_t cycle;
     int32_t levels;    /* coarse levels visited in this cycle */

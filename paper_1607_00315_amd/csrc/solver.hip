@@ -1218,6 +1218,8 @@ int solve_problem(Context& C, Problem& P, double tol, sic_info* info) {
             e.seconds = secs();
             e.objective = P.F;
             e.kkt_max = sr.kkt_max;
+            const double l1 = a_l1_norm(C, P);
+            e.kkt_rel_l1 = l1 > 0 ? sr.kkt_l1 / l1 : INFINITY;
             e.nnz = P.Acur().nnz;
             e.cycle = cyc;
             e.levels = levels;

@@ -39,7 +39,8 @@ class CSR(ct.Structure):
 
 class TraceEntry(ct.Structure):
     _fields_ = [("seconds", ct.c_double), ("objective", ct.c_double), ("kkt_max", ct.c_double),
-                ("nnz", ct.c_int64), ("cycle", ct.c_int32), ("levels", ct.c_int32)]
+                ("kkt_rel_l1", ct.c_double), ("nnz", ct.c_int64), ("cycle", ct.c_int32),
+                ("levels", ct.c_int32)]
 
 
 class Options(ct.Structure):
@@ -333,8 +334,9 @@ class Context:
     def trace(self, length):
         if self._trace is None:
             return []
-        return [dict(seconds=e.seconds, objective=e.objective, kkt_max=e.kkt_max, nnz=e.nnz,
-                     cycle=e.cycle, levels=e.levels) for e in self._trace[:length]]
+        return [dict(seconds=e.seconds, objective=e.objective, kkt_max=e.kkt_max,
+                     kkt_rel_l1=e.kkt_rel_l1, nnz=e.nnz, cycle=e.cycle, levels=e.levels)
+                for e in self._trace[:length]]
 
 
 class Server:

@@ -291,9 +291,10 @@ WORKLOADS = {
     "delaunay_n700_m200": dict(kind="delaunay", n=700, m=200, seed=23, lam=0.5, block=64,
                                normalize=True),
     # Section 8.2 shapes (gene-expression data, n >> m): the datasets are not
-    # available; random sparse precisions of the same n and m stand in for them
-    "geo_n22283_m278": dict(kind="random", n=22283, m=278, seed=24, lam=0.75, block=256,
-                            pairs_per_node=3, normalize=True),
+    # available; planar-graph Gaussian samples of the same n and m, normalised
+    # the same way, stand in for them
+    "geo_n22283_m278": dict(kind="delaunay", n=22283, m=278, seed=24, lam=0.7, block=256,
+                            normalize=True),
 }
 
 

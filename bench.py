@@ -124,7 +124,14 @@ def cpu_baseline(name, X, lam, golden, budget_s):
     recorded = hist[min(its, len(hist) - 1)]["seconds"]
     scale = measured / recorded if recorded > 0 else float("nan")
     value = t_gap * scale if t_gap is not None else None
-    return dict(value=value, unit="s", cores=int(threads), kind="oracle",
+    host = dict(nproc=os.cpu_count())
+    try:
+        host["lscpu_model"] = next((l.split(":", 1)[1].strip() for l in
+                                    open("/proc/cpuinfo") if l.startswith("model name")), None)
+        host["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    return dict(value=value, unit="s", cores=int(threads), kind="oracle", host=host,
                 sample=f"{its} oracle iteration(s) on {name} in {measured:.1f}s "
                        f"(recorded {recorded:.1f}s); time to gap {GAP:g} extrapolated "
                        f"from the recorded oracle history ({t_gap:.1f}s) by that ratio",

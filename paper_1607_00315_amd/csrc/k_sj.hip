@@ -35,8 +35,10 @@ __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ 
                                                      int64_t m, int64_t j0, int b,
                                                      double* __restrict__ out, double invm,
                                                      int row_tiles, int col_tiles) {
-    __shared__ double sA[SJ_KC][SJ_TILE + SJ_PAD];
-    __shared__ double sB[SJ_KC][SJ_TILE + SJ_PAD];
+    // two LDS buffers by round parity: the next round's samples are loaded
+    // from memory while the MFMAs run on this round's, and stored after them
+    __shared__ double sA[2][SJ_KC][SJ_TILE + SJ_PAD];
+    __shared__ double sB[2][SJ_KC][SJ_TILE + SJ_PAD];
     const int L = blockIdx.x, xcd = L & 7, slot = L >> 3;
     const int rt = (slot / col_tiles) * 8 + xcd, ct = slot % col_tiles;
     if (rt >= row_tiles) return;
@@ -52,34 +54,53 @@ __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ 
     double4_t acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int bb = 0; bb < 2; ++bb) acc[a][bb] = (double4_t){0.0, 0.0, 0.0, 0.0};
-
-    for (int64_t r0 = 0; r0 < m; r0 += SJ_KC) {
+    double ra[4], rb[4];
+    auto load = [&](int64_t r0) {
         const int64_t r = r0 + lr;
         const bool rok = r < m;
-        const double* xrow = X + r * n;
+        const double* xrow = X + (rok ? r : 0) * n;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t ia = i0 + lc + q;
             const int cb = c0 + lc + q;
-            sA[lr][lc + q] = (rok && ia < n) ? xrow[ia] : 0.0;
-            sB[lr][lc + q] = (rok && cb < b) ? xrow[j0 + cb] : 0.0;
+            const bool oka = rok && ia < n, okb = rok && cb < b;
+            const double va = xrow[oka ? ia : 0];
+            const double vb = xrow[okb ? j0 + cb : 0];
+            ra[q] = oka ? va : 0.0;
+            rb[q] = okb ? vb : 0.0;
         }
-        __syncthreads();
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sA[buf][lr][lc + q] = ra[q];
+            sB[buf][lr][lc + q] = rb[q];
+        }
+    };
+    load(0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t r0 = 0; r0 < m; r0 += SJ_KC) {
+        const bool more = r0 + SJ_KC < m;
+        if (more) load(r0 + SJ_KC);
 #pragma unroll
         for (int kk = 0; kk < SJ_KC; kk += 4) {
             const int kr = kk + (lane >> 4);
             double av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = sA[kr][wr * 32 + a * 16 + (lane & 15)];
+            for (int a = 0; a < 2; ++a) av[a] = sA[buf][kr][wr * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-            for (int bb = 0; bb < 2; ++bb) bv[bb] = sB[kr][wc * 32 + bb * 16 + (lane & 15)];
+            for (int bb = 0; bb < 2; ++bb) bv[bb] = sB[buf][kr][wc * 32 + bb * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int bb = 0; bb < 2; ++bb)
                     acc[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[bb], acc[a][bb], 0, 0, 0);
         }
+        if (more) stage(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)

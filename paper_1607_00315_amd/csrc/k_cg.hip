@@ -33,6 +33,8 @@ constexpr int CG_WAVES = CG_THREADS / 64;
 constexpr int CG_ROW_TILES = 128;   // row partitions (partials per column)
 constexpr int CG_TPW = CG_ROW_TILES / CG_WAVES;   // partials each wave sums per column
 constexpr int CG_GATHER = 8;        // gathers per row issued before their products
+constexpr int CG_UROWS = 4;         // rows per wave in flight in the update
+constexpr int CG_SROWS = 2;         // rows per wave in flight in the product
 
 // per-tile control block: [0] done, [1] iterations finished, [2] breakdown
 // (p.Ap <= 0 with r.z > 0 in some column: A is not positive definite)
@@ -197,60 +199,57 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     double pq = 0.0;
     const int64_t r0 = (int64_t)ty * rows_per;
     const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
-    // Two rows per wave at a time (i and i + 8), their gathers issued together
-    // in batches of CG_GATHER per row (a grid row's whole gather in one). A short batch repeats the row's last entry
-    // with a zero coefficient; a missing second row repeats the first, and
-    // only the first is stored.
-    for (int64_t i = r0 + wave; i < r1; i += 2 * CG_WAVES) {
-        const int64_t i2 = i + CG_WAVES;
-        const bool has2 = i2 < r1;
-        const int64_t ib = has2 ? i2 : i;
-        const int64_t ea0 = rowptr[i], ea1 = rowptr[i + 1];
-        const int64_t eb0 = rowptr[ib], eb1 = rowptr[ib + 1];
-        const int64_t oa = i * k + jj, ob = ib * k + jj;
-        const double za = zval<V>(dinv[i], R[oa]);
-        const double zb = zval<V>(dinv[ib], R[ob]);
-        const double pa = first ? 0.0 : (double)P[oa];
-        const double pb = first ? 0.0 : (double)P[ob];
-        const double qa = first ? 0.0 : (double)Q[oa];
-        const double qb = first ? 0.0 : (double)Q[ob];
-        double acca = 0.0, accb = 0.0;
-        const int64_t na = ea1 - ea0, nbr = eb1 - eb0;
-        const int64_t nmax = na > nbr ? na : nbr;
+    // CG_SROWS rows per wave at a time (i, i + 8, ...), their gathers issued
+    // together in batches of CG_GATHER per row (a grid row's whole gather in
+    // one). A short batch repeats the row's last entry with a zero
+    // coefficient; a missing row repeats row i and is not stored.
+    for (int64_t i = r0 + wave; i < r1; i += CG_SROWS * CG_WAVES) {
+        bool has[CG_SROWS];
+        int64_t e0[CG_SROWS], ne[CG_SROWS], o[CG_SROWS];
+        double zo[CG_SROWS], po[CG_SROWS], qo[CG_SROWS], acc[CG_SROWS];
+        int64_t nmax = 0;
+#pragma unroll
+        for (int u = 0; u < CG_SROWS; ++u) {
+            const int64_t iu = i + (int64_t)u * CG_WAVES;
+            has[u] = iu < r1;
+            const int64_t ic = has[u] ? iu : i;
+            e0[u] = rowptr[ic];
+            ne[u] = rowptr[ic + 1] - e0[u];
+            nmax = ne[u] > nmax ? ne[u] : nmax;
+            o[u] = ic * k + jj;
+            zo[u] = zval<V>(dinv[ic], R[o[u]]);
+            po[u] = first ? 0.0 : (double)P[o[u]];
+            qo[u] = first ? 0.0 : (double)Q[o[u]];
+            acc[u] = 0.0;
+        }
         for (int64_t e = 0; e < nmax; e += CG_GATHER) {
-            V ra[CG_GATHER], rb[CG_GATHER];
-            double va[CG_GATHER], vb[CG_GATHER], da[CG_GATHER], db[CG_GATHER];
+            V rg[CG_SROWS][CG_GATHER];
+            double vg[CG_SROWS][CG_GATHER], dg[CG_SROWS][CG_GATHER];
 #pragma unroll
-            for (int u = 0; u < CG_GATHER; ++u) {
-                const bool ina = e + u < na, inb = e + u < nbr;
-                const int64_t xa = ina ? ea0 + e + u : ea1 - 1;
-                const int64_t xb = inb ? eb0 + e + u : eb1 - 1;
-                const int64_t ca = col[xa], cb = col[xb];
-                va[u] = ina ? val[xa] : 0.0;
-                vb[u] = inb ? val[xb] : 0.0;
-                da[u] = dinv[ca];
-                db[u] = dinv[cb];
-                ra[u] = R[ca * k + jj];
-                rb[u] = R[cb * k + jj];
-            }
+            for (int u = 0; u < CG_SROWS; ++u)
 #pragma unroll
-            for (int u = 0; u < CG_GATHER; ++u) {
-                acca += va[u] * zval<V>(da[u], ra[u]);
-                accb += vb[u] * zval<V>(db[u], rb[u]);
-            }
+                for (int g = 0; g < CG_GATHER; ++g) {
+                    const bool in = e + g < ne[u];
+                    const int64_t x = in ? e0[u] + e + g : e0[u] + ne[u] - 1;
+                    const int64_t c = col[x];
+                    vg[u][g] = in ? val[x] : 0.0;
+                    dg[u][g] = dinv[c];
+                    rg[u][g] = R[c * k + jj];
+                }
+#pragma unroll
+            for (int u = 0; u < CG_SROWS; ++u)
+#pragma unroll
+                for (int g = 0; g < CG_GATHER; ++g) acc[u] += vg[u][g] * zval<V>(dg[u][g], rg[u][g]);
         }
         if (jok) {
-            const V p1 = (V)(first ? za : za + beta * pa);
-            const V q1 = (V)(first ? acca : acca + beta * qa);
-            P[oa] = p1;
-            Q[oa] = q1;
-            pq += (double)p1 * (double)q1;
-            if (has2) {
-                const V p2 = (V)(first ? zb : zb + beta * pb);
-                const V q2 = (V)(first ? accb : accb + beta * qb);
-                P[ob] = p2;
-                Q[ob] = q2;
-                pq += (double)p2 * (double)q2;
+#pragma unroll
+            for (int u = 0; u < CG_SROWS; ++u) {
+                if (!has[u]) continue;
+                const V pn = (V)(first ? zo[u] : zo[u] + beta * po[u]);
+                const V qn = (V)(first ? acc[u] : acc[u] + beta * qo[u]);
+                P[o[u]] = pn;
+                Q[o[u]] = qn;
+                pq += (double)pn * (double)qn;
             }
         }
     }
@@ -312,29 +311,33 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     const int64_t r0 = (int64_t)ty * rows_per;
     const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
     if (jok) {
-        // two rows per wave at a time: eight loads in flight before the stores
-        for (int64_t i = r0 + wave; i < r1; i += 2 * CG_WAVES) {
-            const int64_t i2 = i + CG_WAVES;
-            const bool has2 = i2 < r1;
-            const int64_t oa = i * k + j, ob = (has2 ? i2 : i) * k + j;
-            const double wa = W[oa], wb = W[ob];
-            const double pa = (double)P[oa], pb = (double)P[ob];
-            const double ra = (double)R[oa], rb = (double)R[ob];
-            const double qa = (double)Q[oa], qb = (double)Q[ob];
-            const double dia = dinv[i], dib = dinv[has2 ? i2 : i];
-            W[oa] = wa + alpha * pa;
-            const V r1v = (V)(ra - alpha * qa);
-            R[oa] = r1v;
-            const double z1 = zval<V>(dia, r1v);
-            rz += (double)r1v * z1;
-            rr += (double)r1v * (double)r1v;
-            if (has2) {
-                W[ob] = wb + alpha * pb;
-                const V r2v = (V)(rb - alpha * qb);
-                R[ob] = r2v;
-                const double z2 = zval<V>(dib, r2v);
-                rz += (double)r2v * z2;
-                rr += (double)r2v * (double)r2v;
+        // CG_UROWS rows per wave at a time (i, i + 8, ...): all their loads in
+        // flight before the first store; missing rows repeat row i, unstored
+        for (int64_t i = r0 + wave; i < r1; i += CG_UROWS * CG_WAVES) {
+            int64_t o[CG_UROWS];
+            bool has[CG_UROWS];
+            double wv[CG_UROWS], pv[CG_UROWS], rv[CG_UROWS], qv[CG_UROWS], dv[CG_UROWS];
+#pragma unroll
+            for (int u = 0; u < CG_UROWS; ++u) {
+                const int64_t iu = i + (int64_t)u * CG_WAVES;
+                has[u] = iu < r1;
+                const int64_t ic = has[u] ? iu : i;
+                o[u] = ic * k + j;
+                wv[u] = W[o[u]];
+                pv[u] = (double)P[o[u]];
+                rv[u] = (double)R[o[u]];
+                qv[u] = (double)Q[o[u]];
+                dv[u] = dinv[ic];
+            }
+#pragma unroll
+            for (int u = 0; u < CG_UROWS; ++u) {
+                if (!has[u]) continue;
+                W[o[u]] = wv[u] + alpha * pv[u];
+                const V rn = (V)(rv[u] - alpha * qv[u]);
+                R[o[u]] = rn;
+                const double zn = zval<V>(dv[u], rn);
+                rz += (double)rn * zn;
+                rr += (double)rn * (double)rn;
             }
         }
     }

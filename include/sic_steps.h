@@ -59,7 +59,7 @@ int sic_step_inverse_columns(sic_prob* p, const int32_t* cols, int k, double tol
  * harnesses that forbid hipMalloc): no device or host allocation happens in
  * this call. Every buffer of the solve lives in one static device array of
  * 128 MiB per GPU (held until the process ends); a solve needs about
- * 24 n k bytes (three n x k float64 arrays) plus O(n + k), which
+ * 24 n k bytes (three n x k float64 arrays) plus 8 nnz + O(n + k), which
  * sic_step_inverse_columns_noalloc_limit reports (0 when it does not fit),
  * and k <= 4096. Larger problems return SIC_ETOOBIG.
  *   rowptr[n+1], col[nnz], val[nnz]: A as a full symmetric CSR with sorted
@@ -78,7 +78,7 @@ int sic_step_inverse_columns_noalloc(const int64_t* rowptr, const int32_t* col,
                                      const int32_t* cols, int k, double tol, int max_iter,
                                      double* W, void* stream, int* iterations,
                                      double* max_rel_residual);
-size_t sic_step_inverse_columns_noalloc_limit(int64_t n, int k);
+size_t sic_step_inverse_columns_noalloc_limit(int64_t n, int64_t nnz, int k);
 
 /* Level set C_l for coarse block updates (Section 7, eq. (MLE_l1_prior_C)):
  * `count` pair keys i*n + j with i <= j. */

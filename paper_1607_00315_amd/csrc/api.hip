@@ -394,10 +394,10 @@ int sic_step_inverse_columns_noalloc(const int64_t* rowptr, const int32_t* col,
     });
 }
 
-size_t sic_step_inverse_columns_noalloc_limit(int64_t n, int k) {
-    if (n < 1 || k < 1 || k > sic::cg_noalloc_max_k()) return 0;
-    return sic::cg_noalloc_bytes(n, k) <= sic::cg_noalloc_capacity() ? sic::cg_noalloc_bytes(n, k)
-                                                                     : 0;
+size_t sic_step_inverse_columns_noalloc_limit(int64_t n, int64_t nnz, int k) {
+    if (n < 1 || nnz < 0 || k < 1 || k > sic::cg_noalloc_max_k()) return 0;
+    const size_t need = sic::cg_noalloc_bytes(n, nnz, k);
+    return need <= sic::cg_noalloc_capacity() ? need : 0;
 }
 
 int sic_step_set_level(sic_prob* p, const int64_t* keys, int64_t count) {

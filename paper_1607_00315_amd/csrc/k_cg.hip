@@ -32,9 +32,11 @@ constexpr int CG_THREADS = 512;     // 8 waves, one matrix row per wave at a tim
 constexpr int CG_WAVES = CG_THREADS / 64;
 constexpr int CG_ROW_TILES = 128;   // row partitions (partials per column)
 constexpr int CG_TPW = CG_ROW_TILES / CG_WAVES;   // partials each wave sums per column
-constexpr int CG_GATHER = 8;        // gathers per row issued before their products
+// gathers per row issued before their products: 8, or 16 for matrices whose
+// rows average more than CG_WIDE_ROW entries (dense-regime iterates)
+constexpr int CG_WIDE_ROW = 12;
 constexpr int CG_UROWS = 4;         // rows per wave in flight in the update
-constexpr int CG_SROWS = 2;         // rows per wave in flight in the product
+constexpr int CG_SROWS = 1;         // rows per wave in flight in the product
 
 // per-tile control block: [0] done, [1] iterations finished, [2] breakdown
 // (p.Ap <= 0 with r.z > 0 in some column: A is not positive definite)
@@ -49,6 +51,15 @@ __global__ void k_cg_dinv(const int64_t* __restrict__ rowptr, const int32_t* __r
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
         if (col[e] == (int32_t)i) d = val[e];
     dinv[i] = d > 0.0 ? 1.0 / d : 1.0;
+}
+
+// The product's coefficients with the preconditioner folded in:
+// vd[e] = a_ic d_c, so that (A z)_i = sum_e vd[e] r_c with z = D^{-1} r.
+__global__ void k_cg_vd(const int32_t* __restrict__ col, const double* __restrict__ val,
+                        const double* __restrict__ dinv, int64_t nnz, double* __restrict__ vd) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        vd[e] = val[e] * dinv[col[e]];
 }
 
 template <typename V>
@@ -86,8 +97,9 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadId
 
 // The preconditioned residual z = D^{-1} r of one entry, rounded to the
 // vector type (the value a stored z would hold). It is formed wherever it is
-// read instead of being stored: one n x k array less written and read per
-// iteration.
+// read instead of being stored (one n x k array less written and read per
+// iteration); the product's gathers take D^{-1} folded into the
+// coefficients (k_cg_vd), so they read r alone.
 template <typename V>
 __device__ inline double zval(double di, V r) {
     return (double)(V)(di * (double)r);
@@ -128,10 +140,10 @@ __device__ inline Tile cg_tile(int mode, int gx, int gy) {
     return t;
 }
 
-template <typename V>
+template <typename V, int CG_GATHER>
 __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, int64_t n, int k, const double* __restrict__ dinv,
+    const double* __restrict__ vd, int64_t n, int k, const double* __restrict__ dinv,
     const V* __restrict__ R, V* __restrict__ P, V* __restrict__ Q, double* __restrict__ scal,
     const double* __restrict__ rzrr, double* __restrict__ part, int* __restrict__ tctl,
     double* __restrict__ tres, double tol, int it, int gx, int gy, int64_t rows_per, int mode,
@@ -200,8 +212,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const int64_t r0 = (int64_t)ty * rows_per;
     const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
     // CG_SROWS rows per wave at a time (i, i + 8, ...), their gathers issued
-    // together in batches of CG_GATHER per row (a grid row's whole gather in
-    // one). A short batch repeats the row's last entry with a zero
+    // together in batches of CG_GATHER per row. A short batch repeats the row's last entry with a zero
     // coefficient; a missing row repeats row i and is not stored.
     for (int64_t i = r0 + wave; i < r1; i += CG_SROWS * CG_WAVES) {
         bool has[CG_SROWS];
@@ -224,22 +235,20 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
         }
         for (int64_t e = 0; e < nmax; e += CG_GATHER) {
             V rg[CG_SROWS][CG_GATHER];
-            double vg[CG_SROWS][CG_GATHER], dg[CG_SROWS][CG_GATHER];
+            double vg[CG_SROWS][CG_GATHER];
 #pragma unroll
             for (int u = 0; u < CG_SROWS; ++u)
 #pragma unroll
                 for (int g = 0; g < CG_GATHER; ++g) {
                     const bool in = e + g < ne[u];
                     const int64_t x = in ? e0[u] + e + g : e0[u] + ne[u] - 1;
-                    const int64_t c = col[x];
-                    vg[u][g] = in ? val[x] : 0.0;
-                    dg[u][g] = dinv[c];
-                    rg[u][g] = R[c * k + jj];
+                    vg[u][g] = in ? vd[x] : 0.0;
+                    rg[u][g] = R[(int64_t)col[x] * k + jj];
                 }
 #pragma unroll
             for (int u = 0; u < CG_SROWS; ++u)
 #pragma unroll
-                for (int g = 0; g < CG_GATHER; ++g) acc[u] += vg[u][g] * zval<V>(dg[u][g], rg[u][g]);
+                for (int g = 0; g < CG_GATHER; ++g) acc[u] += vg[u][g] * (double)rg[u][g];
         }
         if (jok) {
 #pragma unroll
@@ -438,13 +447,14 @@ struct CsrView {
     int64_t n, nnz;
 };
 
-// Buffers of one solve. Device: dinv (n), part (row_tiles * k * 3), scal
+// Buffers of one solve. Device: dinv (n), vd (nnz), part (row_tiles * k * 3), scal
 // (4k + col_tiles), flags (T_INTS * col_tiles). Host: hctl (T_INTS *
 // col_tiles ints) and hres (col_tiles doubles), the targets of the control
 // read-backs. predicted: iterations of the last solve of this kind (read and
 // updated). prof: record launches with the profiler.
 struct CGBufs {
     double* dinv;
+    double* vd;
     double* part;
     double* scal;
     int* flags;
@@ -499,6 +509,7 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
         return res;
     }
     const CgGeom G = cg_geom(n, k);
+    const bool wide = A.nnz > (int64_t)CG_WIDE_ROW * n;
     const int col_tiles = G.gx;
     const int row_tiles = G.gy;
     // partials: r.z and r.r of an update (two per entry), then p.q of a product
@@ -507,6 +518,9 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
     double* tres = bf.scal + 4 * k;
     hipLaunchKernelGGL(k_cg_dinv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        A.rowptr, A.col, A.val, n, bf.dinv);
+    SIC_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_cg_vd, dim3((unsigned)std::min<int64_t>((A.nnz + 255) / 256, 4096)),
+                       dim3(256), 0, s, A.col, A.val, bf.dinv, A.nnz, bf.vd);
     SIC_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, s,
                        n, k, col_tiles, d_cols, bf.dinv, W, R, bf.scal, bf.flags, tres);
@@ -538,10 +552,16 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
             Rec r;
             r.iter = it;
             if (bf.prof) prof_begin(KK_CG_SPMM, s);
-            hipLaunchKernelGGL(k_cg_spmm<V>, G.grid, dim3(CG_THREADS), 0, s, A.rowptr, A.col,
-                               A.val, n, k, bf.dinv, R, P, Q, bf.scal, part_rz, part_pq,
-                               bf.flags, tres, tol, it, col_tiles, row_tiles, G.rows_per, G.mode,
-                               0);
+            if (wide)
+                hipLaunchKernelGGL((k_cg_spmm<V, 16>), G.grid, dim3(CG_THREADS), 0, s, A.rowptr,
+                                   A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
+                                   part_pq, bf.flags, tres, tol, it, col_tiles, row_tiles,
+                                   G.rows_per, G.mode, 0);
+            else
+                hipLaunchKernelGGL((k_cg_spmm<V, 8>), G.grid, dim3(CG_THREADS), 0, s, A.rowptr,
+                                   A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
+                                   part_pq, bf.flags, tres, tol, it, col_tiles, row_tiles,
+                                   G.rows_per, G.mode, 0);
             SIC_CHECK_LAUNCH();
             if (bf.prof)
                 r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
@@ -565,8 +585,8 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
         launched += chunk;
         if (launched >= max_iter) {
             // the last update's residual has no product after it to test it
-            hipLaunchKernelGGL(k_cg_spmm<V>, dim3(col_tiles, 1), dim3(CG_THREADS), 0, s,
-                               A.rowptr, A.col, A.val, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
+            hipLaunchKernelGGL((k_cg_spmm<V, 8>), dim3(col_tiles, 1), dim3(CG_THREADS), 0, s,
+                               A.rowptr, A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
                                part_pq, bf.flags, tres, tol, launched, col_tiles, row_tiles,
                                G.rows_per, 0, 1);
             SIC_CHECK_LAUNCH();
@@ -635,13 +655,14 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
     const size_t nk = (size_t)n * (size_t)std::max(k, 1);
     const int col_tiles = (std::max(k, 1) + 63) / 64;
     wk.dinv.reserve(n);
+    wk.vd.reserve((size_t)std::max<int64_t>(A.nnz, 1));
     wk.part.reserve((size_t)cg_row_tiles(n, k) * std::max(k, 1) * 3);
     wk.scal.reserve((size_t)4 * std::max(k, 1) + col_tiles);
     wk.flags.reserve((size_t)T_INTS * col_tiles);
     wk.hctl.reserve((size_t)T_INTS * col_tiles);
     wk.hres.reserve(col_tiles);
     const CsrView av{A.rowptr.p, A.col.p, A.val.p, A.n, A.nnz};
-    CGBufs bf{wk.dinv.p, wk.part.p, wk.scal.p, wk.flags.p, wk.hctl.p, wk.hres.p,
+    CGBufs bf{wk.dinv.p, wk.vd.p, wk.part.p, wk.scal.p, wk.flags.p, wk.hctl.p, wk.hres.p,
               &wk.predict[(slot & 3) * 2 + (low_precision ? 1 : 0)], true};
     if (low_precision) {
         wk.R32.reserve(nk);
@@ -694,9 +715,9 @@ unsigned char* scratch_address() {
 
 }  // namespace
 
-size_t cg_noalloc_bytes(int64_t n, int k) {
+size_t cg_noalloc_bytes(int64_t n, int64_t nnz, int k) {
     const int ct = (k + 63) / 64;
-    return align256(sizeof(double) * (size_t)n) +
+    return align256(sizeof(double) * (size_t)n) + align256(sizeof(double) * (size_t)nnz) +
            align256(sizeof(double) * (size_t)cg_row_tiles(n, k) * k * 3) +
            align256(sizeof(double) * ((size_t)4 * k + ct)) + align256(sizeof(int) * T_INTS * ct) +
            3 * align256(sizeof(double) * (size_t)n * k);
@@ -708,10 +729,10 @@ int cg_noalloc_max_k() { return NOALLOC_MAX_K; }
 CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const double* val,
                           int64_t n, int64_t nnz, const int32_t* d_cols, int k, double* W,
                           double tol, int max_iter, hipStream_t s) {
-    if (k > NOALLOC_MAX_K || cg_noalloc_bytes(n, k) > NOALLOC_SCRATCH_BYTES)
+    if (k > NOALLOC_MAX_K || cg_noalloc_bytes(n, nnz, k) > NOALLOC_SCRATCH_BYTES)
         throw SicError(SIC_ETOOBIG, "inverse columns without allocation: n x k = " +
                                         std::to_string(n) + " x " + std::to_string(k) +
-                                        " needs " + std::to_string(cg_noalloc_bytes(n, k)) +
+                                        " needs " + std::to_string(cg_noalloc_bytes(n, nnz, k)) +
                                         " bytes of scratch, the limit is " +
                                         std::to_string(NOALLOC_SCRATCH_BYTES) +
                                         " (and k <= " + std::to_string(NOALLOC_MAX_K) + ")");
@@ -724,6 +745,7 @@ CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const doubl
         return p;
     };
     double* dinv = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n));
+    double* vd = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nnz));
     double* part =
         reinterpret_cast<double*>(take(sizeof(double) * (size_t)cg_row_tiles(n, k) * k * 3));
     double* scal = reinterpret_cast<double*>(take(sizeof(double) * ((size_t)4 * k + ct)));
@@ -737,7 +759,7 @@ CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const doubl
     double hres[NOALLOC_MAX_TILES];
     int predicted = 0;
     const CsrView av{rowptr, col, val, n, nnz};
-    const CGBufs bf{dinv, part, scal, flags, hctl, hres, &predicted, false};
+    const CGBufs bf{dinv, vd, part, scal, flags, hctl, hres, &predicted, false};
     return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, R, P, Q, s);
 }
 

@@ -167,7 +167,7 @@ void launch_sddmm(const double* Xt, int64_t m, const int32_t* rows, const int32_
 
 // ---------------------------------------------------------------- k_cg.hip
 struct CGWork {
-    DevBuf<double> R, P, Q, dinv, part, scal;
+    DevBuf<double> R, P, Q, dinv, vd, part, scal;
     DevBuf<float> R32, P32, Q32;        // the float vectors of the reduced-precision CG
     DevBuf<int32_t> flags;
     HostBuf<int32_t> hctl;              // per-tile control words, read back at each check
@@ -199,7 +199,7 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
 CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const double* val,
                           int64_t n, int64_t nnz, const int32_t* d_cols, int k, double* W,
                           double tol, int max_iter, hipStream_t s);
-size_t cg_noalloc_bytes(int64_t n, int k);
+size_t cg_noalloc_bytes(int64_t n, int64_t nnz, int k);
 size_t cg_noalloc_capacity();
 int cg_noalloc_max_k();
 

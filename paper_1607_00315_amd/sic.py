@@ -128,7 +128,7 @@ SIGNATURES = {
                                                     ct.c_int, ct.c_double, ct.c_int,
                                                     ct.c_void_p, ct.c_void_p,
                                                     ct.POINTER(ct.c_int), _dp]),
-    "sic_step_inverse_columns_noalloc_limit": (ct.c_size_t, [ct.c_int64, ct.c_int]),
+    "sic_step_inverse_columns_noalloc_limit": (ct.c_size_t, [ct.c_int64, ct.c_int64, ct.c_int]),
     "sic_step_set_level": (ct.c_int, [_P, _i64p, ct.c_int64]),
     "sic_cluster_order": (ct.c_int, [ct.c_int64, _i64p, ct.c_int64, ct.c_int, _i32p]),
     "sic_step_block": (ct.c_int, [_P, ct.c_int64, ct.c_int, ct.c_int, ct.c_double, ct.c_double,
@@ -554,9 +554,10 @@ def inverse_columns_noalloc(rowptr, col, val, cols, W, tol=1e-12, max_iter=5000,
     return it.value, res.value
 
 
-def inverse_columns_noalloc_limit(n, k):
-    """Scratch bytes the no-allocation solve needs for n x k (0: does not fit)."""
-    return lib().sic_step_inverse_columns_noalloc_limit(n, k)
+def inverse_columns_noalloc_limit(n, nnz, k):
+    """Scratch bytes the no-allocation solve needs for n x k with nnz entries
+    (0: does not fit)."""
+    return lib().sic_step_inverse_columns_noalloc_limit(n, nnz, k)
 
 
 def step_cd(ctx: Context, wjj, b, cptr, cp, S, A, lam, max_sweeps=20, tol=1e-4):

@@ -38,7 +38,7 @@ def _case(sic, torch, ctx, name, cols, tol):
     d_rp, d_col, d_val = (torch.from_numpy(a).to(dev) for a in (rp, col, val))
     d_cols = torch.from_numpy(cols).to(dev)
     W = torch.full((n, cols.size), float("nan"), dtype=torch.float64, device=dev)
-    assert sic.inverse_columns_noalloc_limit(n, cols.size) > 0
+    assert sic.inverse_columns_noalloc_limit(n, col.size, cols.size) > 0
     it, res = sic.inverse_columns_noalloc(d_rp, d_col, d_val, d_cols, W, tol=tol, max_iter=2000)
     torch.cuda.synchronize()
     W = W.cpu().numpy()
@@ -67,7 +67,7 @@ def test_noalloc_refuses_too_large_a_solve():
     from paper_1607_00315_amd import sic
     announce("noalloc CG: a solve beyond the scratch array is refused with SIC_ETOOBIG")
     n, k = 200_000, 256
-    assert sic.inverse_columns_noalloc_limit(n, k) == 0
+    assert sic.inverse_columns_noalloc_limit(n, n, k) == 0
     dev = torch.device("cuda:0")
     rp = torch.arange(n + 1, dtype=torch.int64, device=dev)
     col = torch.arange(n, dtype=torch.int32, device=dev)

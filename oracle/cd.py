@@ -37,7 +37,7 @@ def _lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         f.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ip, dp, dp, ctypes.c_double,
-                      ctypes.c_int, ctypes.c_double, dp, dp, dp]
+                      ctypes.c_int, ctypes.c_double, dp, dp, dp, ctypes.c_int]
         f.restype = ctypes.c_int
         _handle = lib
     return _handle
@@ -48,10 +48,11 @@ def _p(a, t):
 
 
 def cd_sweeps(W: np.ndarray, ri, ci, S_vals, A_vals, lam: float, max_sweeps: int,
-              tol: float, D0=None):
+              tol: float, D0=None, verbose: bool = False):
     """Cyclic CD over coordinates (ri[t], ci[t]) (local indices into W).
 
     Returns (Delta per coordinate, sweeps run, last sweep's max |mu|).
+    verbose: a progress line per sweep on stderr.
     """
     W = np.ascontiguousarray(W, dtype=np.float64)
     nj = W.shape[0]
@@ -67,5 +68,5 @@ def cd_sweeps(W: np.ndarray, ri, ci, S_vals, A_vals, lam: float, max_sweeps: int
         nj, _p(W, ctypes.c_double), nc, _p(ri, ctypes.c_int), _p(ci, ctypes.c_int),
         _p(S_vals, ctypes.c_double), _p(A_vals, ctypes.c_double), float(lam),
         int(max_sweeps), float(tol), _p(D, ctypes.c_double), _p(U, ctypes.c_double),
-        ctypes.byref(last))
+        ctypes.byref(last), int(bool(verbose)))
     return D, sweeps, last.value

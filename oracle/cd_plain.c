@@ -20,6 +20,7 @@
  * a dense nj x nj matrix and updated by two row axpys per coordinate step.
  */
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -38,11 +39,12 @@ static double soft(double z, double t)
  * max_sweeps  sweep cap; tol: stop after a sweep with max|mu| <= tol*max|Delta|
  * D           in/out: per-coordinate Delta (read as the starting point)
  * U           workspace of nj*nj doubles
+ * verbose     nonzero: one progress line per sweep on stderr (no effect on the result)
  * returns the number of sweeps run; *last_max_mu gets the last sweep's max|mu|
  */
 int oracle_cd_sweeps(int nj, const double *W, int ncoord, const int *ri, const int *ci,
                      const double *S, const double *A, double lam, int max_sweeps,
-                     double tol, double *D, double *U, double *last_max_mu)
+                     double tol, double *D, double *U, double *last_max_mu, int verbose)
 {
     const size_t N = (size_t)nj;
     memset(U, 0, sizeof(double) * N * N);
@@ -82,6 +84,11 @@ int oracle_cd_sweeps(int nj, const double *W, int ncoord, const int *ri, const i
         double maxd = 0.0;
         for (int t = 0; t < ncoord; ++t)
             if (fabs(D[t]) > maxd) maxd = fabs(D[t]);
+        if (verbose) {
+            fprintf(stderr, "[oracle-cd] sweep %d of %d coordinates: max|mu| %.3e, max|Delta| %.3e\n",
+                    sweeps, ncoord, maxmu, maxd);
+            fflush(stderr);
+        }
         if (maxmu <= tol * maxd) break;
     }
     if (last_max_mu) *last_max_mu = maxmu;

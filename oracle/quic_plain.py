@@ -121,7 +121,7 @@ def solve(S: np.ndarray, lam: float, tol: float = 1e-10, max_iter: int = 200,
         ri, ci = np.nonzero(mask)
         inner_tol = max(1e-13, min(1e-3, kkt))
         D_vals, _, _ = cd_sweeps(W, ri, ci, S[ri, ci], A[ri, ci], lam,
-                                 max_sweeps=200, tol=inner_tol)
+                                 max_sweeps=200, tol=inner_tol, verbose=verbose)
         D = np.zeros_like(A)
         D[ri, ci] = D_vals
         D[ci, ri] = D_vals

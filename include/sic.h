@@ -73,6 +73,11 @@ extern "C" {
                                               of the graph of A's support and the last finest
                                               sweep's free pairs (sic_cluster_order); results
                                               come back in the caller's labels */
+#define SIC_FLAG_NO_WARM_CG (1ull << 6)    /* start every conjugate-gradient solve from zero.
+                                              By default, a problem whose n^2 doubles fit in
+                                              2 GiB keeps the inverse columns it has solved
+                                              (n^2 doubles of device memory) and starts each
+                                              solve from the latest ones */
 #define SIC_FLAG_CONTINUATION (1ull << 5)  /* continuation (the BCDcont schedule of Section 8):
                                               the first three cycles run at lambda_4 =
                                               (1 + lambda) / 2 and then two values linearly

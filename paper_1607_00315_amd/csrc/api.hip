@@ -261,7 +261,7 @@ int sic_prob_create(sic_ctx* ctx, const double* X, int64_t n, int64_t m, double 
         SIC_HIP(hipSetDevice(C.device));
         auto p = std::make_unique<sic_prob>();
         p->ctx = ctx;
-        sic::problem_init(C, p->P, X, SIC_X_F64, n, m, lambda);
+        sic::problem_init(C, p->P, X, SIC_X_F64, n, m, lambda, false);
         *out = p.release();
         return SIC_OK;
     });

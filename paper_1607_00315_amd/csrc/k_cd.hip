@@ -292,6 +292,7 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(
     if (tid == 0) {
         stats[0] = (double)sweeps;
         for (int i = 0; i < 4; ++i) stats[3 + i] = (double)tph[i];
+        stats[7] = 0.0;
     }
 }
 
@@ -325,12 +326,15 @@ __device__ inline void lds_barrier() {
 
 // HT[t * nc + k] = H[k][t] (column t of H stored contiguously), formed in
 // float64 and stored as HV (float64, or float for the reduced-precision cycles).
+// xf (may be null): nxf ints cleared for the multi-workgroup sweep that follows.
 template <typename HV>
 __global__ void k_cd_hess(int64_t nc, int jp, const int32_t* __restrict__ c_p,
                           const int32_t* __restrict__ c_ci, const double* __restrict__ WJJ,
-                          HV* __restrict__ HT) {
+                          HV* __restrict__ HT, int* __restrict__ xf, int nxf) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t t = blockIdx.y;
+    if (xf && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int e = threadIdx.x; e < nxf; e += blockDim.x) xf[e] = 0;
     if (k >= nc) return;
     const int pt = c_p[t], ct = c_ci[t];
     const int pk = c_p[k], ck = c_ci[k];
@@ -535,53 +539,100 @@ __global__ __launch_bounds__(CDH_THREADS) void k_cd_dense(
         stats[0] = (double)sweeps;
         for (int i = 0; i < 3; ++i) stats[3 + i] = (double)tph[i];
         stats[6] = 0.0;
+        stats[7] = 0.0;
     }
 }
 
 
-// ------------------------------------------------------------------------
-// Pipelined explicit-Hessian sweep (blocks whose z, Delta and four 64 x 64
-// tiles fit in LDS). Chunk intervals g = 0, 1, ... (chunk i = g mod C):
-//   wave 0     applies the previous chunk's steps to the rows of chunk i from
-//              the prefetched tile H[chunk i][chunk i-1], then runs the
-//              chain of chunk i on the tile H[chunk i][chunk i] and publishes
-//              its nonzero steps;
-//   waves 1-15 apply the previous chunk's steps to every row outside chunks
-//              i-1 and i (streaming those columns of H^T) and prefetch the
-//              two tiles of the next interval.
-// One barrier per chunk; tiles and step lists are double buffered. The rows
-// of chunk i receive every step before its chain: steps of chunk i-1 from
-// wave 0, older ones from the workers' earlier intervals.
-constexpr int CDP_THREADS = 1024;
-constexpr int CDP_WORKERS = CDP_THREADS - 64;
+// Staging of the multi-workgroup sweep below: 64 x 64 tiles of H and a chunk's
+// constants.
 constexpr int CDP_TILE = CDH_K * CDH_K;
 constexpr int CDP_CONST = 4 * CDH_K;   // a chunk's 1/a, A, S and W_rc, staged with its tiles
-constexpr int CDP_TPT = (2 * CDP_TILE + CDP_CONST + CDP_WORKERS - 1) / CDP_WORKERS;   // prefetch loads per worker
-// The step list is zero padded to a multiple of this, the column loads a worker
-// has in flight at once
-constexpr int CDP_PAD = 16;
 
-__device__ __forceinline__ double cd_soft(double y, double t) {
-    return y > t ? y - t : (y < -t ? y + t : 0.0);
+// ------------------------------------------------------------------------
+// The same sweep over several compute units. The coordinate chain is serial,
+// but applying a chunk's steps to the other coordinates' z is not, and one
+// workgroup can only stream H as fast as its compute unit draws from memory
+// (k_cd_dense above, about 50 GB/s). Here workgroup 0 runs the chain and helper
+// workgroups 1..nhelp apply the steps. Intervals g = 0, 1, ... visit the chunks
+// in order, interval g taking chunk g mod C (C chunks per sweep):
+//   helpers    helper h owns the z of chunks h, h + nhelp, ... For every
+//              published step list g' it adds H[own chunk][chunk g'] mu(g')
+//              to that z, and after list g' it publishes the z of the chunk
+//              due at interval g' + 3 (a snapshot of the steps of intervals
+//              <= g' = x - 3, for x = g' + 3);
+//   workgroup 0, interval g: wave 0 starts from snapshot(g), plus the steps
+//              of interval g-2 on chunk g (formed by waves 1-8 during interval
+//              g-1 from the tile H[chunk g][chunk g-2]), plus those of g-1
+//              (from the staged tile H[chunk g][chunk g-1]), runs the chain
+//              and writes its step list; waves 1-15 stage the next interval's
+//              tiles, form the g-1 contribution for chunk g+1, and wave 9
+//              fetches snapshot(g+1).
+// z_k is then sum_t H[k][t] Delta_t summed by interval, and the chain and its
+// visiting order are those of k_cd_dense.
+//
+// The lists, snapshots and their sequence flags pass through global memory as
+// device-scope relaxed atomics (they bypass the per-XCD L2 caches); a writer
+// waits for its data stores to complete before it stores the flag. Every wait
+// gives up after two seconds and raises an abort flag that ends all
+// workgroups; the host turns it into an error.
+constexpr int CDM_THREADS = 1024;
+constexpr int CDM_WAVES = CDM_THREADS / 64;
+constexpr int CDM_HELPERS = 16;      // most helper workgroups
+constexpr int CDM_OWN = 4;           // chunks per helper at most
+constexpr int CDM_MAXC = CDM_HELPERS * CDM_OWN;   // chunks at most (4096 coordinates)
+constexpr int CDM_RS = 128;          // step-list ring (any helper is fewer than C + 2 lists behind)
+constexpr int CDM_RZ = 8;            // snapshot ring
+constexpr int CDM_LAG = 3;           // snapshot(x) holds the steps of intervals <= x - 3
+constexpr int CDM_PW = 8;            // waves forming the interval-(g-1) part for chunk g+1
+constexpr int CDM_SNAPW = CDM_PW + 1;   // the wave fetching the snapshot
+// exchange buffer: int flags, one per 128-byte line, then the two rings (doubles)
+enum { XF_PUB = 0, XF_STATUS = 32, XF_SNAP = 64 };   // snapshot flag s at XF_SNAP + 32 s
+constexpr int CDM_FLAG_INTS = XF_SNAP + 32 * CDM_RZ;
+constexpr int64_t CDM_XSTEPS = CDM_FLAG_INTS / 2;
+constexpr int64_t CDM_XSNAP = CDM_XSTEPS + (int64_t)CDM_RS * CDH_K;
+constexpr int CDM_BIG = 1 << 30;     // published-list count meaning "stop"
+constexpr long long CDM_SPIN_TICKS = 200000000ll;   // two seconds of the 100 MHz clock
+static_assert(CDM_RS >= CDM_MAXC + CDM_LAG, "step ring shorter than the slowest helper's lag");
+static_assert(CDM_RZ >= CDM_LAG, "snapshot ring shorter than the lag");
+
+__device__ __forceinline__ int xld_i(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xst_i(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xld_d(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xst_d(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// this wave's earlier memory operations complete before its later ones issue
+__device__ __forceinline__ void x_drain() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <int ROWS, typename HV>   // worker rows per thread: ceil(nc / 960); H's storage type
-__global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
-    int64_t nc, const HV* __restrict__ HT, const double* __restrict__ c_S,
-    const double* __restrict__ c_A, const double* __restrict__ c_inva,
-    const double* __restrict__ c_wtc, double lam, int max_sweeps, double tol,
-    double* __restrict__ delta, double* __restrict__ stats) {
-    extern __shared__ double sm[];
-    double* zs = sm;                          // [nc]
-    double* ds = zs + nc;                     // [nc]
-    double* Dt = ds + nc;                     // [2][64 x 64] H[chunk i][chunk i], [t][k]
-    double* St = Dt + 2 * CDP_TILE;           // [2][64 x 64] H[chunk i][chunk i-1], [t][k]
-    double* mud = St + 2 * CDP_TILE;          // [2][64] steps of the chunk, dense (0 when none)
-    double* nzm = mud + 2 * CDH_K;            // [2][64] nonzero steps (zero padded)
-    double* cst = nzm + 2 * CDH_K;            // [2][4][64] chunk i's 1/a, A, S, W_rc
-    int* nzl = (int*)(cst + 2 * CDP_CONST);   // [2][64] their chunk positions
+template <typename HV>
+__device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* __restrict__ c_S,
+                          const double* __restrict__ c_A, const double* __restrict__ c_inva,
+                          const double* __restrict__ c_wtc, double lam, int max_sweeps, double tol,
+                          double* __restrict__ delta, double* __restrict__ stats,
+                          double* __restrict__ xb, double* sm) {
+    double* ds = sm;                            // [nc]
+    double* Dt = ds + nc;                       // [2][64 x 64] H[chunk g][chunk g], [t][k]
+    double* St = Dt + 2 * CDP_TILE;             // [2][64 x 64] H[chunk g][chunk g-1], [t][k]
+    double* mud = St + 2 * CDP_TILE;            // [2][64] steps of the interval (0 past K)
+    double* cst = mud + 2 * CDH_K;              // [2][4][64] the chunk's 1/a, A, S, W_rc
+    double* zp = cst + 2 * CDP_CONST;           // [2][CDM_PW + 1][64] parts of the chunk's z
+    int* xf = reinterpret_cast<int*>(xb);
+    double* xsteps = xb + CDM_XSTEPS;
+    double* xsnap = xb + CDM_XSNAP;
     __shared__ int s_nnz[2];
-    __shared__ int s_stop;
+    __shared__ int s_stop, s_abort;
+    __shared__ long long s_tph[4];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -590,17 +641,16 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
         const int64_t r = nc - (int64_t)c * CDH_K;
         return (int)(r < CDH_K ? r : CDH_K);
     };
-    // worker: load the tiles of chunk ci (and its predecessor cp) and the
-    // constants of chunk ci into registers
-    double treg[CDP_TPT];
+    // waves 1-15: the tiles of chunk ci (and its predecessor cp) and the
+    // constants of chunk ci, into registers, then into LDS buffer b
+    constexpr int TPT = (2 * CDP_TILE + CDP_CONST + (CDM_THREADS - 64) - 1) / (CDM_THREADS - 64);
+    double treg[TPT];
     auto load_tiles = [&](int ci, int cp) {
         const int64_t ki = (int64_t)ci * CDH_K, kp = (int64_t)cp * CDH_K;
         const int Ki = klen(ci), Kp = klen(cp);
 #pragma unroll
-        for (int r = 0; r < CDP_TPT; ++r) {
-            // unconditional loads: a tile entry (element 0 of H past the tiles,
-            // discarded), and in the slot that reaches past the tiles a constant
-            const int e = (tid - 64) + CDP_WORKERS * r;
+        for (int r = 0; r < TPT; ++r) {
+            const int e = (tid - 64) + (CDM_THREADS - 64) * r;
             const bool is_tile = e < 2 * CDP_TILE;
             const int which = e / CDP_TILE, f = e % CDP_TILE;
             const int t = f / CDH_K, k = f % CDH_K;
@@ -608,20 +658,16 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
             const int64_t col = (dtile ? ki : kp) + t;
             const bool ok = is_tile && k < Ki && (dtile ? t < Ki : t < Kp);
             const double tv = load_or(HT, col * nc + ki + k, ok, 0.0);
-            if (CDP_WORKERS * (r + 1) > 2 * CDP_TILE) {
-                const int g = e - 2 * CDP_TILE, gw = g / CDH_K, gk = g % CDH_K;
-                const double* src = gw == 0 ? c_inva : (gw == 1 ? c_A : (gw == 2 ? c_S : c_wtc));
-                const double cv = load_or(src, ki + gk, !is_tile && g < CDP_CONST && gk < Ki, 0.0);
-                treg[r] = is_tile ? tv : cv;
-            } else {
-                treg[r] = tv;
-            }
+            const int g = e - 2 * CDP_TILE, gw = g / CDH_K, gk = g % CDH_K;
+            const double* src = gw == 0 ? c_inva : (gw == 1 ? c_A : (gw == 2 ? c_S : c_wtc));
+            const double cv = load_or(src, ki + gk, !is_tile && g < CDP_CONST && gk < Ki, 0.0);
+            treg[r] = is_tile ? tv : cv;
         }
     };
     auto store_tiles = [&](int b) {
 #pragma unroll
-        for (int r = 0; r < CDP_TPT; ++r) {
-            const int e = (tid - 64) + CDP_WORKERS * r;
+        for (int r = 0; r < TPT; ++r) {
+            const int e = (tid - 64) + (CDM_THREADS - 64) * r;
             if (e < 2 * CDP_TILE) {
                 const int which = e / CDP_TILE, f = e % CDP_TILE;
                 (which == 0 ? Dt : St)[b * CDP_TILE + f] = treg[r];
@@ -631,54 +677,52 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
         }
     };
 
-    for (int64_t k = tid; k < nc; k += CDP_THREADS) {
-        zs[k] = 0.0;
-        ds[k] = 0.0;
-    }
+    for (int64_t k = tid; k < nc; k += CDM_THREADS) ds[k] = 0.0;
+    for (int e = tid; e < 2 * (CDM_PW + 1) * CDH_K; e += CDM_THREADS) zp[e] = 0.0;
     if (wave > 0) {
         load_tiles(0, C - 1);
         store_tiles(0);
     }
-    // the chain is the critical path: let its wave win issue arbitration on its SIMD
-    if (wave == 0) __builtin_amdgcn_s_setprio(3);
+    if (wave == 0) __builtin_amdgcn_s_setprio(3);   // the chain is the critical path
     if (tid == 0) {
-        s_nnz[0] = 0;
-        s_nnz[1] = 0;
+        s_nnz[0] = s_nnz[1] = 0;
         s_stop = 0;
+        s_abort = 0;
+        s_tph[0] = s_tph[1] = s_tph[2] = 0;
+        s_tph[3] = wall_clock64();
     }
     lds_barrier();
 
     int sweeps = 0;
     double maxmu = 0.0;   // wave 0
-    // thread 0's phase clocks (step application, chain, barrier wait), in LDS:
-    // registers are the workers' load depth
-    __shared__ long long s_tph[4];
-    if (tid == 0) {
-        s_tph[0] = s_tph[1] = s_tph[2] = 0;
-        s_tph[3] = wall_clock64();
-    }
     int64_t g = 0;
     bool done = false;
     for (int sweep = 0; sweep < max_sweeps && !done; ++sweep) {
         for (int i = 0; i < C; ++i, ++g) {
-            const int b = (int)(g & 1), pb = 1 - b;   // this interval's buffers / previous steps
-            const int cp = (i + C - 1) % C;            // previous chunk
-            const int64_t k0 = (int64_t)i * CDH_K, kp0 = (int64_t)cp * CDH_K;
+            const int b = (int)(g & 1), pb = 1 - b;
             const int K = klen(i);
-            const bool have_prev = g > 0 && C > 1;
             if (wave == 0) {
+                // the list of interval g-1 was stored at its end: publish it
+                if (g > 0 && lane == 0) {
+                    x_drain();
+                    xst_i(xf + XF_PUB, (int)g);
+                }
                 if (i == 0) maxmu = 0.0;
                 const bool on = lane < K;
-                const int kl = on ? (int)k0 + lane : (int)k0;
-                double z = on ? zs[kl] : 0.0;
-                // steps of the previous chunk onto the rows of this one
-                if (have_prev && s_nnz[pb] > 0) {
+                const int kl = on ? i * CDH_K + lane : i * CDH_K;
+                // z: snapshot, then the parts of interval g-2 in wave order
+                const double* zb = zp + b * (CDM_PW + 1) * CDH_K;
+                double z = zb[CDM_PW * CDH_K + lane];
+#pragma unroll
+                for (int w = 0; w < CDM_PW; ++w) z += zb[w * CDH_K + lane];
+                // steps of interval g-1 onto the rows of this chunk
+                if (g > 0 && s_nnz[pb] > 0) {
                     const double* st = St + b * CDP_TILE;
                     const double* pm = mud + pb * CDH_K;
                     double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
                     for (int t = 0; t < CDH_K; t += 8) {
-                        double sv[8], mv[8];   // all eight reads in flight before the fmas
+                        double sv[8], mv[8];
 #pragma unroll
                         for (int u = 0; u < 8; ++u) {
                             sv[u] = st[(t + u) * CDH_K + lane];
@@ -687,10 +731,10 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
 #pragma unroll
                         for (int u = 0; u < 8; ++u) a[u & 3] += sv[u] * mv[u];
                     }
-                    z += on ? (a[0] + a[1]) + (a[2] + a[3]) : 0.0;
+                    z += (a[0] + a[1]) + (a[2] + a[3]);
                 }
+                z = on ? z : 0.0;
                 if (tid == 0) { const long long now = wall_clock64(); s_tph[0] += now - s_tph[3]; s_tph[3] = now; }
-                // chain constants of this chunk (staged with its tiles; zero past K)
                 const double* cb = cst + b * CDP_CONST;
                 const double ia = cb[lane];
                 const double d0 = on ? ds[kl] : 0.0;
@@ -703,10 +747,9 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                 // mu = soft(p - z/a, lam/a) - x is the median of a, -x and b
                 // (a <= b). Every lane evaluates it for its own coordinate at the
                 // current z; lane t's value is step t: broadcast (two readlanes),
-                // applied to every z and kept in lane t. Ten instructions a step,
-                // five of them dependent.
+                // applied to every z and kept in lane t.
                 const double qlo = pv - xl - lam * ia, qhi = pv - xl + lam * ia, nx = -xl;
-                int mlo = 0, mhi = 0;   // the steps, lane k holding step k (bits)
+                int mlo = 0, mhi = 0;
                 double hN[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) hN[u] = dt[u * CDH_K + lane];
@@ -714,7 +757,7 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                     double hC[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) hC[u] = hN[u];
-                    const int tn = tt + 4 < CDH_K ? tt + 4 : CDH_K - 4;   // in range; unused past K4
+                    const int tn = tt + 4 < CDH_K ? tt + 4 : CDH_K - 4;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) hN[u] = dt[(tn + u) * CDH_K + lane];
 #pragma unroll
@@ -731,28 +774,14 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                         mhi = lane == t ? shi : mhi;
                     }
                 }
-                const double mul = __longlong_as_double(((long long)mhi << 32) | (unsigned int)mlo);
+                double mul = __longlong_as_double(((long long)mhi << 32) | (unsigned int)mlo);
+                mul = on ? mul : 0.0;
+                // the list goes out first; it is published at the next interval's start
+                xst_d(xsteps + (g % CDM_RS) * CDH_K + lane, mul);
                 maxmu = fmax(maxmu, wave_max(fabs(mul)));
-                if (on) {
-                    zs[kl] = z;
-                    ds[kl] = d0 + mul;
-                }
-                mud[b * CDH_K + lane] = mul;   // lanes >= K hold 0
-                const bool nzs = on && mul != 0.0;
-                const unsigned long long bits = __ballot(nzs);
-                const int nnz = __popcll(bits);
-                double* om = nzm + b * CDH_K;
-                int* ol = nzl + b * CDH_K;
-                if (nzs) {
-                    const int pos = __popcll(bits & ((1ull << lane) - 1ull));
-                    ol[pos] = lane;
-                    om[pos] = mul;
-                }
-                const int npad = (nnz + CDP_PAD - 1) / CDP_PAD * CDP_PAD;
-                if (lane >= nnz && lane < npad) {
-                    ol[lane] = 0;
-                    om[lane] = 0.0;
-                }
+                if (on) ds[kl] = d0 + mul;
+                mud[b * CDH_K + lane] = mul;
+                const int nnz = __popcll(__ballot(mul != 0.0));
                 if (lane == 0) s_nnz[b] = nnz;
                 if (i == C - 1) {
                     // stopping rule of the sweep: max|mu| <= tol * max|Delta|
@@ -767,61 +796,60 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
                 }
                 if (tid == 0) { const long long now = wall_clock64(); s_tph[1] += now - s_tph[3]; s_tph[3] = now; }
             } else {
-                // next interval's tiles and constants (chunk i+1 and its predecessor
-                // i), issued first so that their latency hides behind the column
-                // stream (with two float64 rows per thread the registers do not
-                // allow it: then they follow the stream and hide behind the chain)
-                constexpr bool early = ROWS == 1 || sizeof(HV) < sizeof(double);
-                if (early) load_tiles((i + 1) % C, i);
-                // steps of the previous chunk onto every row outside chunks cp and i
-                if (have_prev && C > 2) {
-                    const int np = (s_nnz[pb] + CDP_PAD - 1) / CDP_PAD * CDP_PAD;
-                    const double* pm = nzm + pb * CDH_K;
-                    const int* pl = nzl + pb * CDH_K;
-                    const HV* hcol = HT + kp0 * nc;
-                    double acc[ROWS];
-                    bool rv[ROWS];
-                    int rk[ROWS];
-                    // worker w takes the w-th row outside the (64-aligned) chunks cp and i
-                    const int64_t ea = kp0 < k0 ? kp0 : k0, eb = kp0 < k0 ? k0 : kp0;
+                const int cn = (i + 1) % C;                  // the next interval's chunk
+                load_tiles(cn, i);
+                double* zn = zp + pb * (CDM_PW + 1) * CDH_K;
+                if (wave <= CDM_PW) {
+                    // steps of interval g-1 on the rows of chunk cn: tile rows t of
+                    // this wave's eighth of chunk g-1
+                    double acc = 0.0;
+                    if (g > 0 && s_nnz[b ^ 1] > 0) {
+                        const int cq = (int)((g - 1) % C);
+                        const int Kq = klen(cq), Kn = klen(cn);
+                        const int t0 = (wave - 1) * (CDH_K / CDM_PW);
+                        const double* pm = mud + pb * CDH_K;
+                        double hv[CDH_K / CDM_PW];
 #pragma unroll
-                    for (int r = 0; r < ROWS; ++r) {
-                        int64_t k = (tid - 64) + (int64_t)CDP_WORKERS * r;
-                        if (k >= ea) k += CDH_K;
-                        if (k >= eb) k += CDH_K;
-                        rv[r] = k < nc;
-                        rk[r] = rv[r] ? (int)k : 0;
-                        acc[r] = 0.0;
-                    }
-                    // the column index is the same in every lane: a scalar base address
-                    // plus a 32-bit row offset per load
-                    constexpr int BATCH = CDP_PAD / ROWS;
-#pragma unroll 1
-                    for (int q0 = 0; q0 < np; q0 += BATCH) {
-                        HV hv[ROWS][BATCH];
-#pragma unroll
-                        for (int q = 0; q < BATCH; ++q) {
-                            const int t = __builtin_amdgcn_readfirstlane(pl[q0 + q]);
-                            const HV* colp = hcol + (int64_t)t * nc;
-#pragma unroll
-                            for (int r = 0; r < ROWS; ++r) hv[r][q] = colp[rk[r]];
+                        for (int u = 0; u < CDH_K / CDM_PW; ++u) {
+                            const int t = t0 + u;
+                            hv[u] = load_or(HT, ((int64_t)cq * CDH_K + t) * nc + (int64_t)cn * CDH_K + lane,
+                                            t < Kq && lane < Kn, 0.0);
                         }
 #pragma unroll
-                        for (int q = 0; q < BATCH; ++q) {
-                            const double m = pm[q0 + q];
-#pragma unroll
-                            for (int r = 0; r < ROWS; ++r) acc[r] += (double)hv[r][q] * m;
-                        }
+                        for (int u = 0; u < CDH_K / CDM_PW; ++u) acc += hv[u] * pm[t0 + u];
                     }
-#pragma unroll
-                    for (int r = 0; r < ROWS; ++r)
-                        if (rv[r]) zs[rk[r]] += acc[r];
+                    zn[(wave - 1) * CDH_K + lane] = acc;
+                } else if (wave == CDM_SNAPW) {
+                    // snapshot(g+1) from the helper that owns chunk cn
+                    double v = 0.0;
+                    if (g + 1 >= CDM_LAG) {
+                        const int slot = (int)((g + 1) % CDM_RZ);
+                        const long long t0 = wall_clock64();
+                        int polls = 0;
+                        bool ok = true;
+                        while (xld_i(xf + XF_SNAP + 32 * slot) != (int)(g + 1)) {
+                            if ((++polls & 15) == 0) {
+                                if (xld_i(xf + XF_STATUS) == 2 || wall_clock64() - t0 > CDM_SPIN_TICKS) {
+                                    ok = false;
+                                    break;
+                                }
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        if (ok) v = xld_d(xsnap + (int64_t)slot * CDH_K + lane);
+                        else if (lane == 0) s_abort = 1;
+                    }
+                    zn[CDM_PW * CDH_K + lane] = v;
                 }
-                if (!early) load_tiles((i + 1) % C, i);
                 store_tiles(pb);
             }
             lds_barrier();
             if (tid == 0) { const long long now = wall_clock64(); s_tph[2] += now - s_tph[3]; s_tph[3] = now; }
+            if (s_abort) {
+                done = true;
+                break;
+            }
             if (i == C - 1) {
                 ++sweeps;
                 if (s_stop) {
@@ -831,12 +859,139 @@ __global__ __launch_bounds__(CDP_THREADS) void k_cd_pipe(
             }
         }
     }
-    for (int64_t k = tid; k < nc; k += CDP_THREADS) delta[k] = ds[k];
+    // the helpers stop at the next list they wait for
+    if (tid == 0) {
+        x_drain();
+        xst_i(xf + XF_STATUS, s_abort ? 2 : 1);
+        x_drain();
+        xst_i(xf + XF_PUB, CDM_BIG);
+    }
+    for (int64_t k = tid; k < nc; k += CDM_THREADS) delta[k] = ds[k];
     if (tid == 0) {
         stats[0] = (double)sweeps;
         for (int i = 0; i < 3; ++i) stats[3 + i] = (double)s_tph[i];
         stats[6] = 0.0;
+        stats[7] = s_abort ? 1.0 : 0.0;
     }
+}
+
+template <typename HV>
+__device__ void cdm_helper(int64_t nc, const HV* __restrict__ HT, int nhelp,
+                           double* __restrict__ xb, double* sm) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = (int)blockIdx.x - 1;
+    const int C = (int)((nc + CDH_K - 1) / CDH_K);
+    const int nown = (C - h + nhelp - 1) / nhelp;   // chunks h, h + nhelp, ...
+    double* part = sm;                               // [2][CDM_OWN][16][64]
+    double* mus = part + 2 * CDM_OWN * CDM_WAVES * CDH_K;   // [2][64]
+    int* xf = reinterpret_cast<int*>(xb);
+    const double* xsteps = xb + CDM_XSTEPS;
+    double* xsnap = xb + CDM_XSNAP;
+    __shared__ int s_exit;
+    auto klen = [&](int c) {
+        const int64_t r = nc - (int64_t)c * CDH_K;
+        return (int)(r < CDH_K ? r : CDH_K);
+    };
+    // this thread's tile entries of list gg: rows t = wave + 16 r of chunk
+    // gg mod C, column `lane` of each owned chunk
+    double tcur[CDM_OWN][4], tnext[CDM_OWN][4];
+    auto load = [&](int64_t gg, double (&tv)[CDM_OWN][4]) {
+        const int c = (int)(gg % C);
+        const int Kc = klen(c);
+#pragma unroll
+        for (int o = 0; o < CDM_OWN; ++o) {
+            const int j = h + o * nhelp;
+            const bool oj = o < nown;
+            const int Kj = oj ? klen(j) : 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = wave + CDM_WAVES * r;
+                tv[o][r] = load_or(HT, ((int64_t)c * CDH_K + t) * nc + (int64_t)j * CDH_K + lane,
+                                   oj && t < Kc && lane < Kj, 0.0);
+            }
+        }
+    };
+    double zown[CDM_OWN];   // wave 0: z of the owned chunks, lane k = row k
+#pragma unroll
+    for (int o = 0; o < CDM_OWN; ++o) zown[o] = 0.0;
+    if (tid == 0) s_exit = 0;
+    load(0, tcur);
+    for (int64_t gg = 0;; ++gg) {
+        const int q = (int)(gg & 1);
+        if (wave == 0) {
+            // wait for list gg, then fetch it
+            const long long t0 = wall_clock64();
+            int polls = 0, pub;
+            while ((pub = xld_i(xf + XF_PUB)) <= (int)gg) {
+                if ((++polls & 15) == 0 && wall_clock64() - t0 > CDM_SPIN_TICKS) {
+                    pub = -1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (pub < 0 || pub >= CDM_BIG) {
+                if (pub < 0 && lane == 0) xst_i(xf + XF_STATUS, 2);
+                if (lane == 0) s_exit = 1;
+            } else {
+                mus[q * CDH_K + lane] = xld_d(xsteps + (gg % CDM_RS) * CDH_K + lane);
+            }
+        }
+        lds_barrier();
+        if (s_exit) break;
+        load(gg + 1, tnext);
+        double m[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m[r] = mus[q * CDH_K + wave + CDM_WAVES * r];
+#pragma unroll
+        for (int o = 0; o < CDM_OWN; ++o) {
+            if (o < nown) {
+                const double a = (tcur[o][0] * m[0] + tcur[o][1] * m[1]) +
+                                 (tcur[o][2] * m[2] + tcur[o][3] * m[3]);
+                part[((q * CDM_OWN + o) * CDM_WAVES + wave) * CDH_K + lane] = a;
+            }
+        }
+        lds_barrier();
+        if (wave == 0) {
+            // the owned chunk due at interval gg + 3 gets its snapshot
+            const int due = (int)((gg + CDM_LAG) % C);
+#pragma unroll
+            for (int o = 0; o < CDM_OWN; ++o) {
+                if (o < nown) {
+                    const double* pp = part + (q * CDM_OWN + o) * CDM_WAVES * CDH_K;
+                    double s = 0.0;
+#pragma unroll
+                    for (int w = 0; w < CDM_WAVES; ++w) s += pp[w * CDH_K + lane];
+                    zown[o] += s;
+                    if (h + o * nhelp == due) {
+                        const int slot = (int)((gg + CDM_LAG) % CDM_RZ);
+                        xst_d(xsnap + (int64_t)slot * CDH_K + lane, zown[o]);
+                        x_drain();
+                        if (lane == 0) xst_i(xf + XF_SNAP + 32 * slot, (int)(gg + CDM_LAG));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < CDM_OWN; ++o)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tcur[o][r] = tnext[o][r];
+    }
+}
+
+template <typename HV>
+__global__ __launch_bounds__(CDM_THREADS) void k_cd_multi(
+    int64_t nc, const HV* __restrict__ HT, const double* __restrict__ c_S,
+    const double* __restrict__ c_A, const double* __restrict__ c_inva,
+    const double* __restrict__ c_wtc, double lam, int max_sweeps, double tol,
+    double* __restrict__ delta, double* __restrict__ stats, double* __restrict__ xb, int nhelp) {
+    extern __shared__ double sm[];
+    if (blockIdx.x == 0)
+        cdm_chain<HV>(nc, HT, c_S, c_A, c_inva, c_wtc, lam, max_sweeps, tol, delta, stats, xb, sm);
+    else
+        cdm_helper<HV>(nc, HT, nhelp, xb, sm);
 }
 
 }  // namespace
@@ -893,10 +1048,14 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
 
 int64_t cd_hessian_limit() { return (int64_t)CDH_RMAX * CDH_THREADS; }
 
-size_t cd_pipe_lds_bytes(int64_t ncoord) {
-    return sizeof(double) * ((size_t)2 * ncoord + 4 * CDP_TILE + 4 * CDH_K + 2 * CDP_CONST) +
-           sizeof(int) * 2 * CDH_K;
+size_t cd_multi_lds_bytes(int64_t ncoord) {
+    const size_t chain = sizeof(double) * ((size_t)ncoord + 4 * CDP_TILE + 2 * CDH_K + 2 * CDP_CONST +
+                                           2 * (CDM_PW + 1) * CDH_K);
+    const size_t helper = sizeof(double) * ((size_t)2 * CDM_OWN * CDM_WAVES * CDH_K + 2 * CDH_K);
+    return std::max(chain, helper);
 }
+
+size_t cd_exchange_doubles() { return (size_t)CDM_XSNAP + (size_t)CDM_RZ * CDH_K; }
 
 size_t cd_hessian_lds_bytes(int64_t ncoord) {
     return sizeof(double) * ((size_t)2 * ncoord + CDH_K * CDH_K + CDH_K) + sizeof(int) * CDH_K;
@@ -905,26 +1064,28 @@ size_t cd_hessian_lds_bytes(int64_t ncoord) {
 int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
                           const double* WJJ, const double* c_S, const double* c_A,
                           const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
-                          double tol, double* HT, double* delta, double* stats, hipStream_t s,
-                          bool low) {
+                          double tol, double* HT, double* delta, double* stats, double* xbuf,
+                          hipStream_t s, bool low) {
     if (ncoord <= 0) return -1;
     const size_t lds = cd_hessian_lds_bytes(ncoord);
     if (ncoord > cd_hessian_limit() || lds > CD_MAX_LDS_BYTES)
         throw SicError(SIC_EINTERNAL, "coordinate count too large for the explicit-Hessian sweep");
-    const size_t lds_pipe = cd_pipe_lds_bytes(ncoord);
-    // rows the workers cover: all but two chunks (all but one or none for C <= 2)
-    const int prow = (int)((std::max<int64_t>(ncoord - 2 * CDH_K, 1) + CDP_WORKERS - 1) / CDP_WORKERS);
-    const bool pipe = lds_pipe <= CD_MAX_LDS_BYTES && prow <= 2;
-    // float storage of H (the pipelined sweep only): half the bytes the sweep streams
-    const bool hf = low && pipe;
+    const int C = (int)((ncoord + CDH_K - 1) / CDH_K);
+    const size_t lds_multi = cd_multi_lds_bytes(ncoord);
+    const bool multi = xbuf && C <= CDM_MAXC && lds_multi <= CD_MAX_LDS_BYTES;
+    // float storage of H (the multi-workgroup sweep only): half the bytes the sweep streams
+    const bool hf = low && multi;
     const double hsz = hf ? 4.0 : 8.0;
     float* HTf = reinterpret_cast<float*>(HT);
+    int* xf = multi ? reinterpret_cast<int*>(xbuf) : nullptr;
     const dim3 hgrid((unsigned)((ncoord + 255) / 256), (unsigned)ncoord);
     prof_begin(KK_CD_HESS, s);
     if (hf)
-        hipLaunchKernelGGL(k_cd_hess<float>, hgrid, dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HTf);
+        hipLaunchKernelGGL(k_cd_hess<float>, hgrid, dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HTf,
+                           xf, CDM_FLAG_INTS);
     else
-        hipLaunchKernelGGL(k_cd_hess<double>, hgrid, dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HT);
+        hipLaunchKernelGGL(k_cd_hess<double>, hgrid, dim3(256), 0, s, ncoord, jp, c_p, c_ci, WJJ, HT,
+                           xf, CDM_FLAG_INTS);
     SIC_CHECK_LAUNCH();
     // H written once; 4 gathers of W per entry (from the L2-resident W on J')
     prof_end(KK_CD_HESS, s, hsz * (double)ncoord * ncoord, 3.0 * (double)ncoord * ncoord);
@@ -936,21 +1097,17 @@ int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int3
                            c_wtc, lam, max_sweeps, tol, delta, stats);
         SIC_CHECK_LAUNCH();
     };
-    auto launch_pipe = [&](auto kern, auto* H) {
+    auto launch_multi = [&](auto kern, auto* H) {
         allow_dynamic_lds((const void*)kern);
+        const int nhelp = std::min(C, CDM_HELPERS);
         prof_begin(KK_CD, s);
-        hipLaunchKernelGGL(kern, dim3(1), dim3(CDP_THREADS), lds_pipe, s, ncoord, H, c_S, c_A,
-                           c_inva, c_wtc, lam, max_sweeps, tol, delta, stats);
+        hipLaunchKernelGGL(kern, dim3(1 + nhelp), dim3(CDM_THREADS), lds_multi, s, ncoord, H, c_S,
+                           c_A, c_inva, c_wtc, lam, max_sweeps, tol, delta, stats, xbuf, nhelp);
         SIC_CHECK_LAUNCH();
     };
-    if (pipe) {
-        if (hf) {
-            if (prow == 1) launch_pipe(k_cd_pipe<1, float>, (const float*)HTf);
-            else launch_pipe(k_cd_pipe<2, float>, (const float*)HTf);
-        } else {
-            if (prow == 1) launch_pipe(k_cd_pipe<1, double>, (const double*)HT);
-            else launch_pipe(k_cd_pipe<2, double>, (const double*)HT);
-        }
+    if (multi) {
+        if (hf) launch_multi(k_cd_multi<float>, (const float*)HTf);
+        else launch_multi(k_cd_multi<double>, (const double*)HT);
     } else {
         switch (rows) {
             case 1: launch(k_cd_dense<1>); break;

@@ -95,6 +95,72 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// Warm start from the store of inverse columns: x0[:, j] = Ws[cols[j], :]
+// (row c of the store holds column c of A^{-1}, which is symmetric) when the
+// store holds column cols[j], else 0; p = q = 0. One 64 x 64 tile per
+// workgroup, transposed through LDS so both sides are read and written in
+// contiguous runs.
+template <typename V>
+__global__ __launch_bounds__(256) void k_cg_warm(int64_t n, int k, const int32_t* __restrict__ cols,
+                                                 const double* __restrict__ Ws,
+                                                 const unsigned char* __restrict__ valid,
+                                                 double* __restrict__ W, V* __restrict__ P,
+                                                 V* __restrict__ Q) {
+    __shared__ double t[64][65];
+    const int64_t i0 = (int64_t)blockIdx.y * 64;
+    const int j0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4 threads
+    for (int jr = ty; jr < 64; jr += 4) {
+        const int j = j0 + jr;
+        const int64_t c = j < k ? cols[j] : -1;
+        const bool ok = c >= 0 && c < n && valid[c] && i0 + tx < n;
+        t[jr][tx] = ok ? Ws[c * n + i0 + tx] : 0.0;
+    }
+    __syncthreads();
+    for (int ir = ty; ir < 64; ir += 4) {
+        const int64_t i = i0 + ir;
+        const int j = j0 + tx;
+        if (i < n && j < k) {
+            const int64_t o = i * k + j;
+            W[o] = t[tx][ir];
+            P[o] = (V)0.0;
+            Q[o] = (V)0.0;
+        }
+    }
+}
+
+// The converged columns back into the store: Ws[cols[j], :] = x[:, j].
+__global__ __launch_bounds__(256) void k_cg_store(int64_t n, int k, const int32_t* __restrict__ cols,
+                                                  const double* __restrict__ W,
+                                                  double* __restrict__ Ws,
+                                                  unsigned char* __restrict__ valid) {
+    __shared__ double t[64][65];
+    const int64_t i0 = (int64_t)blockIdx.y * 64;
+    const int j0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int ir = ty; ir < 64; ir += 4) {
+        const int64_t i = i0 + ir;
+        const int j = j0 + tx;
+        t[ir][tx] = (i < n && j < k) ? W[i * k + j] : 0.0;
+    }
+    __syncthreads();
+    for (int jr = ty; jr < 64; jr += 4) {
+        const int j = j0 + jr;
+        if (j >= k) continue;
+        const int64_t c = cols[j];
+        if (c < 0 || c >= n) continue;
+        if (i0 + tx < n) Ws[c * n + i0 + tx] = t[tx][jr];
+        if (blockIdx.y == 0 && tx == 0) valid[c] = 1;
+    }
+}
+
+// rz of the step before a warm start: 1 (any positive value), so that the
+// first product's beta multiplies p = q = 0.
+__global__ void k_cg_warm_scal(int k, double* __restrict__ scal) {
+    for (int j = threadIdx.x + blockIdx.x * blockDim.x; j < k; j += blockDim.x * gridDim.x)
+        scal[j * 4 + S_RZ0] = 1.0;
+}
+
 // The preconditioned residual z = D^{-1} r of one entry, rounded to the
 // vector type (the value a stored z would hold). It is formed wherever it is
 // read instead of being stored (one n x k array less written and read per
@@ -500,7 +566,8 @@ int cg_row_tiles(int64_t n, int k) { return cg_geom(n, k).gy; }
 
 template <typename V>
 CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W, double tol,
-                       int max_iter, const CGBufs& bf, V* R, V* P, V* Q, hipStream_t s) {
+                       int max_iter, const CGBufs& bf, V* R, V* P, V* Q, hipStream_t s,
+                       const WarmStore* ws = nullptr) {
     constexpr bool LOW = sizeof(V) < sizeof(double);
     CGResult res;
     const int64_t n = A.n;
@@ -525,10 +592,27 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
     hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, s,
                        n, k, col_tiles, d_cols, bf.dinv, W, R, bf.scal, bf.flags, tres);
     SIC_CHECK_LAUNCH();
+    // warm start: x0 from the store, r0 = e - A x0 exactly, and the iterations
+    // begin at 1 with p = q = 0 (the first product's beta then acts on zeros)
+    int start = 0;
+    if (ws) {
+        const dim3 tg((unsigned)((k + 63) / 64), (unsigned)((n + 63) / 64));
+        hipLaunchKernelGGL(k_cg_warm<V>, tg, dim3(256), 0, s, n, k, d_cols, ws->W, ws->valid, W, P,
+                           Q);
+        SIC_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_cg_warm_scal, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, k,
+                           bf.scal);
+        SIC_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_cg_true_residual<V>, G.grid, dim3(CG_THREADS), 0, s, A.rowptr, A.col,
+                           A.val, n, k, d_cols, bf.dinv, W, R, part_rz, bf.flags, col_tiles,
+                           row_tiles, G.rows_per, G.mode);
+        SIC_CHECK_LAUNCH();
+        start = 1;
+    }
     const int* hctl = bf.hctl;
     const double* hres = bf.hres;
     int& predicted = *bf.predicted;
-    int launched = 0;
+    int launched = start;
     int active = col_tiles;   // tiles still iterating (as of the last check)
     // algorithmic traffic of one tile-launch (bytes): the sparse matrix once,
     // each n x 64 block touched once per read or write
@@ -543,7 +627,7 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
         // the first check where the last solve of this kind converged (its last
         // update is tested by the next launch's product), then every 4 or 8
         const int first = predicted > 0 ? predicted + 1 : 4;
-        const int chunk = std::min(launched == 0 ? first : (launched < 16 ? 4 : 8),
+        const int chunk = std::min(launched == start ? first : (launched < 16 ? 4 : 8),
                                    max_iter - launched);
         recs.clear();
         for (int c = 0; c < chunk; ++c) {
@@ -632,6 +716,11 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
     res.converged = done && !bad;
     res.max_rel_res = mres;
     predicted = res.converged ? iters : 0;
+    if (ws && res.converged) {
+        const dim3 tg((unsigned)((k + 63) / 64), (unsigned)((n + 63) / 64));
+        hipLaunchKernelGGL(k_cg_store, tg, dim3(256), 0, s, n, k, d_cols, W, ws->W, ws->valid);
+        SIC_CHECK_LAUNCH();
+    }
     return res;
 }
 
@@ -649,7 +738,7 @@ void check_cg(const CGResult& r, const char* what) {
 
 CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
                   double tol, int max_iter, CGWork& wk, hipStream_t s, bool low_precision,
-                  int slot) {
+                  int slot, const WarmStore* ws) {
     if (k > 0 && ldw != k) throw SicError(SIC_EINTERNAL, "block_cg expects ldw == k");
     const int64_t n = A.n;
     const size_t nk = (size_t)n * (size_t)std::max(k, 1);
@@ -669,13 +758,13 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
         wk.P32.reserve(nk);
         wk.Q32.reserve(nk);
         return block_cg_impl<float>(av, d_cols, k, W, tol, max_iter, bf, wk.R32.p, wk.P32.p,
-                                    wk.Q32.p, s);
+                                    wk.Q32.p, s, ws);
     }
     wk.R.reserve(nk);
     wk.P.reserve(nk);
     wk.Q.reserve(nk);
     return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, wk.R.p, wk.P.p, wk.Q.p,
-                                 s);
+                                 s, ws);
 }
 
 // ------------------------------------------------------------------------

@@ -359,7 +359,7 @@ __global__ void k_pcd_stats(const double* __restrict__ sc, double* __restrict__ 
     if (threadIdx.x == 0) {
         stats[0] = sc[SC_ITERS];
         stats[1] = sc[SC_STEP];
-        for (int k = 2; k < 7; ++k) stats[k] = 0.0;
+        for (int k = 2; k < 8; ++k) stats[k] = 0.0;
     }
 }
 

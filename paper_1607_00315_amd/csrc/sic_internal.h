@@ -188,9 +188,17 @@ void check_cg(const CGResult& r, const char* what);
 // low_precision: float vectors with float64 iterate, scalars and sums, and the
 // true residual recomputed in float64 every few iterations (tol >= ~1e-6).
 // slot (0..3) names the caller's kind of solve for the iteration prediction.
+// A store of inverse columns for warm starts: row c of W (n x n row-major)
+// holds column c of A^{-1} as last solved, when valid[c] != 0.
+struct WarmStore {
+    double* W;
+    unsigned char* valid;
+};
+// ws (may be null): start every column from the store (x0 = 0 where it holds
+// none) and write the converged columns back into it.
 CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int64_t ldw,
                   double tol, int max_iter, CGWork& wk, hipStream_t s,
-                  bool low_precision = false, int slot = 0);
+                  bool low_precision = false, int slot = 0, const WarmStore* ws = nullptr);
 
 // The same solve with every buffer in a static per-device array: no device
 // or host allocation. All pointers are device pointers. Throws SIC_ETOOBIG
@@ -261,7 +269,7 @@ void launch_cd(int jp, int b, const int64_t* cptr, const int32_t* c_p, const dou
                double* ug, unsigned char* markg, double* stats, hipStream_t s);
 // Explicit coordinate Hessian form: builds H^T (ncoord^2 doubles at HT), then
 // runs the sweeps; requires cd_hessian_lds_bytes(ncoord) <= CD_MAX_LDS_BYTES.
-// low: H stored as float (in the first half of HT) when the pipelined sweep
+// low: H stored as float (in the first half of HT) when the multi-workgroup sweep
 // runs, the sweep's arithmetic still float64 (the reduced-precision cycles).
 int64_t cd_hessian_limit();   // largest coordinate count the explicit-Hessian sweep takes
 size_t cd_hessian_lds_bytes(int64_t ncoord);
@@ -270,8 +278,13 @@ size_t cd_hessian_lds_bytes(int64_t ncoord);
 int64_t launch_cd_hessian(int64_t ncoord, int jp, const int32_t* c_p, const int32_t* c_ci,
                           const double* WJJ, const double* c_S, const double* c_A,
                           const double* c_inva, const double* c_wtc, double lam, int max_sweeps,
-                          double tol, double* HT, double* delta, double* stats, hipStream_t s,
-                          bool low = false);
+                          double tol, double* HT, double* delta, double* stats, double* xbuf,
+                          hipStream_t s, bool low = false);
+// Doubles of the exchange buffer (xbuf above) through which the workgroups of
+// the multi-workgroup sweep pass step lists and partial gradients; with a null
+// xbuf the sweep runs on one workgroup. stats[7] != 0 after the sweep: its
+// workgroups gave up waiting on one another (the result is not usable).
+size_t cd_exchange_doubles();
 
 // ---------------------------------------------------------------- k_pcd.hip
 struct PcdWork {

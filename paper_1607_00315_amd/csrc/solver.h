@@ -24,6 +24,7 @@ struct Options {
 // Scratch of one block update; sized on demand, reused across blocks.
 struct BlockWork {
     DevBuf<double> SJ, WI, AJ, ANEW, WN, WJJ, U, ug, HT;
+    DevBuf<double> cdx;    // exchange buffer of the multi-workgroup CD sweep
     DevBuf<unsigned char> markg;
     DevBuf<char> xstage;   // reduced-precision X before its conversion; relabelled X
     DevBuf<int32_t> perm;  // a relabelling on the device
@@ -71,6 +72,11 @@ struct BlockResult {
     int64_t nnz_after = 0;
 };
 
+// (the step entry points of sic_steps.h pass warm_allowed = false: their
+// conjugate gradients start from zero, as the oracle's do)
+constexpr size_t warm_store_max_bytes = (size_t)2 << 30;
+inline bool warm_store_fits(int64_t n) { return (double)n * n * 8.0 <= (double)warm_store_max_bytes; }
+
 struct Problem {
     int64_t n = 0, m = 0;
     double lam = 0;
@@ -94,7 +100,20 @@ struct Problem {
     // relabelling of the variables (SIC_FLAG_CLUSTER): perm[p] is the caller's
     // label of the variable the solver calls p; empty means none
     std::vector<int32_t> perm;
+    // inverse columns as last solved, the conjugate gradients' warm starts:
+    // row c of Wst holds column c of A^{-1} when Wvalid[c] (kept when n^2
+    // doubles fit in warm_store_max_bytes and SIC_FLAG_NO_WARM_CG is off)
+    DevBuf<double> Wst;
+    DevBuf<unsigned char> Wvalid;
+    bool warm = false;
+    const WarmStore* warm_store() {
+        ws_ = WarmStore{Wst.p, Wvalid.p};
+        return warm ? &ws_ : nullptr;
+    }
     DevCSR& Acur() { return A[cur]; }
+  private:
+    WarmStore ws_{nullptr, nullptr};
+  public:
 };
 
 struct Context {
@@ -114,7 +133,7 @@ struct Context {
     // pinned staging for small device-to-host reads (64 entries each):
     //   h_i64[0, 3) counts, [8] the rebuilt CSR's entry count, [16] the coarse-level
     //   error flag (int32); h_f64[0, 26) line-search trials, [32] the PCD stop
-    //   flag, [40, 47) sweep statistics, [48, 50) the coarse A_II factor's flags
+    //   flag, [40, 48) sweep statistics, [48, 50) the coarse A_II factor's flags
     int64_t* h_i64 = nullptr;
     double* h_f64 = nullptr;
     BlockResult last;
@@ -132,7 +151,7 @@ void release_workspace(Context& C);
 
 // problem setup / transfer
 void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n, int64_t m,
-                  double lam);
+                  double lam, bool warm_allowed = true);
 void set_identity(Context& C, Problem& P);
 void set_A_host(Context& C, Problem& P, const sic_csr* A);
 void get_A_host(Context& C, Problem& P, sic_csr* out);

@@ -258,7 +258,7 @@ __global__ void k_to_f64_from_bf16(const uint16_t* __restrict__ in, int64_t coun
 }
 
 void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n, int64_t m,
-                  double lam) {
+                  double lam, bool warm_allowed) {
     hipStream_t s = C.stream;
     P.n = n;
     P.m = m;
@@ -310,6 +310,12 @@ void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n,
     P.F = tr + lam * (double)n;   // F(I) = -log det I + tr(S) + lam * n
     P.level_set = false;
     P.perm.clear();
+    P.warm = warm_allowed && !(C.opt.flags & SIC_FLAG_NO_WARM_CG) && warm_store_fits(n);
+    if (P.warm) {
+        P.Wst.reserve((size_t)n * n);
+        P.Wvalid.reserve(n);
+        SIC_HIP(hipMemsetAsync(P.Wvalid.p, 0, (size_t)n, s));
+    }
 }
 
 void set_identity(Context& C, Problem& P) {
@@ -565,9 +571,10 @@ static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max
     if (nc > 0 && nc <= C.opt.cd_hessian_max && nc <= cd_hessian_limit() &&
         cd_hessian_lds_bytes(nc) <= CD_MAX_LDS_BYTES) {
         W.HT.reserve((size_t)nc * nc);
+        W.cdx.reserve(cd_exchange_doubles());
         return launch_cd_hessian(nc, jp, W.c_p.p, W.c_ci.p, W.WJJ.p, W.c_S.p, W.c_A.p,
                                  W.c_inva.p, W.c_wtc.p, lam, max_sweeps, tol, W.HT.p, W.delta.p,
-                                 W.cdstats.p, s, C.prec != PREC_F64);
+                                 W.cdstats.p, W.cdx.p, s, C.prec != PREC_F64);
     }
     W.U.reserve((size_t)jp * b);
     W.ug.reserve(jp);
@@ -610,7 +617,7 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
         SIC_HIP(hipEventRecord(C.ev_join, C.side));
         launch_iota_i32(W.cols.p, b, (int32_t)j0, s);
         CGResult cg = block_cg(A, W.cols.p, b, W.WI.p, b, tolI, C.opt.cg_max_iter, W.cg, s,
-                               C.prec != PREC_F64, 0);
+                               C.prec != PREC_F64, 0, P.warm_store());
         check_cg(cg, "W_I");
         R.cg_iters_I = cg.iterations;
         R.cg_res_I = cg.max_rel_res;
@@ -659,7 +666,7 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
         W.WNC.reserve((size_t)n * std::max<int64_t>(nC, 1));
         if (nC > 0) {
             CGResult cg = block_cg(A, W.NC.p, (int)nC, W.WNC.p, nC, tolI, C.opt.cg_max_iter, W.cg,
-                                   s, C.prec != PREC_F64, 2);
+                                   s, C.prec != PREC_F64, 2, P.warm_store());
             check_cg(cg, "W_{N^C}");
             R.cg_iters_N = cg.iterations;
             R.cg_res_N = cg.max_rel_res;
@@ -719,7 +726,7 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
     if (fine && nN > 0) {
         W.WN.reserve((size_t)n * nN);
         CGResult cg = block_cg(A, W.Jp.p + b, (int)nN, W.WN.p, nN, tolN, C.opt.cg_max_iter, W.cg,
-                               s, C.prec != PREC_F64, 1);
+                               s, C.prec != PREC_F64, 1, P.warm_store());
         check_cg(cg, "W_N");
         R.cg_iters_N = cg.iterations;
         R.cg_res_N = cg.max_rel_res;
@@ -752,12 +759,13 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
     // the sweep statistics go to pinned staging: the copy does not hold the host,
     // and the line search's first read-back waits for it
     double* h_cds = C.h_f64 + 40;
-    SIC_HIP(hipMemcpyAsync(h_cds, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
+    SIC_HIP(hipMemcpyAsync(h_cds, W.cdstats.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
     // (e) line search
     LineSearch ls = line_search(C, P.lam, jp, b, nN, nc, true);
     sync(C);   // (no-op when the line search ended on a read-back)
-    double cds[7];
-    std::copy(h_cds, h_cds + 7, cds);
+    double cds[8];
+    std::copy(h_cds, h_cds + 8, cds);
+    if (cds[7] != 0.0) throw SicError(SIC_EINTERNAL, "CD sweep workgroups timed out waiting on one another");
     R.cd_sweeps = (int)cds[0];
     R.cd_last_maxmu = cds[1];
     prof_scale(cd_rec, cds[0]);
@@ -1061,6 +1069,7 @@ void cluster_problem(Context& C, Problem& P) {
     for (int64_t p = 0; p < n; ++p) composed[p] = P.perm.empty() ? order[p] : P.perm[order[p]];
     P.perm = std::move(composed);
     P.level_set = false;
+    if (P.warm) SIC_HIP(hipMemsetAsync(P.Wvalid.p, 0, (size_t)n, s));   // stored columns: old labels
     sync(C);
 }
 
@@ -1084,7 +1093,7 @@ static double exact_kkt_body(Context& C, Problem& P, double tol_cg, double* l1) 
         launch_sj_gemm_f64(P.X.p, n, P.m, j0, bb, W.SJ.p, s);
         launch_iota_i32(W.cols.p, bb, (int32_t)j0, s);
         check_cg(block_cg(P.Acur(), W.cols.p, bb, W.WI.p, bb, tol_cg, C.opt.cg_max_iter * 4, W.cg,
-                          s, false, 3),
+                          s, false, 3, P.warm_store()),
                  "exact KKT pass");
         const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
         W.tilecount.reserve((size_t)tiles * bb);
@@ -1320,9 +1329,10 @@ int step_cd_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cp
     const int64_t nc = cptr[b];
     const int64_t cd_rec = run_cd(C, jp, b, nc, lambda, max_sweeps, tol);
     if (nc) SIC_HIP(hipMemcpyAsync(delta_out, W.delta.p, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-    double st[7];
-    SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
+    double st[8];
+    SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
     sync(C);
+    if (st[7] != 0.0) throw SicError(SIC_EINTERNAL, "CD sweep workgroups timed out waiting on one another");
     prof_scale(cd_rec, st[0]);
     if (stats_out) std::copy(st, st + 7, stats_out);
     return SIC_OK;

@@ -202,3 +202,27 @@ def test_continuation_matches_oracle(name, multilevel):
     assert info["status"] == 0
     assert info["cycles"] >= 4
     _check_against_oracle(csr_to_dense(rp, col, val, n), _oracle(S, lam), S, lam, info)
+
+
+@pytest.mark.parametrize("name", ["random_n600_m300", "delaunay_n700_m200"])
+def test_warm_started_cg_matches_cold(name):
+    """Warm starts of the block CG (each column of W_J started from the last
+    inverse column computed for it) change only where the iterations begin:
+    with and without them the result is the oracle's minimiser, and the warm
+    run needs no more CG iterations than the cold one."""
+    from paper_1607_00315_amd import sic
+    X, P, spec = workload(name)
+    n = X.shape[1]
+    lam = spec["lam"]
+    S = core.covariance(X)
+    ref = _oracle(S, lam)
+    its = {}
+    for warm in (True, False):
+        flags = 0 if warm else sic.FLAG_NO_WARM_CG
+        announce(f"warm-start CG {name} lam={lam} warm={warm}")
+        with sic.Context(block=spec["block"], flags=flags) as c:
+            (rp, col, val), info, _ = c.solve(X, lam, TOL)
+        assert info["status"] == 0
+        _check_against_oracle(csr_to_dense(rp, col, val, n), ref, S, lam, info)
+        its[warm] = info["cg_iterations"]
+    assert its[True] <= its[False], its

@@ -198,22 +198,33 @@ def test_cd_step_matches_oracle(ctx, ctx_u, rnd600, start, form):
     assert np.max(np.abs(got2 - ref2)) <= 1e-3 * max(1e-12, np.max(np.abs(ref2)))
 
 
-@pytest.mark.parametrize("j1", [160, 176])
-def test_cd_pipelined_step_matches_oracle(ctx, rnd600, j1):
-    """The pipelined explicit-Hessian sweep (the kernel of the benchmark's
-    blocks): 718 coordinates (one worker row per thread, 12 chunks, the last
-    ragged) and 1137 (two rows per thread, 18 chunks), six fixed sweeps against
-    the plain C loop, then the default stopping rule against the oracle."""
+@pytest.mark.parametrize("j1,lam_scale,chunks", [(160, 1.0, 12), (176, 1.0, 18), (130, 1.0, 3),
+                                                 (129, 1.0, 2), (129, 1.5, 1), (129, 3.0, 1)])
+def test_cd_multi_step_matches_oracle(ctx, rnd600, j1, lam_scale, chunks):
+    """The multi-workgroup explicit-Hessian sweep (the kernel of the benchmark's
+    blocks): 718 coordinates (12 chunks, the last ragged, one helper workgroup
+    each) and 1137 (18 chunks, two helpers owning two chunks), and the cases
+    with fewer chunks than the snapshot lag of three intervals (3, 2, 1 chunks,
+    down to a single coordinate); six fixed sweeps against the plain C loop,
+    then the default stopping rule against the oracle."""
     from paper_1607_00315_amd import sic
     X, P, spec, S = rnd600
-    lam = spec["lam"]
+    lam = spec["lam"] * lam_scale
     j0 = 128
     d = _block_inputs(np.eye(600), S, lam, j0, j1)
-    announce(f"step_cd (pipelined) random_n600 block [{j0},{j1}) coords={d['r'].size}")
+    assert (d["r"].size + 63) // 64 == chunks
+    announce(f"step_cd (multi-workgroup) random_n600 block [{j0},{j1}) lam={lam} "
+             f"coords={d['r'].size}")
     got, st = sic.step_cd(ctx, d["wjj"], d["b"], d["cptr"], d["cp"], d["S"], d["A"], lam,
                           max_sweeps=6, tol=0.0)
     ref, sw, _ = cd_sweeps(d["wjj"], d["cp"], d["c"] - j0, d["S"], d["A"], lam, 6, 0.0)
-    assert int(st[0]) == sw == 6
+    # with tol = 0 a sweep stops the loop only when every step is exactly zero:
+    # either side can reach such a fixed point early on a small block (more
+    # sweeps would keep it); the summation orders differ, so one may stop while
+    # the other keeps taking steps of rounding size
+    assert 1 <= sw <= 6 and 1 <= int(st[0]) <= 6
+    if chunks > 3:
+        assert int(st[0]) == sw == 6
     assert np.max(np.abs(got - ref)) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
     got2, st2 = sic.step_cd(ctx, d["wjj"], d["b"], d["cptr"], d["cp"], d["S"], d["A"], lam)
     ref2, sw2, _ = steps.cd_block(d["W"], d["r"], d["c"], d["S"], d["A"], lam, j0, j1, d["N"])

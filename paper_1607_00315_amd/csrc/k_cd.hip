@@ -561,13 +561,13 @@ constexpr int CDP_CONST = 4 * CDH_K;   // a chunk's 1/a, A, S and W_rc, staged w
 //              to that z, and after list g' it publishes the z of the chunk
 //              due at interval g' + 3 (a snapshot of the steps of intervals
 //              <= g' = x - 3, for x = g' + 3);
-//   workgroup 0, interval g: wave 0 starts from snapshot(g), plus the steps
-//              of interval g-2 on chunk g (formed by waves 1-8 during interval
+//   workgroup 0, interval g: z starts from snapshot(g), plus the steps of
+//              interval g-2 on chunk g (formed by waves 1-8 during interval
 //              g-1 from the tile H[chunk g][chunk g-2]), plus those of g-1
-//              (from the staged tile H[chunk g][chunk g-1]), runs the chain
-//              and writes its step list; waves 1-15 stage the next interval's
-//              tiles, form the g-1 contribution for chunk g+1, and wave 9
-//              fetches snapshot(g+1).
+//              (from the staged tile H[chunk g][chunk g-1], a quarter on each
+//              of waves 0-3); wave 0 then runs the chain; waves 1-15 stage the next interval's tiles, form the g-1
+//              contribution for chunk g+1, wave 9 fetches snapshot(g+1) and
+//              wave 10 publishes the step list of interval g-1.
 // z_k is then sum_t H[k][t] Delta_t summed by interval, and the chain and its
 // visiting order are those of k_cd_dense.
 //
@@ -586,6 +586,7 @@ constexpr int CDM_RZ = 8;            // snapshot ring
 constexpr int CDM_LAG = 3;           // snapshot(x) holds the steps of intervals <= x - 3
 constexpr int CDM_PW = 8;            // waves forming the interval-(g-1) part for chunk g+1
 constexpr int CDM_SNAPW = CDM_PW + 1;   // the wave fetching the snapshot
+constexpr int CDM_PUBW = CDM_PW + 2;    // the wave publishing the step lists
 // exchange buffer: int flags, one per 128-byte line, then the two rings (doubles)
 enum { XF_PUB = 0, XF_STATUS = 32, XF_SNAP = 64 };   // snapshot flag s at XF_SNAP + 32 s
 constexpr int CDM_FLAG_INTS = XF_SNAP + 32 * CDM_RZ;
@@ -701,38 +702,36 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
         for (int i = 0; i < C; ++i, ++g) {
             const int b = (int)(g & 1), pb = 1 - b;
             const int K = klen(i);
-            if (wave == 0) {
-                // the list of interval g-1 was stored at its end: publish it
-                if (g > 0 && lane == 0) {
-                    x_drain();
-                    xst_i(xf + XF_PUB, (int)g);
+            // z of this chunk's rows, in two stages: waves 0-3 each apply a quarter
+            // of the steps of interval g-1 (tile rows 16 w .. 16 w + 15) and add
+            // two of the parts of interval g-2 (wave 0 also the snapshot) into
+            // part slot 2 w; after the barrier wave 0 adds the four slots
+            double* zb = zp + b * (CDM_PW + 1) * CDH_K;
+            if (wave < 4) {
+                double a0 = zb[(2 * wave) * CDH_K + lane] + zb[(2 * wave + 1) * CDH_K + lane];
+                if (wave == 0) a0 = zb[CDM_PW * CDH_K + lane] + a0;
+                if (g > 0 && s_nnz[pb] > 0) {
+                    const double* st = St + b * CDP_TILE + (16 * wave) * CDH_K;
+                    const double* pm = mud + pb * CDH_K + 16 * wave;
+                    double sv[16], mv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        sv[u] = st[u * CDH_K + lane];
+                        mv[u] = pm[u];
+                    }
+                    double ac[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) ac[u & 3] += sv[u] * mv[u];
+                    a0 += (ac[0] + ac[1]) + (ac[2] + ac[3]);
                 }
+                zb[(2 * wave) * CDH_K + lane] = a0;
+            }
+            lds_barrier();
+            if (wave == 0) {
                 if (i == 0) maxmu = 0.0;
                 const bool on = lane < K;
                 const int kl = on ? i * CDH_K + lane : i * CDH_K;
-                // z: snapshot, then the parts of interval g-2 in wave order
-                const double* zb = zp + b * (CDM_PW + 1) * CDH_K;
-                double z = zb[CDM_PW * CDH_K + lane];
-#pragma unroll
-                for (int w = 0; w < CDM_PW; ++w) z += zb[w * CDH_K + lane];
-                // steps of interval g-1 onto the rows of this chunk
-                if (g > 0 && s_nnz[pb] > 0) {
-                    const double* st = St + b * CDP_TILE;
-                    const double* pm = mud + pb * CDH_K;
-                    double a[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-                    for (int t = 0; t < CDH_K; t += 8) {
-                        double sv[8], mv[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            sv[u] = st[(t + u) * CDH_K + lane];
-                            mv[u] = pm[t + u];
-                        }
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) a[u & 3] += sv[u] * mv[u];
-                    }
-                    z += (a[0] + a[1]) + (a[2] + a[3]);
-                }
+                double z = (zb[lane] + zb[2 * CDH_K + lane]) + (zb[4 * CDH_K + lane] + zb[6 * CDH_K + lane]);
                 z = on ? z : 0.0;
                 if (tid == 0) { const long long now = wall_clock64(); s_tph[0] += now - s_tph[3]; s_tph[3] = now; }
                 const double* cb = cst + b * CDP_CONST;
@@ -776,8 +775,6 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
                 }
                 double mul = __longlong_as_double(((long long)mhi << 32) | (unsigned int)mlo);
                 mul = on ? mul : 0.0;
-                // the list goes out first; it is published at the next interval's start
-                xst_d(xsteps + (g % CDM_RS) * CDH_K + lane, mul);
                 maxmu = fmax(maxmu, wave_max(fabs(mul)));
                 if (on) ds[kl] = d0 + mul;
                 mud[b * CDH_K + lane] = mul;
@@ -819,6 +816,13 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
                         for (int u = 0; u < CDH_K / CDM_PW; ++u) acc += hv[u] * pm[t0 + u];
                     }
                     zn[(wave - 1) * CDH_K + lane] = acc;
+                } else if (wave == CDM_PUBW) {
+                    // publish the list of interval g-1 (wave 0 does not wait on global stores)
+                    if (g > 0) {
+                        xst_d(xsteps + ((g - 1) % CDM_RS) * CDH_K + lane, mud[pb * CDH_K + lane]);
+                        x_drain();
+                        if (lane == 0) xst_i(xf + XF_PUB, (int)g);
+                    }
                 } else if (wave == CDM_SNAPW) {
                     // snapshot(g+1) from the helper that owns chunk cn
                     double v = 0.0;

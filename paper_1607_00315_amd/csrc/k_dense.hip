@@ -35,8 +35,9 @@ struct CholShared {
     double Pn[CB_N][CB * CB_PLD];       // updated blocks of column kb, accumulator layout
     double Part[CH_WAVES][4 * 64];      // partial sums when a block's K range is split
     double Lik[CB * CB_PLD];            // inverse of the diagonal factor (lower)
+    double piv[CH_NB];                  // pivots (t of pivot 1 + t, or t), for the log det
+    double red[CH_WAVES];
     int bad;
-    double logdet;
 };
 
 // Barrier for LDS traffic only: outstanding global stores and loads stay in
@@ -66,13 +67,15 @@ __device__ inline double chol_readlane(double v, int l) {
 // (batch over blockIdx.x, matrices `stride` doubles apart, leading dimension
 // ld), left-looking over 16-column block columns; the factor is written in
 // place and re-read from there (the matrix stays in L2). For block column kb:
-//   1. row block kb of L is staged in LDS; C_I = A_{I,kb} - sum_j L_{I,j}
-//      L_{kb,j}^T for every block row I >= kb on FP64 MFMA (16x16x4), the
-//      L_{I,j} operands read from the stored factor, all of a step's loads
-//      in flight at once; when few block rows remain, their K ranges are
-//      split over the waves and the partial sums added in a fixed order;
-//   2. one wave factors C_kk and inverts the factor in registers (rows in
-//      lanes 0..15, the pivot row broadcast with readlane);
+//   1. C_I = A_{I,kb} - sum_j L_{I,j} L_{kb,j}^T for every block row I >= kb
+//      on FP64 MFMA (16x16x4), the L_{I,j} operands read from the stored
+//      factor, all of a step's loads in flight at once; the waves of block
+//      row kb also put their operands (row block kb of L) in LDS as the other
+//      factor. When few block rows remain, their K ranges are split over the
+//      waves and the partial sums added in a fixed order;
+//   2. one wave factors C_kk (rows in lanes 0..15, the pivot row broadcast
+//      with readlane) and inverts the factor (lane j forming column j, the
+//      factor read back from LDS);
 //   3. each panel block becomes L_I = C_I L_kk^{-T} (4 MFMAs) and is stored.
 // Only the panel stores are re-read inside the kernel, so only the barrier
 // that ends a block column waits for global stores.
@@ -96,10 +99,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
     const int lr = lane >> 4, lc = lane & 15;
     const int nt = (nb + CB - 1) / CB;
     const double pad = identity ? 0.0 : 1.0;   // padded diagonal: contributes log 1 = 0
-    if (tid == 0) {
-        sh.bad = 0;
-        sh.logdet = 0.0;
-    }
+    if (tid == 0) sh.bad = 0;
     for (int kb = 0; kb < nt; ++kb) {
         const int r0 = kb * CB;
         // (1) C_I for I = kb .. nt-1. With nout >= 8 block rows, wave w takes rows
@@ -138,18 +138,35 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
             const bool valid = nbw >= 1 && j < jhi;
             // L_{I,j}[lc][4 lr + t], read from its transpose in the upper triangle so
             // that 16 consecutive lanes read one contiguous row segment
+            // (valid is the same in every lane: jobs past the wave's range issue
+            // nothing, which matters because the memory pipeline's cost is per
+            // instruction). Lanes past nb read element 0 and are masked where
+            // the values are used: a select here would wait for each load.
             const int acol = (q ? I1 : I0) * CB + lc;
+            if (valid) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                a[x][t] = -load_or(A, (int64_t)(j * CB + 4 * lr + t) * ld + acol, valid && acol < nb,
-                                   0.0);
+                for (int t = 0; t < 4; ++t)
+                    a[x][t] = A[acol < nb ? (int64_t)(j * CB + 4 * lr + t) * ld + acol : 0];
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[x][t] = 0.0;
+            }
         }
-        // stage L_{kb, 0:kb}: Rk[j][r][c] = L[r0 + r][j*16 + c]
-        for (int e = tid; e < kb * CB * CB; e += CH_THREADS) {
-            const int j = e / (CB * CB), rc = e - j * CB * CB;
-            const int r = rc / CB, c = rc - r * CB;
-            const int row = r0 + r;
-            sh.Rk[j][r * CB_RLD + c] = load_or(A, (int64_t)row * ld + j * CB + c, row < nb, 0.0);
+        // Rk[j][r][c] = -L[r0 + r][j*16 + c] (the B operands, row block kb of L,
+        // negated so that the products subtract) from the waves whose block row
+        // is kb: their A operands above are those blocks, read from the
+        // transposed copy, so no load of its own is needed
+        const bool in0c = I0 * CB + lc < nb, in1c = I1 * CB + lc < nb;   // lanes inside the matrix
+        if (I0 == kb) {
+#pragma unroll
+            for (int x = 0; x < JOBS; ++x) {
+                const int j = jlo + (nbw == 2 ? (x & 7) : x);
+                if ((nbw == 1 || x < 8) && j < jhi) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        sh.Rk[j][lc * CB_RLD + 4 * lr + t] = in0c ? -a[x][t] : 0.0;
+                }
+            }
         }
         chol_lds_barrier();
 #pragma unroll
@@ -160,10 +177,11 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const double bv = sh.Rk[j][lc * CB_RLD + 4 * lr + t];
+                    const double av = (q ? in1c : in0c) ? a[x][t] : 0.0;
                     if (q)
-                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][t], bv, acc1, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1, 0, 0, 0);
                     else
-                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][t], bv, acc0, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
                 }
             }
         }
@@ -222,37 +240,51 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
 #pragma unroll
                 for (int j = k + 1; j < CB; ++j) rw[j] -= rw[k] * chol_readlane(rw[k], j);
             }
-            // rows of the inverse factor: right-looking forward substitution
-            double li[CB];
-#pragma unroll
-            for (int j = 0; j < CB; ++j) li[j] = (lane == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < CB; ++k) {
-                const double ikk = ikks[k];
-                const double f = (lane > k) ? rw[k] : 0.0;
-#pragma unroll
-                for (int j = 0; j <= k; ++j) {
-                    if (lane == k) li[j] *= ikk;             // row k of the inverse is final
-                    li[j] -= f * chol_readlane(li[j], k);    // rows below: subtract L_ik (row k)
-                }
-            }
-            double lg = (on && !bad) ? (identity ? log1p(tsave) : log(tsave)) : 0.0;
-            for (int off = 32; off > 0; off >>= 1) lg += __shfl_xor(lg, off, 64);
+            // The factor's rows go out, and to LDS transposed (T[k][i] = L_ik,
+            // with 1/L_kk on the diagonal) in the partial-sum area, free now.
+            // Then lane j forms column j of the inverse by forward substitution,
+            // right-looking (once x_k is known every later row's sum takes
+            // L_ik x_k, one broadcast read of T), each entry stored when formed.
+            double* T = &sh.Part[0][0];
             if (on) {
                 const int row = r0 + lane;
 #pragma unroll
-                for (int j = 0; j < CB; ++j) {
-                    const double lv = (j <= lane) ? rw[j] : 0.0;
-                    const double iv = (j <= lane) ? li[j] : 0.0;
-                    sh.Lik[lane * CB_PLD + j] = iv;
-                    if (row < nb && r0 + j < nb) A[(int64_t)row * ld + r0 + j] = lv;
-                    if (dinv && !bad) dinv[kb * CB * CB + lane * CB + j] = iv;
+                for (int k = 0; k < CB; ++k) {
+                    T[k * CB_PLD + lane] = (k == lane) ? ikks[k] : ((k < lane) ? rw[k] : 0.0);
+                    if (row < nb && r0 + k < nb) A[(int64_t)row * ld + r0 + k] = (k <= lane) ? rw[k] : 0.0;
                 }
             }
-            if (lane == 0) {
-                sh.logdet += lg;
-                if (bad) sh.bad = 1;
+            // Row k + 1 of T is read at the start of step k, before the step's
+            // stores, so its latency hides behind the step; the compiler
+            // barrier keeps the reads from being hoisted further (all of T at
+            // once would not fit the registers).
+            double rs[CB], tn[CB];
+#pragma unroll
+            for (int i = 0; i < CB; ++i) {
+                rs[i] = 0.0;
+                tn[i] = T[i];
             }
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                double tc[CB];
+#pragma unroll
+                for (int i = k; i < CB; ++i) tc[i] = tn[i];
+                if (k + 1 < CB) {
+#pragma unroll
+                    for (int i = k + 1; i < CB; ++i) tn[i] = T[(k + 1) * CB_PLD + i];
+                }
+                const double x = ((lane == k ? 1.0 : 0.0) - rs[k]) * tc[k];
+                if (on) {
+                    const double iv = (k >= lane) ? x : 0.0;
+                    sh.Lik[k * CB_PLD + lane] = iv;
+                    if (dinv && !bad) dinv[kb * CB * CB + k * CB + lane] = iv;
+                }
+#pragma unroll
+                for (int i = k + 1; i < CB; ++i) rs[i] = fma(tc[i], x, rs[i]);
+                asm volatile("" ::: "memory");
+            }
+            if (on) sh.piv[kb * CB + lane] = tsave;
+            if (lane == 0 && bad) sh.bad = 1;
         }
         chol_lds_barrier();   // the factor's global copy is not re-read in this kernel
         if (sh.bad) break;
@@ -278,8 +310,17 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
         }
         __syncthreads();   // the new block column of L is visible to the next step
     }
+    // log det: the log (log1p for I + E) of every pivot at once, summed in a
+    // fixed order (the padded pivots contribute log 1 = 0)
+    double lg = 0.0;
+    if (!sh.bad && tid < nt * CB) lg = identity ? log1p(sh.piv[tid]) : log(sh.piv[tid]);
+    for (int off = 32; off > 0; off >>= 1) lg += __shfl_xor(lg, off, 64);
+    if (lane == 0) sh.red[wave] = lg;
+    __syncthreads();
     if (tid == 0) {
-        out[2 * blockIdx.x] = sh.logdet;
+        double ld_sum = 0.0;
+        for (int w = 0; w < CH_WAVES; ++w) ld_sum += sh.red[w];
+        out[2 * blockIdx.x] = sh.bad ? 0.0 : ld_sum;
         out[2 * blockIdx.x + 1] = sh.bad ? 0.0 : 1.0;
     }
 }

@@ -66,7 +66,8 @@ template <typename V>
 __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __restrict__ cols,
                           const double* __restrict__ dinv, double* __restrict__ W,
                           V* __restrict__ R, double* __restrict__ scal,
-                          int* __restrict__ tctl, double* __restrict__ tres) {
+                          int* __restrict__ tctl, double* __restrict__ tres,
+                          int* __restrict__ mctl, double* __restrict__ mres) {
     // x0 = 0, r0 = e_cols[j] over the whole n x k block (rows over workgroups,
     // columns over threads); z0 = D^{-1} r0 is formed where it is read
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
@@ -89,6 +90,12 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
             tctl[j * T_INTS + T_ITER] = 0;
             tctl[j * T_INTS + T_BAD] = 0;
             tres[j] = 1.0;
+            if (mctl) {
+                mctl[j * T_INTS + T_DONE] = 0;
+                mctl[j * T_INTS + T_ITER] = 0;
+                mctl[j * T_INTS + T_BAD] = 0;
+                mres[j] = 1.0;
+            }
         }
     }
 }
@@ -212,8 +219,8 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const double* __restrict__ vd, int64_t n, int k, const double* __restrict__ dinv,
     const V* __restrict__ R, V* __restrict__ P, V* __restrict__ Q, double* __restrict__ scal,
     const double* __restrict__ rzrr, double* __restrict__ part, int* __restrict__ tctl,
-    double* __restrict__ tres, double tol, int it, int gx, int gy, int64_t rows_per, int mode,
-    int check_only) {
+    double* __restrict__ tres, int* __restrict__ mctl, double* __restrict__ mres, double tol,
+    int it, int gx, int gy, int64_t rows_per, int mode, int check_only) {
     const Tile T = cg_tile(mode, gx, gy);
     if (!T.ok) return;
     const int tx = T.tx, ty = T.ty;
@@ -266,9 +273,15 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
                 scal[j * 4 + S_RR] = rr;
             }
             if (lane == 0) {
+                const int itv = (conv || check_only) ? it : it + 1;
                 tres[tx] = res;
-                tctl[tx * T_INTS + T_ITER] = (conv || check_only) ? it : it + 1;
+                tctl[tx * T_INTS + T_ITER] = itv;
                 if (conv) tctl[tx * T_INTS + T_DONE] = 1;
+                if (mctl) {   // the host's copy (pinned memory), read at its next check
+                    mres[tx] = res;
+                    mctl[tx * T_INTS + T_ITER] = itv;
+                    if (conv) mctl[tx * T_INTS + T_DONE] = 1;
+                }
             }
         }
         if (conv) return;
@@ -343,7 +356,8 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
     int64_t n, int k, const double* __restrict__ dinv, double* __restrict__ W,
     V* __restrict__ R, const V* __restrict__ P, const V* __restrict__ Q,
     const double* __restrict__ scal, const double* __restrict__ pqp, double* __restrict__ part,
-    int* __restrict__ tctl, int it, int gx, int gy, int64_t rows_per, int mode) {
+    int* __restrict__ tctl, int* __restrict__ mctl, int it, int gx, int gy, int64_t rows_per,
+    int mode) {
     const Tile T = cg_tile(mode, gx, gy);
     if (!T.ok) return;
     const int tx = T.tx, ty = T.ty;
@@ -379,6 +393,10 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(
             int* c = tctl + tx * T_INTS;
             c[T_BAD] = 1;
             c[T_DONE] = 1;
+            if (mctl) {
+                mctl[tx * T_INTS + T_BAD] = 1;
+                mctl[tx * T_INTS + T_DONE] = 1;
+            }
         }
         return;
     }
@@ -515,8 +533,10 @@ struct CsrView {
 
 // Buffers of one solve. Device: dinv (n), vd (nnz), part (row_tiles * k * 3), scal
 // (4k + col_tiles), flags (T_INTS * col_tiles). Host: hctl (T_INTS *
-// col_tiles ints) and hres (col_tiles doubles), the targets of the control
-// read-backs. predicted: iterations of the last solve of this kind (read and
+// col_tiles ints) and hres (col_tiles doubles), the host's view of the control
+// words. mirror: hctl and hres are pinned, and the kernels write them beside
+// the device words (a check then copies nothing); otherwise each check copies
+// them. predicted: iterations of the last solve of this kind (read and
 // updated). prof: record launches with the profiler.
 struct CGBufs {
     double* dinv;
@@ -528,6 +548,7 @@ struct CGBufs {
     double* hres;
     int* predicted;
     bool prof;
+    bool mirror;
 };
 
 // Launch geometry of one solve: gx 64-column tiles; gy row tiles of rows_per
@@ -577,6 +598,8 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
     }
     const CgGeom G = cg_geom(n, k);
     const bool wide = A.nnz > (int64_t)CG_WIDE_ROW * n;
+    int* hm_ctl = bf.mirror ? bf.hctl : nullptr;   // host mirrors of the control words
+    double* hm_res = bf.mirror ? bf.hres : nullptr;
     const int col_tiles = G.gx;
     const int row_tiles = G.gy;
     // partials: r.z and r.r of an update (two per entry), then p.q of a product
@@ -590,7 +613,8 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
                        dim3(256), 0, s, A.col, A.val, bf.dinv, A.nnz, bf.vd);
     SIC_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, s,
-                       n, k, col_tiles, d_cols, bf.dinv, W, R, bf.scal, bf.flags, tres);
+                       n, k, col_tiles, d_cols, bf.dinv, W, R, bf.scal, bf.flags, tres, hm_ctl,
+                       hm_res);
     SIC_CHECK_LAUNCH();
     // warm start: x0 from the store, r0 = e - A x0 exactly, and the iterations
     // begin at 1 with p = q = 0 (the first product's beta then acts on zeros)
@@ -639,20 +663,20 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
             if (wide)
                 hipLaunchKernelGGL((k_cg_spmm<V, 16>), G.grid, dim3(CG_THREADS), 0, s, A.rowptr,
                                    A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
-                                   part_pq, bf.flags, tres, tol, it, col_tiles, row_tiles,
-                                   G.rows_per, G.mode, 0);
+                                   part_pq, bf.flags, tres, hm_ctl, hm_res, tol, it, col_tiles,
+                                   row_tiles, G.rows_per, G.mode, 0);
             else
                 hipLaunchKernelGGL((k_cg_spmm<V, 8>), G.grid, dim3(CG_THREADS), 0, s, A.rowptr,
                                    A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
-                                   part_pq, bf.flags, tres, tol, it, col_tiles, row_tiles,
-                                   G.rows_per, G.mode, 0);
+                                   part_pq, bf.flags, tres, hm_ctl, hm_res, tol, it, col_tiles,
+                                   row_tiles, G.rows_per, G.mode, 0);
             SIC_CHECK_LAUNCH();
             if (bf.prof)
                 r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
                                   2.0 * A.nnz * k + 4.0 * n * k);
             if (bf.prof) prof_begin(KK_CG_UPDATE, s);
             hipLaunchKernelGGL(k_cg_update<V>, G.grid, dim3(CG_THREADS), 0, s, n, k, bf.dinv, W,
-                               R, P, Q, bf.scal, part_pq, part_rz, bf.flags, it, col_tiles,
+                               R, P, Q, bf.scal, part_pq, part_rz, bf.flags, hm_ctl, it, col_tiles,
                                row_tiles, G.rows_per, G.mode);
             SIC_CHECK_LAUNCH();
             if (bf.prof)
@@ -671,14 +695,16 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
             // the last update's residual has no product after it to test it
             hipLaunchKernelGGL((k_cg_spmm<V, 8>), dim3(col_tiles, 1), dim3(CG_THREADS), 0, s,
                                A.rowptr, A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
-                               part_pq, bf.flags, tres, tol, launched, col_tiles, row_tiles,
-                               G.rows_per, 0, 1);
+                               part_pq, bf.flags, tres, hm_ctl, hm_res, tol, launched, col_tiles,
+                               row_tiles, G.rows_per, 0, 1);
             SIC_CHECK_LAUNCH();
         }
-        SIC_HIP(hipMemcpyAsync(bf.hctl, bf.flags, sizeof(int) * T_INTS * col_tiles,
-                               hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(bf.hres, tres, sizeof(double) * col_tiles,
-                               hipMemcpyDeviceToHost, s));
+        if (!bf.mirror) {
+            SIC_HIP(hipMemcpyAsync(bf.hctl, bf.flags, sizeof(int) * T_INTS * col_tiles,
+                                   hipMemcpyDeviceToHost, s));
+            SIC_HIP(hipMemcpyAsync(bf.hres, tres, sizeof(double) * col_tiles,
+                                   hipMemcpyDeviceToHost, s));
+        }
         stream_wait(s);
         // a launch did work only for the tiles still iterating at its index:
         // scale its algorithmic bytes, drop launches that found nothing to do
@@ -752,7 +778,7 @@ CGResult block_cg(const DevCSR& A, const int32_t* d_cols, int k, double* W, int6
     wk.hres.reserve(col_tiles);
     const CsrView av{A.rowptr.p, A.col.p, A.val.p, A.n, A.nnz};
     CGBufs bf{wk.dinv.p, wk.vd.p, wk.part.p, wk.scal.p, wk.flags.p, wk.hctl.p, wk.hres.p,
-              &wk.predict[(slot & 3) * 2 + (low_precision ? 1 : 0)], true};
+              &wk.predict[(slot & 3) * 2 + (low_precision ? 1 : 0)], true, true};
     if (low_precision) {
         wk.R32.reserve(nk);
         wk.P32.reserve(nk);
@@ -848,7 +874,7 @@ CGResult block_cg_noalloc(const int64_t* rowptr, const int32_t* col, const doubl
     double hres[NOALLOC_MAX_TILES];
     int predicted = 0;
     const CsrView av{rowptr, col, val, n, nnz};
-    const CGBufs bf{dinv, vd, part, scal, flags, hctl, hres, &predicted, false};
+    const CGBufs bf{dinv, vd, part, scal, flags, hctl, hres, &predicted, false, false};
     return block_cg_impl<double>(av, d_cols, k, W, tol, max_iter, bf, R, P, Q, s);
 }
 

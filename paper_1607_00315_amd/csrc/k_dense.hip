@@ -331,12 +331,15 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(double* __restrict__ M, int
 // (leading dimension ldb). Blocked substitution over 16-row blocks: block i
 // of X is dinv_i (B_i - sum_{j<i} L_ij X_j) (forward) or
 // dinv_i^T (B_i - sum_{j>i} L_ji^T X_j) (backward). One workgroup solves
-// TS_COLS right-hand sides, held in LDS; thread (r, c) owns row r of the
-// current block in column c.
+// TS_COLS right-hand sides, held in LDS. The sum over j is a product on FP64
+// MFMA (16x16x4), its 16-column K blocks split over the four waves and the
+// partial sums added in a fixed order; wave 0 then applies dinv_i, also on
+// MFMA.
 constexpr int TS_COLS = 16;
 constexpr int TS_T = CB;   // the factor's diagonal-block size (dinv layout)
 constexpr int TS_THREADS = TS_COLS * TS_T;
 static_assert(TS_THREADS == TS_T * TS_T, "one diagonal-block entry per thread");
+static_assert(TS_THREADS == 4 * 64, "the partial sums are added as four waves");
 
 __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __restrict__ L, int nb,
                                                              int ldl, const double* __restrict__ dinv,
@@ -347,10 +350,13 @@ __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __res
     __shared__ double Ls[TS_T * CH_NB];   // the L entries of the current step (see below)
     __shared__ double As[TS_T][TS_COLS];
     __shared__ double Ds[TS_T * TS_T];    // inverse of the step's diagonal block
+    __shared__ double Part[TS_THREADS / 64][TS_T * TS_COLS];   // the waves' partial sums
     const int tid = threadIdx.x;
     const int r = tid / TS_COLS, c = tid % TS_COLS;
     const int col = blockIdx.x * TS_COLS + c;
     const bool con = col < ncols;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lr = lane >> 4, lc = lane & 15;   // MFMA operand lanes (as in k_chol)
     const int nt = (nb + TS_T - 1) / TS_T;
     for (int k = r; k < nt * TS_T; k += TS_T)
         Xs[k][c] = load_or(B, (int64_t)k * ldb + col, con && k < nb, 0.0);
@@ -386,30 +392,51 @@ __global__ __launch_bounds__(TS_THREADS) void k_trsm_blocked(const double* __res
         Ds[tid] = dv;
         __syncthreads();
         if (step + 1 < nt) load_step(trans ? nt - 2 - step : step + 1);
-        const int row = i * TS_T + r;
         const int k0 = trans ? (i + 1) * TS_T : 0;
-        double a[4] = {Xs[row][c], 0.0, 0.0, 0.0};
-        int q = 0;
-        for (; q + 8 <= kcnt; q += 8) {
-            double lv[8], xv[8];   // eight LDS reads in flight before the fmas
+        // partial sum of L_i. X over the K blocks jb = wave, wave + 4, ...: the
+        // A operand is Ls[q][m] (zero past kcnt), the B operand X[k0 + q][n]
+        const int nkb = (kcnt + TS_T - 1) / TS_T;
+        chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int jb = wave; jb < nkb; jb += TS_THREADS / 64) {
+            double av[4], bv[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                lv[u] = Ls[(q + u) * TS_T + r];
-                xv[u] = Xs[k0 + q + u][c];
+            for (int t = 0; t < 4; ++t) {
+                const int q = jb * TS_T + 4 * lr + t;
+                av[t] = Ls[q * TS_T + lc];
+                bv[t] = Xs[k0 + q][lc];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[u & 3] -= lv[u] * xv[u];
+            for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
         }
-        for (; q < kcnt; ++q) a[0] -= Ls[q * TS_T + r] * Xs[k0 + q][c];
-        As[r][c] = row < nb ? (a[0] + a[1]) + (a[2] + a[3]) : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Part[wave][(lr + 4 * v) * TS_COLS + lc] = acc[v];
         __syncthreads();
-        double x = 0.0;
-        if (!trans) {
-            for (int qq = 0; qq <= r; ++qq) x += Ds[r * TS_T + qq] * As[qq][c];
-        } else {
-            for (int qq = r; qq < TS_T; ++qq) x += Ds[qq * TS_T + r] * As[qq][c];
+        if (wave == 0) {
+            // A_i = B_i - the partial sums (rows lr + 4 v, column lc), then
+            // X_i = dinv_i A_i (dinv_i^T A_i backward) through As
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = lr + 4 * v, row = i * TS_T + rr;
+                const int o = rr * TS_COLS + lc;
+                const double s4 = (Part[0][o] + Part[1][o]) + (Part[2][o] + Part[3][o]);
+                As[rr][lc] = row < nb ? Xs[row][lc] - s4 : 0.0;
+            }
+            chol_d4 x = {0.0, 0.0, 0.0, 0.0};
+            double dv[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int q = 4 * lr + t;
+                dv[t] = trans ? Ds[q * TS_T + lc] : Ds[lc * TS_T + q];
+                bv[t] = As[q][lc];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) x = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[t], bv[t], x, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = i * TS_T + lr + 4 * v;
+                if (row < nb) Xs[row][lc] = x[v];
+            }
         }
-        if (row < nb) Xs[row][c] = x;
         __syncthreads();
     }
     if (con)

@@ -66,7 +66,8 @@ constexpr int CM_GROUPS = SCAN_THREADS / CM_COLS;
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* __restrict__ cnt,
                                                                 int tiles, int b,
                                                                 int32_t* __restrict__ offsets,
-                                                                int64_t* __restrict__ colptr) {
+                                                                int64_t* __restrict__ colptr,
+                                                                int64_t* __restrict__ total) {
     __shared__ int64_t part[CM_GROUPS][CM_COLS];
     __shared__ int64_t cs[CM_COLS];
     const int t = threadIdx.x;
@@ -109,7 +110,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* _
     int64_t run = c > 0 ? cs[c - 1] : 0;
     for (int q = 0; q < g; ++q) run += part[q][c];
     if (g == 0 && on) colptr[c] = run;
-    if (t == 0) colptr[b] = cs[b - 1];
+    if (t == 0) {
+        colptr[b] = cs[b - 1];
+        if (total) *total = cs[b - 1];
+    }
     for (int q0 = tile0; q0 < tile1; q0 += G) {
         int32_t v[G];
         gather(q0, v);
@@ -142,11 +146,11 @@ void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* to
 }
 
 void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets, int64_t* colptr,
-                          hipStream_t s) {
+                          int64_t* total, hipStream_t s) {
     if (b < 1 || b > CM_COLS || tiles < 1)
         throw SicError(SIC_EINTERNAL, "column-major scan: 1 <= b <= 256 and tiles >= 1 required");
     hipLaunchKernelGGL(k_scan_colmajor, dim3(1), dim3(SCAN_THREADS), 0, s, cnt, tiles, b, offsets,
-                       colptr);
+                       colptr, total);
     SIC_CHECK_LAUNCH();
 }
 

@@ -213,8 +213,9 @@ int cg_noalloc_max_k();
 
 // ---------------------------------------------------------------- k_util.hip
 void launch_scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* total, hipStream_t s);
+// total (may be null, or pinned host memory): colptr[b] written there as well
 void launch_scan_colmajor(const int32_t* cnt, int tiles, int b, int32_t* offsets, int64_t* colptr,
-                          hipStream_t s);
+                          int64_t* total, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 void launch_iota_i32(int32_t* p, int64_t count, int32_t start, hipStream_t s);
 // out (m x n row-major) = the columns perm[0..n) of X (m x n row-major)

@@ -39,9 +39,9 @@ struct BlockWork {
     // coordinates
     DevBuf<int64_t> cptr;
     DevBuf<int32_t> c_p, c_e, c_ci, c_gr, c_gc;
-    DevBuf<double> c_S, c_A, c_a, c_inva, c_wtc, c_wtt, delta, mu, cdstats;
+    DevBuf<double> c_S, c_A, c_a, c_inva, c_wtc, c_wtt, delta, mu;
     // line search
-    DevBuf<double> Dinv, Rb, D11, Mo, Y, Pm, T1, T2, D1, X, XtX, RPR, E1, E2, C, chol_out;
+    DevBuf<double> Dinv, Rb, D11, Mo, Y, Pm, T1, T2, D1, X, XtX, RPR, E1, E2, C;
     // coarse levels
     DevBuf<int32_t> cand_col, cflag, cmap, NC, err;
     DevBuf<double> S_cand, WNC, WII, Kb, AII;
@@ -131,9 +131,12 @@ struct Context {
     sic_trace_entry* trace = nullptr;
     int trace_cap = 0;
     // pinned staging for small device-to-host reads (64 entries each):
-    //   h_i64[0, 3) counts, [8] the rebuilt CSR's entry count, [16] the coarse-level
+    //   h_i64[0, 4) counts, [8] the rebuilt CSR's entry count, [16] the coarse-level
     //   error flag (int32); h_f64[0, 26) line-search trials, [32] the PCD stop
-    //   flag, [40, 48) sweep statistics, [48, 50) the coarse A_II factor's flags
+    //   flag, [40, 48) sweep statistics, [48, 50) the coarse A_II factor's flags.
+    //   Most are written by the producing kernels themselves (the memory is
+    //   mapped for the device), the rest by copies; either way the host reads
+    //   them after waiting for the stream.
     int64_t* h_i64 = nullptr;
     double* h_f64 = nullptr;
     BlockResult last;

@@ -109,6 +109,11 @@ void ensure_flags(Context& C, int64_t n, int b) {
     W.b_init = b;
 }
 
+// The line search's outputs, written by its kernels straight into pinned
+// staging: W_II's log det and PD flag, two per trial, then the trials' linear
+// terms (2 + 3 LS_BATCH doubles).
+double* ls_out(Context& C) { return C.h_f64; }
+
 struct LineSearch {
     double alpha = 0, dF = 0;
     int trials = 0;
@@ -125,15 +130,13 @@ void ls_reserve(Context& C, int b, int64_t nN) {
     W.RPR.reserve(bb); W.E1.reserve(bb); W.E2.reserve(bb);
     W.Y.reserve((size_t)std::max<int64_t>(nN, 1) * b);
     W.C.reserve(LS_BATCH * bb);
-    // chol_out: W_II's log det and PD flag, two per trial, then the trials' linear terms
-    W.chol_out.reserve(2 + 3 * LS_BATCH);
 }
 
 // R R^T = W_II (R lower, in W.Rb; its diagonal-block inverses in W.Dinv), on stream st.
 void ls_factor_wii(Context& C, int jp, int b, hipStream_t st) {
     BlockWork& W = C.work;
     launch_copy_block(W.WJJ.p, jp, b, W.Rb.p, st);
-    launch_chol(W.Rb.p, (int64_t)b * b, 1, b, b, 0, W.chol_out.p, st, W.Dinv.p);
+    launch_chol(W.Rb.p, (int64_t)b * b, 1, b, b, 0, ls_out(C), st, W.Dinv.p);
     launch_zero_upper(W.Rb.p, b, b, st);
 }
 
@@ -144,11 +147,11 @@ void ls_factor_wii(Context& C, int jp, int b, hipStream_t st) {
 void ls_prepare(Context& C, int jp, int b, int64_t nN, bool factored) {
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
-    // the side stream may still be factoring W_II into Rb / chol_out / Dinv:
-    // those were sized before the fork, and sizing them again must not move them
-    const void* held[3] = {W.Rb.p, W.chol_out.p, W.Dinv.p};
+    // the side stream may still be factoring W_II into Rb / Dinv: those were
+    // sized before the fork, and sizing them again must not move them
+    const void* held[2] = {W.Rb.p, W.Dinv.p};
     ls_reserve(C, b, nN);
-    if (factored && (held[0] != W.Rb.p || held[1] != W.chol_out.p || held[2] != W.Dinv.p))
+    if (factored && (held[0] != W.Rb.p || held[1] != W.Dinv.p))
         throw SicError(SIC_EINTERNAL, "a buffer of the side stream moved before its join");
     if (factored)
         SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
@@ -182,14 +185,12 @@ bool ls_eval(Context& C, int b, int64_t ncoord, double lam, int first, int nt,
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
     const size_t bb = (size_t)b * b;
-    double* dlin = W.chol_out.p + 2 + 2 * LS_BATCH;
+    double* h_out = ls_out(C);
+    double* dlin = h_out + 2 + 2 * LS_BATCH;
     launch_ls_trials(W.E1.p, W.E2.p, b, first, nt, W.C.p, s);
-    launch_chol(W.C.p, (int64_t)bb, nt, b, b, 1, W.chol_out.p + 2, s);
+    launch_chol(W.C.p, (int64_t)bb, nt, b, b, 1, h_out + 2, s);
     launch_ls_linear(ncoord, W.c_p.p, W.c_ci.p, W.c_S.p, W.c_A.p, W.delta.p, lam, first, nt,
                      dlin, s);
-    double* h_out = C.h_f64;   // 2 + 3 LS_BATCH doubles of the pinned staging
-    SIC_HIP(hipMemcpyAsync(h_out, W.chol_out.p, sizeof(double) * (2 + 3 * LS_BATCH),
-                           hipMemcpyDeviceToHost, s));
     sync(C);
     for (int t = 0; t < nt; ++t) {
         logdet[t] = h_out[2 + 2 * t];
@@ -559,29 +560,33 @@ static void cov_block(Context& C, Problem& P, int64_t j0, int b, double* out, hi
         launch_sj_gemm_f64(P.X.p, P.n, P.m, j0, b, out, st);
 }
 
+// The sweep statistics (8 doubles), written by the CD kernels straight into
+// pinned staging.
+static double* cd_stats(Context& C) { return C.h_f64 + 40; }
+
 static int64_t run_cd(Context& C, int jp, int b, int64_t nc, double lam, int max_sweeps,
                       double tol) {
     BlockWork& W = C.work;
     hipStream_t s = C.stream;
-    W.cdstats.reserve(8);
+    double* stats = cd_stats(C);
     if (nc > 0 && C.opt.pcd_min_coords > 0 && nc >= C.opt.pcd_min_coords)
         return launch_pcd(nc, jp, b, W.cptr.p, W.c_p.p, W.c_ci.p, W.c_S.p, W.c_A.p, W.c_wtc.p,
                           W.c_inva.p, W.WJJ.p, lam, 10 * max_sweeps, tol, W.delta.p,
-                          W.pcd, W.cdstats.p, C.h_f64 + 32, s);
+                          W.pcd, stats, C.h_f64 + 32, s);
     if (nc > 0 && nc <= C.opt.cd_hessian_max && nc <= cd_hessian_limit() &&
         cd_hessian_lds_bytes(nc) <= CD_MAX_LDS_BYTES) {
         W.HT.reserve((size_t)nc * nc);
         W.cdx.reserve(cd_exchange_doubles());
         return launch_cd_hessian(nc, jp, W.c_p.p, W.c_ci.p, W.WJJ.p, W.c_S.p, W.c_A.p,
                                  W.c_inva.p, W.c_wtc.p, lam, max_sweeps, tol, W.HT.p, W.delta.p,
-                                 W.cdstats.p, W.cdx.p, s, C.prec != PREC_F64);
+                                 stats, W.cdx.p, s, C.prec != PREC_F64);
     }
     W.U.reserve((size_t)jp * b);
     W.ug.reserve(jp);
     W.markg.reserve(jp);
     SIC_HIP(hipMemsetAsync(W.U.p, 0, sizeof(double) * jp * b, s));
     launch_cd(jp, b, W.cptr.p, W.c_p.p, W.c_S.p, W.c_A.p, W.c_inva.p, W.c_wtc.p, W.WJJ.p, lam,
-              max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, W.cdstats.p, s);
+              max_sweeps, tol, W.U.p, W.delta.p, W.mu.p, W.ug.p, W.markg.p, stats, s);
     return -1;
 }
 
@@ -630,7 +635,7 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
                            W.tilecount.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                            W.nflag.p, W.kkt.p, s);
         if (record) launch_kkt_accumulate(W.kkt.p, tiles, W.kkt_acc.p, s);
-        launch_scan_colmajor(W.tilecount.p, tiles, b, W.offsets.p, W.colptr.p, s);
+        launch_scan_colmajor(W.tilecount.p, tiles, b, W.offsets.p, W.colptr.p, C.h_i64 + 2, s);
         reserve_free_lists(W, nb);
         launch_screen_fine(1, n, j0, b, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, W.WI.p, W.AJ.p,
                            W.tilecount.p, W.offsets.p, W.e_row.p, W.e_g.p, W.e_s.p, W.e_a.p,
@@ -647,19 +652,20 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
         const size_t bb = (size_t)b * b;
         W.Kb.reserve(bb); W.AII.reserve(bb); W.WII.reserve(bb); W.Dinv.reserve(8 * 1024);
         W.err.reserve(1);
-        W.chol_out.reserve(2 + 3 * LS_BATCH);
+        double* h = C.h_f64 + 48;   // A_II's log det and PD flag, written by the factor
         SIC_HIP(hipEventRecord(C.ev_fork, s));
         SIC_HIP(hipStreamWaitEvent(C.side, C.ev_fork, 0));
         launch_dense_aii(A, j0, b, W.AII.p, C.side);
-        launch_chol(W.AII.p, (int64_t)bb, 1, b, b, 0, W.chol_out.p, C.side, W.Dinv.p);
+        launch_chol(W.AII.p, (int64_t)bb, 1, b, b, 0, h, C.side, W.Dinv.p);
         launch_zero_upper(W.AII.p, b, b, C.side);
         SIC_HIP(hipEventRecord(C.ev_join, C.side));
         launch_expand_cand(P.crow.p, j0, b, base, W.cand_col.p, s);
         launch_sddmm(P.Xt.p, P.m, P.ccol.p + base, W.cand_col.p, cnt, W.S_cand.p, s);
         launch_flag_cand(P.ccol.p, base, cnt, j0, b, W.cflag.p, s);
         W.scan_n.reserve(n + 1);
-        launch_scan_i32(W.cflag.p, n, W.scan_n.p, nullptr, s);
-        nC = read_i64(C, W.scan_n.p + n);
+        launch_scan_i32(W.cflag.p, n, W.scan_n.p, C.h_i64 + 3, s);
+        sync(C);
+        nC = C.h_i64[3];
         R.nC = nC;
         W.NC.reserve(std::max<int64_t>(nC, 1));
         launch_flag_compact(W.cflag.p, W.scan_n.p, n, W.NC.p, W.cmap.p, s);
@@ -677,9 +683,7 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
         SIC_HIP(hipStreamWaitEvent(s, C.ev_join, 0));
         launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 0, s);
         launch_trsm_lower(W.AII.p, b, b, W.Dinv.p, W.WII.p, b, b, 1, s);
-        double* h = C.h_f64 + 48;                          // pinned staging
         int32_t* herr = reinterpret_cast<int32_t*>(C.h_i64 + 16);
-        SIC_HIP(hipMemcpyAsync(h, W.chol_out.p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
         SIC_HIP(hipMemcpyAsync(herr, W.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         sync(C);
         if (*herr) throw SicError(SIC_EINTERNAL, "support of A is not inside the level set");
@@ -687,7 +691,7 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
         launch_screen_coarse(0, P.crow.p, P.ccol.p, base, j0, b, P.lam, W.S_cand.p, W.WII.p,
                              W.WNC.p, nC, W.cmap.p, W.AJ.p, W.ccount.p, nullptr, nullptr, nullptr,
                              nullptr, nullptr, nullptr, W.nflag.p, s);
-        launch_scan_i32(W.ccount.p, b, W.colptr.p, nullptr, s);
+        launch_scan_i32(W.ccount.p, b, W.colptr.p, C.h_i64 + 2, s);
         reserve_free_lists(W, nb);
         launch_screen_coarse(1, P.crow.p, P.ccol.p, base, j0, b, P.lam, W.S_cand.p, W.WII.p,
                              W.WNC.p, nC, W.cmap.p, W.AJ.p, W.ccount.p, W.colptr.p, W.e_row.p,
@@ -697,15 +701,14 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
     // coordinate count come back in one read (J' is sized for b + n, past any
     // count the flags can give)
     W.scan_n.reserve(n + 1);
-    launch_scan_i32(W.nflag.p, n, W.scan_n.p, nullptr, s);
+    launch_scan_i32(W.nflag.p, n, W.scan_n.p, C.h_i64, s);
     W.Jp.reserve(n + b);
     launch_nbr_compact(W.nflag.p, W.scan_n.p, n, j0, b, W.Jp.p, W.lmap.p, s);
     W.cptr.reserve(b + 1);
     launch_coord_count(W.colptr.p, W.e_row.p, j0, b, W.ccount.p, s);
-    launch_scan_i32(W.ccount.p, b, W.cptr.p, nullptr, s);
-    SIC_HIP(hipMemcpyAsync(C.h_i64, W.scan_n.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    SIC_HIP(hipMemcpyAsync(C.h_i64 + 1, W.cptr.p + b, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    SIC_HIP(hipMemcpyAsync(C.h_i64 + 2, W.colptr.p + b, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    launch_scan_i32(W.ccount.p, b, W.cptr.p, C.h_i64 + 1, s);
+    // |N|, the coordinate count and E = colptr[b] were written by the scans
+    // straight into pinned staging
     sync(C);
     R.nN = C.h_i64[0];
     R.ncoord = C.h_i64[1];
@@ -756,13 +759,11 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
         launch_sddmm(P.Xt.p, P.m, W.c_gr.p, W.c_gc.p, nc, W.c_S.p, s);
     }
     const int64_t cd_rec = run_cd(C, jp, b, nc, P.lam, C.opt.cd_max_sweeps, C.opt.cd_tol);
-    // the sweep statistics go to pinned staging: the copy does not hold the host,
-    // and the line search's first read-back waits for it
-    double* h_cds = C.h_f64 + 40;
-    SIC_HIP(hipMemcpyAsync(h_cds, W.cdstats.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
+    // the sweep statistics are in pinned staging once the line search's first
+    // read-back has waited for the stream
+    const double* h_cds = cd_stats(C);
     // (e) line search
-    LineSearch ls = line_search(C, P.lam, jp, b, nN, nc, true);
-    sync(C);   // (no-op when the line search ended on a read-back)
+    LineSearch ls = line_search(C, P.lam, jp, b, nN, nc, true);   // ends on its read-back
     double cds[8];
     std::copy(h_cds, h_cds + 8, cds);
     if (cds[7] != 0.0) throw SicError(SIC_EINTERNAL, "CD sweep workgroups timed out waiting on one another");
@@ -796,11 +797,9 @@ static BlockResult block_update_body(Context& C, Problem& P, int64_t j0, int b, 
                            W.ANEW.p, s);
         launch_upd_rows(0, n, j0, b, A, W.lmap.p, W.cptr.p, W.c_p.p, W.Jp.p, W.ANEW.p, W.rcount.p,
                         nullptr, nullptr, nullptr, s);
-        launch_scan_i32(W.rcount.p, n, An.rowptr.p, nullptr, s);
-        // the new entry count is read at the block's closing synchronisation;
-        // the fill pass writes nothing at or beyond cap meanwhile
-        SIC_HIP(hipMemcpyAsync(C.h_i64 + 8, An.rowptr.p + n, sizeof(int64_t),
-                               hipMemcpyDeviceToHost, s));
+        // the new entry count goes straight to pinned staging, read at the block's
+        // closing synchronisation; the fill pass writes nothing at or beyond cap
+        launch_scan_i32(W.rcount.p, n, An.rowptr.p, C.h_i64 + 8, s);
         new_nnz_pending = true;
         new_cap = cap;
         launch_upd_rows(1, n, j0, b, A, W.lmap.p, W.cptr.p, W.c_p.p, W.Jp.p, W.ANEW.p, W.rcount.p,
@@ -916,8 +915,9 @@ void initial_free_set(Context& C, Problem& P) {
         launch_screen_fine(0, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, nullptr, W.AJ.p,
                            W.tilecount.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                            W.nflag.p, W.kkt.p, s);
-        launch_scan_colmajor(W.tilecount.p, tiles, bb, W.offsets.p, W.colptr.p, s);
-        const int64_t E = read_i64(C, W.colptr.p + bb);
+        launch_scan_colmajor(W.tilecount.p, tiles, bb, W.offsets.p, W.colptr.p, C.h_i64, s);
+        sync(C);
+        const int64_t E = C.h_i64[0];
         const size_t Es = (size_t)std::max<int64_t>(E, 1);
         W.e_row.reserve(Es); W.e_g.reserve(Es); W.e_s.reserve(Es); W.e_a.reserve(Es); W.e_w.reserve(Es);
         launch_screen_fine(1, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, nullptr, W.AJ.p,
@@ -1329,9 +1329,9 @@ int step_cd_impl(Context& C, int jp, int b, const double* wjj, const int64_t* cp
     const int64_t nc = cptr[b];
     const int64_t cd_rec = run_cd(C, jp, b, nc, lambda, max_sweeps, tol);
     if (nc) SIC_HIP(hipMemcpyAsync(delta_out, W.delta.p, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-    double st[8];
-    SIC_HIP(hipMemcpyAsync(st, W.cdstats.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
     sync(C);
+    double st[8];
+    std::copy(cd_stats(C), cd_stats(C) + 8, st);
     if (st[7] != 0.0) throw SicError(SIC_EINTERNAL, "CD sweep workgroups timed out waiting on one another");
     prof_scale(cd_rec, st[0]);
     if (stats_out) std::copy(st, st + 7, stats_out);

@@ -42,9 +42,12 @@ FP64_PEAK_TFS = 78.6
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB reference copy; valid only
 # while the kernel's source is the one measured (sha256 prefix of the file).
 PMC_TRAFFIC = {
-    "cd": dict(source="paper_1607_00315_amd/csrc/k_cd.hip", sha256="d11ab77cb73ce5a8",
-               fetch=57621609.0, write=6710.0,
+    "cd": dict(source="paper_1607_00315_amd/csrc/k_cd.hip", sha256="6e44e0aa25c2da1b",
+               fetch=9988540.0, write=134411.0,
                profile="profiles/cd_grid_n10000_m5000_pmc.md"),
+    "chol": dict(source="paper_1607_00315_amd/csrc/k_dense.hip", sha256="53072a36c5a8f075",
+                 fetch=2102017.0, write=1888180.0,
+                 profile="profiles/cd_grid_n10000_m5000_pmc.md"),
 }
 
 
@@ -505,10 +508,12 @@ def main():
         dom, k, full = kern["dom"], kern["live"], kern["full"]
         total = sum(v["ms"] for v in full.values())
         avg_ms = k["ms"] / max(k["launches"], 1)
-        if dom == "sj_gemm_f64":
+        if dom in ("sj_gemm_f64", "chol", "gemm_small", "trsm"):
+            # FP64 MFMA contractions (the Cholesky and triangular solves are
+            # latency chains on one workgroup per matrix: their fraction is small)
             ach = k["flops"] / max(k["launches"], 1) / (avg_ms * 1e-3) / 1e12
             roofline = dict(kernel=dom, bound="mfma", achieved=ach, peak=FP64_PEAK_TFS,
-                            unit="TFLOP/s", frac=ach / FP64_PEAK_TFS, traffic=None)
+                            unit="TFLOP/s", frac=ach / FP64_PEAK_TFS, traffic=pmc_traffic(dom))
         else:
             ach = k["bytes"] / max(k["launches"], 1) / (avg_ms * 1e-3) / 1e9
             roofline = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,

@@ -564,8 +564,9 @@ constexpr int CDP_CONST = 4 * CDH_K;   // a chunk's 1/a, A, S and W_rc, staged w
 //   workgroup 0, interval g: z starts from snapshot(g), plus the steps of
 //              interval g-2 on chunk g (formed by waves 1-8 during interval
 //              g-1 from the tile H[chunk g][chunk g-2]), plus those of g-1
-//              (from the staged tile H[chunk g][chunk g-1], a quarter on each
-//              of waves 0-3); wave 0 then runs the chain; waves 1-15 stage the next interval's tiles, form the g-1
+//              (accumulated by wave 0 during the chain of interval g-1 from
+//              the tile H[chunk g][chunk g-1], staged with that interval's
+//              tiles); wave 0 then runs the chain; waves 1-15 stage the next interval's tiles, form the g-1
 //              contribution for chunk g+1, wave 9 fetches snapshot(g+1) and
 //              wave 10 publishes the step list of interval g-1.
 // z_k is then sum_t H[k][t] Delta_t summed by interval, and the chain and its
@@ -624,7 +625,7 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
                           double* __restrict__ xb, double* sm) {
     double* ds = sm;                            // [nc]
     double* Dt = ds + nc;                       // [2][64 x 64] H[chunk g][chunk g], [t][k]
-    double* St = Dt + 2 * CDP_TILE;             // [2][64 x 64] H[chunk g][chunk g-1], [t][k]
+    double* St = Dt + 2 * CDP_TILE;             // [2][64 x 64] H[chunk g+1][chunk g], [t][k]
     double* mud = St + 2 * CDP_TILE;            // [2][64] steps of the interval (0 past K)
     double* cst = mud + 2 * CDH_K;              // [2][4][64] the chunk's 1/a, A, S, W_rc
     double* zp = cst + 2 * CDP_CONST;           // [2][CDM_PW + 1][64] parts of the chunk's z
@@ -642,13 +643,14 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
         const int64_t r = nc - (int64_t)c * CDH_K;
         return (int)(r < CDH_K ? r : CDH_K);
     };
-    // waves 1-15: the tiles of chunk ci (and its predecessor cp) and the
-    // constants of chunk ci, into registers, then into LDS buffer b
+    // waves 1-15: the tiles H[ci][ci] and H[cr][ci] (rows of chunk cr, the
+    // one after ci) and the constants of chunk ci, into registers, then into
+    // LDS buffer b
     constexpr int TPT = (2 * CDP_TILE + CDP_CONST + (CDM_THREADS - 64) - 1) / (CDM_THREADS - 64);
     double treg[TPT];
-    auto load_tiles = [&](int ci, int cp) {
-        const int64_t ki = (int64_t)ci * CDH_K, kp = (int64_t)cp * CDH_K;
-        const int Ki = klen(ci), Kp = klen(cp);
+    auto load_tiles = [&](int ci, int cr) {
+        const int64_t ki = (int64_t)ci * CDH_K, kr = (int64_t)cr * CDH_K;
+        const int Ki = klen(ci), Kr = klen(cr);
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
             const int e = (tid - 64) + (CDM_THREADS - 64) * r;
@@ -656,9 +658,10 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
             const int which = e / CDP_TILE, f = e % CDP_TILE;
             const int t = f / CDH_K, k = f % CDH_K;
             const bool dtile = which == 0;
-            const int64_t col = (dtile ? ki : kp) + t;
-            const bool ok = is_tile && k < Ki && (dtile ? t < Ki : t < Kp);
-            const double tv = load_or(HT, col * nc + ki + k, ok, 0.0);
+            // entry [t][k]: H[row k of chunk ci (Dt) or cr (St)][column t of chunk ci]
+            const int64_t rbase = dtile ? ki : kr;
+            const bool ok = is_tile && t < Ki && (dtile ? k < Ki : k < Kr);
+            const double tv = load_or(HT, (ki + t) * nc + rbase + k, ok, 0.0);
             const int g = e - 2 * CDP_TILE, gw = g / CDH_K, gk = g % CDH_K;
             const double* src = gw == 0 ? c_inva : (gw == 1 ? c_A : (gw == 2 ? c_S : c_wtc));
             const double cv = load_or(src, ki + gk, !is_tile && g < CDP_CONST && gk < Ki, 0.0);
@@ -681,7 +684,7 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
     for (int64_t k = tid; k < nc; k += CDM_THREADS) ds[k] = 0.0;
     for (int e = tid; e < 2 * (CDM_PW + 1) * CDH_K; e += CDM_THREADS) zp[e] = 0.0;
     if (wave > 0) {
-        load_tiles(0, C - 1);
+        load_tiles(0, 1 % C);
         store_tiles(0);
     }
     if (wave == 0) __builtin_amdgcn_s_setprio(3);   // the chain is the critical path
@@ -696,42 +699,23 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
 
     int sweeps = 0;
     double maxmu = 0.0;   // wave 0
+    double zcarry = 0.0;  // wave 0: the steps of the last chain on the rows of the next chunk
     int64_t g = 0;
     bool done = false;
     for (int sweep = 0; sweep < max_sweeps && !done; ++sweep) {
         for (int i = 0; i < C; ++i, ++g) {
             const int b = (int)(g & 1), pb = 1 - b;
             const int K = klen(i);
-            // z of this chunk's rows, in two stages: waves 0-3 each apply a quarter
-            // of the steps of interval g-1 (tile rows 16 w .. 16 w + 15) and add
-            // two of the parts of interval g-2 (wave 0 also the snapshot) into
-            // part slot 2 w; after the barrier wave 0 adds the four slots
-            double* zb = zp + b * (CDM_PW + 1) * CDH_K;
-            if (wave < 4) {
-                double a0 = zb[(2 * wave) * CDH_K + lane] + zb[(2 * wave + 1) * CDH_K + lane];
-                if (wave == 0) a0 = zb[CDM_PW * CDH_K + lane] + a0;
-                if (g > 0 && s_nnz[pb] > 0) {
-                    const double* st = St + b * CDP_TILE + (16 * wave) * CDH_K;
-                    const double* pm = mud + pb * CDH_K + 16 * wave;
-                    double sv[16], mv[16];
-#pragma unroll
-                    for (int u = 0; u < 16; ++u) {
-                        sv[u] = st[u * CDH_K + lane];
-                        mv[u] = pm[u];
-                    }
-                    double ac[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int u = 0; u < 16; ++u) ac[u & 3] += sv[u] * mv[u];
-                    a0 += (ac[0] + ac[1]) + (ac[2] + ac[3]);
-                }
-                zb[(2 * wave) * CDH_K + lane] = a0;
-            }
-            lds_barrier();
             if (wave == 0) {
                 if (i == 0) maxmu = 0.0;
                 const bool on = lane < K;
                 const int kl = on ? i * CDH_K + lane : i * CDH_K;
-                double z = (zb[lane] + zb[2 * CDH_K + lane]) + (zb[4 * CDH_K + lane] + zb[6 * CDH_K + lane]);
+                // z: the steps of interval g-1 (accumulated during its chain), the
+                // snapshot, then the parts of interval g-2 in wave order
+                const double* zb = zp + b * (CDM_PW + 1) * CDH_K;
+                double z = zcarry + zb[CDM_PW * CDH_K + lane];
+#pragma unroll
+                for (int w = 0; w < CDM_PW; ++w) z += zb[w * CDH_K + lane];
                 z = on ? z : 0.0;
                 if (tid == 0) { const long long now = wall_clock64(); s_tph[0] += now - s_tph[3]; s_tph[3] = now; }
                 const double* cb = cst + b * CDP_CONST;
@@ -740,25 +724,38 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
                 const double xl = on ? cb[CDH_K + lane] + d0 : 0.0;
                 const double pv = on ? xl - (cb[2 * CDH_K + lane] - cb[3 * CDH_K + lane]) * ia : 0.0;
                 const double* dt = Dt + b * CDP_TILE;
+                const double* sn = St + b * CDP_TILE;
                 const int K4 = (K + 3) & ~3;
                 // The chain, one coordinate per step in the stored order. With
                 // q = p - x, a = q - lam/a - z/a and b = q + lam/a - z/a, the step
                 // mu = soft(p - z/a, lam/a) - x is the median of a, -x and b
                 // (a <= b). Every lane evaluates it for its own coordinate at the
                 // current z; lane t's value is step t: broadcast (two readlanes),
-                // applied to every z and kept in lane t.
+                // applied to every z and kept in lane t. The same step goes into
+                // zn, the next chunk's rows (tile H[next][this]), off the chain's
+                // dependency path: the next interval starts from it.
                 const double qlo = pv - xl - lam * ia, qhi = pv - xl + lam * ia, nx = -xl;
                 int mlo = 0, mhi = 0;
-                double hN[4];
+                double zn = 0.0;
+                double hN[4], sN[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) hN[u] = dt[u * CDH_K + lane];
+                for (int u = 0; u < 4; ++u) {
+                    hN[u] = dt[u * CDH_K + lane];
+                    sN[u] = sn[u * CDH_K + lane];
+                }
                 for (int tt = 0; tt < K4; tt += 4) {
-                    double hC[4];
+                    double hC[4], sC[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) hC[u] = hN[u];
+                    for (int u = 0; u < 4; ++u) {
+                        hC[u] = hN[u];
+                        sC[u] = sN[u];
+                    }
                     const int tn = tt + 4 < CDH_K ? tt + 4 : CDH_K - 4;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) hN[u] = dt[(tn + u) * CDH_K + lane];
+                    for (int u = 0; u < 4; ++u) {
+                        hN[u] = dt[(tn + u) * CDH_K + lane];
+                        sN[u] = sn[(tn + u) * CDH_K + lane];
+                    }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int t = tt + u;
@@ -769,10 +766,12 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
                         const double mu =
                             __longlong_as_double(((long long)shi << 32) | (unsigned int)slo);
                         z += mu * hC[u];
+                        zn += mu * sC[u];
                         mlo = lane == t ? slo : mlo;
                         mhi = lane == t ? shi : mhi;
                     }
                 }
+                zcarry = zn;
                 double mul = __longlong_as_double(((long long)mhi << 32) | (unsigned int)mlo);
                 mul = on ? mul : 0.0;
                 maxmu = fmax(maxmu, wave_max(fabs(mul)));
@@ -794,7 +793,7 @@ __device__ void cdm_chain(int64_t nc, const HV* __restrict__ HT, const double* _
                 if (tid == 0) { const long long now = wall_clock64(); s_tph[1] += now - s_tph[3]; s_tph[3] = now; }
             } else {
                 const int cn = (i + 1) % C;                  // the next interval's chunk
-                load_tiles(cn, i);
+                load_tiles(cn, (i + 2) % C);
                 double* zn = zp + pb * (CDM_PW + 1) * CDH_K;
                 if (wave <= CDM_PW) {
                     // steps of interval g-1 on the rows of chunk cn: tile rows t of

@@ -31,17 +31,25 @@ constexpr int SJ_PAD = 4;
 // dispatch). Each XCD takes every eighth 64-row slab and runs the slab's
 // column tiles one after another, so the slab of X they all read is fetched
 // into that XCD's L2 once instead of once per column tile.
+// ks (1 or 2) splits the samples of every tile between ks workgroups (the
+// grid has 2.5 tiles per compute unit otherwise, unevenly spread). With two,
+// both halves are added atomically into the zeroed output: 0 + a + b is a + b
+// exactly in either order, so the result does not depend on which lands first.
 __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ X, int64_t n,
                                                      int64_t m, int64_t j0, int b,
                                                      double* __restrict__ out, double invm,
-                                                     int row_tiles, int col_tiles) {
+                                                     int row_tiles, int col_tiles, int ks) {
     // two LDS buffers by round parity: the next round's samples are loaded
     // from memory while the MFMAs run on this round's, and stored after them
     __shared__ double sA[2][SJ_KC][SJ_TILE + SJ_PAD];
     __shared__ double sB[2][SJ_KC][SJ_TILE + SJ_PAD];
     const int L = blockIdx.x, xcd = L & 7, slot = L >> 3;
-    const int rt = (slot / col_tiles) * 8 + xcd, ct = slot % col_tiles;
+    const int rt = (slot / (col_tiles * ks)) * 8 + xcd, rem = slot % (col_tiles * ks);
+    const int ct = rem % col_tiles, half = rem / col_tiles;
     if (rt >= row_tiles) return;
+    // this workgroup's samples [kbeg, kend): whole rounds, the last split ragged
+    const int64_t mk = ((m + ks - 1) / ks + SJ_KC - 1) / SJ_KC * SJ_KC;
+    const int64_t kbeg = half * mk, kend = kbeg + mk < m ? kbeg + mk : m;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -54,35 +62,36 @@ __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ 
     double4_t acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int bb = 0; bb < 2; ++bb) acc[a][bb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    // The next round's loads go out before this round's MFMAs; entries past
+    // the matrix read element 0 and are zeroed only when staged, since a
+    // select next to the load would wait for it there.
     double ra[4], rb[4];
     auto load = [&](int64_t r0) {
         const int64_t r = r0 + lr;
-        const bool rok = r < m;
+        const bool rok = r < kend;
         const double* xrow = X + (rok ? r : 0) * n;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t ia = i0 + lc + q;
             const int cb = c0 + lc + q;
-            const bool oka = rok && ia < n, okb = rok && cb < b;
-            const double va = xrow[oka ? ia : 0];
-            const double vb = xrow[okb ? j0 + cb : 0];
-            ra[q] = oka ? va : 0.0;
-            rb[q] = okb ? vb : 0.0;
+            ra[q] = xrow[rok && ia < n ? ia : 0];
+            rb[q] = xrow[rok && cb < b ? j0 + cb : 0];
         }
     };
-    auto stage = [&](int buf) {
+    auto stage = [&](int buf, int64_t r0) {
+        const bool rok = r0 + lr < kend;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            sA[buf][lr][lc + q] = ra[q];
-            sB[buf][lr][lc + q] = rb[q];
+            sA[buf][lr][lc + q] = rok && i0 + lc + q < n ? ra[q] : 0.0;
+            sB[buf][lr][lc + q] = rok && c0 + lc + q < b ? rb[q] : 0.0;
         }
     };
-    load(0);
-    stage(0);
+    load(kbeg);
+    stage(0, kbeg);
     __syncthreads();
     int buf = 0;
-    for (int64_t r0 = 0; r0 < m; r0 += SJ_KC) {
-        const bool more = r0 + SJ_KC < m;
+    for (int64_t r0 = kbeg; r0 < kend; r0 += SJ_KC) {
+        const bool more = r0 + SJ_KC < kend;
         if (more) load(r0 + SJ_KC);
 #pragma unroll
         for (int kk = 0; kk < SJ_KC; kk += 4) {
@@ -98,7 +107,7 @@ __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ 
                 for (int bb = 0; bb < 2; ++bb)
                     acc[a][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[bb], acc[a][bb], 0, 0, 0);
         }
-        if (more) stage(buf ^ 1);
+        if (more) stage(buf ^ 1, r0 + SJ_KC);
         __syncthreads();
         buf ^= 1;
     }
@@ -110,7 +119,10 @@ __global__ __launch_bounds__(256) void k_sj_gemm_f64(const double* __restrict__ 
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * v;
                 const int c = c0 + wc * 32 + bb * 16 + (lane & 15);
-                if (i < n && c < b) out[i * b + c] = acc[a][bb][v] * invm;
+                if (i < n && c < b) {
+                    if (ks == 1) out[i * b + c] = acc[a][bb][v] * invm;
+                    else unsafeAtomicAdd(out + i * b + c, acc[a][bb][v] * invm);
+                }
             }
 }
 
@@ -124,41 +136,70 @@ typedef short short4_t __attribute__((ext_vector_type(4)));
 
 constexpr int SJR_KC = 32;    // samples staged per LDS round
 constexpr int SJR_PAD = 4;
+constexpr int SJR_TPAD = 4;   // bfloat16 staging: [column][sample] rows of SJR_KC + 4 (8-byte aligned)
 
+// Tiles, XCD order, sample split (ks = 1 or 2, atomically added) and double
+// buffering as in k_sj_gemm_f64. bfloat16 samples are staged transposed,
+// [column][sample], so the four consecutive samples a lane supplies to the
+// MFMA are one 8-byte LDS read; float samples [sample][column].
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_sj_gemm_low(const void* __restrict__ Xv, int64_t n,
                                                      int64_t m, int64_t j0, int b,
-                                                     double* __restrict__ out, double invm) {
+                                                     double* __restrict__ out, double invm,
+                                                     int row_tiles, int col_tiles, int ks) {
     typedef typename std::conditional<BF16, unsigned short, float>::type E;
     const E* __restrict__ X = (const E*)Xv;
-    __shared__ E sA[SJR_KC][SJ_TILE + SJR_PAD];
-    __shared__ E sB[SJR_KC][SJ_TILE + SJR_PAD];
+    constexpr int RS = BF16 ? SJR_KC + SJR_TPAD : SJ_TILE + SJR_PAD;   // LDS row stride
+    constexpr int NR = BF16 ? SJ_TILE : SJR_KC;                         // LDS rows
+    __shared__ __attribute__((aligned(16))) E sA[2][NR * RS];
+    __shared__ __attribute__((aligned(16))) E sB[2][NR * RS];
+    auto at = [](int k, int col) { return BF16 ? col * RS + k : k * RS + col; };
+    const int L = blockIdx.x, xcd = L & 7, slot = L >> 3;
+    const int rt = (slot / (col_tiles * ks)) * 8 + xcd, rem = slot % (col_tiles * ks);
+    const int ct = rem % col_tiles, half = rem / col_tiles;
+    if (rt >= row_tiles) return;
+    const int64_t mk = ((m + ks - 1) / ks + SJR_KC - 1) / SJR_KC * SJR_KC;
+    const int64_t kbeg = half * mk, kend = kbeg + mk < m ? kbeg + mk : m;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int64_t i0 = (int64_t)blockIdx.x * SJ_TILE;
-    const int c0 = blockIdx.y * SJ_TILE;
-    // loader: 32 rows x 64 columns, 8 consecutive elements per thread
+    const int64_t i0 = (int64_t)rt * SJ_TILE;
+    const int c0 = ct * SJ_TILE;
+    // loader: 32 samples x 64 columns, 8 consecutive columns per thread
     const int lr = tid >> 3;          // 0..31
     const int lc = (tid & 7) * 8;     // 0..56
     float4_t acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int bb = 0; bb < 2; ++bb) acc[a][bb] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    for (int64_t r0 = 0; r0 < m; r0 += SJR_KC) {
+    E ra[8], rb[8];
+    auto load = [&](int64_t r0) {   // raw values; entries past the matrix read element 0
         const int64_t r = r0 + lr;
-        const bool rok = r < m;
+        const bool rok = r < kend;
         const E* xrow = X + (rok ? r : 0) * n;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t ia = i0 + lc + q;
             const int cb = c0 + lc + q;
-            const E va = xrow[(rok && ia < n) ? ia : 0];
-            const E vb = xrow[(rok && cb < b) ? j0 + cb : 0];
-            sA[lr][lc + q] = (rok && ia < n) ? va : (E)0;
-            sB[lr][lc + q] = (rok && cb < b) ? vb : (E)0;
+            ra[q] = xrow[rok && ia < n ? ia : 0];
+            rb[q] = xrow[rok && cb < b ? j0 + cb : 0];
         }
-        __syncthreads();
+    };
+    auto stage = [&](int buf, int64_t r0) {   // masked here, after the MFMAs
+        const bool rok = r0 + lr < kend;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            sA[buf][at(lr, lc + q)] = rok && i0 + lc + q < n ? ra[q] : (E)0;
+            sB[buf][at(lr, lc + q)] = rok && c0 + lc + q < b ? rb[q] : (E)0;
+        }
+    };
+    load(kbeg);
+    stage(0, kbeg);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t r0 = kbeg; r0 < kend; r0 += SJR_KC) {
+        const bool more = r0 + SJR_KC < kend;
+        if (more) load(r0 + SJR_KC);
         if constexpr (BF16) {
 #pragma unroll
             for (int kk = 0; kk < SJR_KC; kk += 16) {
@@ -166,14 +207,10 @@ __global__ __launch_bounds__(256) void k_sj_gemm_low(const void* __restrict__ Xv
                 short4_t av[2], bv[2];
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        av[a][q] = (short)sA[kr + q][wr * 32 + a * 16 + (lane & 15)];
+                    av[a] = *(const short4_t*)&sA[buf][at(kr, wr * 32 + a * 16 + (lane & 15))];
 #pragma unroll
                 for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        bv[bb][q] = (short)sB[kr + q][wc * 32 + bb * 16 + (lane & 15)];
+                    bv[bb] = *(const short4_t*)&sB[buf][at(kr, wc * 32 + bb * 16 + (lane & 15))];
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -187,9 +224,9 @@ __global__ __launch_bounds__(256) void k_sj_gemm_low(const void* __restrict__ Xv
                 const int kr = kk + (lane >> 4);
                 float av[2], bv[2];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = sA[kr][wr * 32 + a * 16 + (lane & 15)];
+                for (int a = 0; a < 2; ++a) av[a] = sA[buf][at(kr, wr * 32 + a * 16 + (lane & 15))];
 #pragma unroll
-                for (int bb = 0; bb < 2; ++bb) bv[bb] = sB[kr][wc * 32 + bb * 16 + (lane & 15)];
+                for (int bb = 0; bb < 2; ++bb) bv[bb] = sB[buf][at(kr, wc * 32 + bb * 16 + (lane & 15))];
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -198,7 +235,9 @@ __global__ __launch_bounds__(256) void k_sj_gemm_low(const void* __restrict__ Xv
                                                                           0, 0, 0);
             }
         }
+        if (more) stage(buf ^ 1, r0 + SJR_KC);
         __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -208,7 +247,11 @@ __global__ __launch_bounds__(256) void k_sj_gemm_low(const void* __restrict__ Xv
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + v;
                 const int c = c0 + wc * 32 + bb * 16 + (lane & 15);
-                if (i < n && c < b) out[i * b + c] = (double)acc[a][bb][v] * invm;
+                if (i < n && c < b) {
+                    const double val = (double)acc[a][bb][v] * invm;
+                    if (ks == 1) out[i * b + c] = val;
+                    else unsafeAtomicAdd(out + i * b + c, val);
+                }
             }
 }
 
@@ -285,10 +328,13 @@ void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b
                         hipStream_t s) {
     const int row_tiles = (int)((n + SJ_TILE - 1) / SJ_TILE);
     const int col_tiles = (b + SJ_TILE - 1) / SJ_TILE;
-    const unsigned grid = (unsigned)(8 * ((row_tiles + 7) / 8) * col_tiles);
+    // the samples split in two when there are enough of them to pay for the fill
+    const int ks = m >= 256 ? 2 : 1;
+    const unsigned grid = (unsigned)(8 * ((row_tiles + 7) / 8) * col_tiles * ks);
+    if (ks > 1) SIC_HIP(hipMemsetAsync(out, 0, sizeof(double) * n * b, s));
     prof_begin(KK_SJ, s);
     hipLaunchKernelGGL(k_sj_gemm_f64, dim3(grid), dim3(256), 0, s, X, n, m, j0, b, out,
-                       1.0 / (double)m, row_tiles, col_tiles);
+                       1.0 / (double)m, row_tiles, col_tiles, ks);
     SIC_CHECK_LAUNCH();
     // algorithmic: X read once (m x n) and S_J written once; 2 n b m flops
     prof_end(KK_SJ, s, 8.0 * ((double)m * n + (double)n * b), 2.0 * (double)n * b * m);
@@ -296,15 +342,19 @@ void launch_sj_gemm_f64(const double* X, int64_t n, int64_t m, int64_t j0, int b
 
 void launch_sj_gemm_low(const void* X, bool bf16, int64_t n, int64_t m, int64_t j0, int b,
                         double* out, hipStream_t s) {
-    dim3 grid((unsigned)((n + SJ_TILE - 1) / SJ_TILE), (unsigned)((b + SJ_TILE - 1) / SJ_TILE));
+    const int row_tiles = (int)((n + SJ_TILE - 1) / SJ_TILE);
+    const int col_tiles = (b + SJ_TILE - 1) / SJ_TILE;
+    const int ks = m >= 256 ? 2 : 1;
+    const unsigned grid = (unsigned)(8 * ((row_tiles + 7) / 8) * col_tiles * ks);
+    if (ks > 1) SIC_HIP(hipMemsetAsync(out, 0, sizeof(double) * n * b, s));
     const double esz = bf16 ? 2.0 : 4.0;
     prof_begin(bf16 ? KK_SJ_BF16 : KK_SJ_F32, s);
     if (bf16)
-        hipLaunchKernelGGL(k_sj_gemm_low<true>, grid, dim3(256), 0, s, X, n, m, j0, b, out,
-                           1.0 / (double)m);
+        hipLaunchKernelGGL(k_sj_gemm_low<true>, dim3(grid), dim3(256), 0, s, X, n, m, j0, b, out,
+                           1.0 / (double)m, row_tiles, col_tiles, ks);
     else
-        hipLaunchKernelGGL(k_sj_gemm_low<false>, grid, dim3(256), 0, s, X, n, m, j0, b, out,
-                           1.0 / (double)m);
+        hipLaunchKernelGGL(k_sj_gemm_low<false>, dim3(grid), dim3(256), 0, s, X, n, m, j0, b, out,
+                           1.0 / (double)m, row_tiles, col_tiles, ks);
     SIC_CHECK_LAUNCH();
     prof_end(bf16 ? KK_SJ_BF16 : KK_SJ_F32, s, esz * (double)m * n + 8.0 * (double)n * b,
              2.0 * (double)n * b * m);

@@ -78,6 +78,14 @@ extern "C" {
                                               2 GiB keeps the inverse columns it has solved
                                               (n^2 doubles of device memory) and starts each
                                               solve from the latest ones */
+#define SIC_FLAG_NO_S_CACHE (1ull << 7)    /* compute S_J = X^T X_J / m afresh for every block.
+                                              By default, a problem whose n^2 doubles fit in
+                                              2 GiB keeps the float64 columns of S it has formed
+                                              (n^2 doubles of device memory) and copies them out
+                                              in later cycles (the same values: only the time
+                                              differs); with SIC_MIXED the columns are then
+                                              float64 in every cycle, and the bfloat16 and float
+                                              products of S_J run only with this flag */
 #define SIC_FLAG_CONTINUATION (1ull << 5)  /* continuation (the BCDcont schedule of Section 8):
                                               the first three cycles run at lambda_4 =
                                               (1 + lambda) / 2 and then two values linearly

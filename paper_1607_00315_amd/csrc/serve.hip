@@ -117,7 +117,7 @@ size_t footprint_of(int64_t n, int64_t m, int x_dtype, int block, int n_lambda) 
     bytes += 8.0 * hc * hc;                             // coordinate Hessian
     bytes += 60.0 * dn * b;                             // free lists and coordinates
     bytes += 8.0 * 40.0 * b * b + 64.0 * dn + (16 << 20);   // line search, flags, slack
-    if (sic::warm_store_fits(n)) bytes += 8.0 * dn * dn + dn;   // the warm-start store
+    if (sic::warm_store_fits(n)) bytes += 16.0 * dn * dn + dn;   // warm-start store, cached S
     return (size_t)bytes;
 }
 

@@ -106,6 +106,12 @@ struct Problem {
     DevBuf<double> Wst;
     DevBuf<unsigned char> Wvalid;
     bool warm = false;
+    // float64 columns of S as formed: row-major n x n, column j valid when
+    // s_cached[j] (same size rule; SIC_FLAG_NO_S_CACHE turns it off). S_J of a
+    // later cycle is copied out instead of formed again.
+    DevBuf<double> Scache;
+    std::vector<char> s_cached;
+    bool scache = false;
     const WarmStore* warm_store() {
         ws_ = WarmStore{Wst.p, Wvalid.p};
         return warm ? &ws_ : nullptr;

@@ -311,6 +311,9 @@ void problem_init(Context& C, Problem& P, const void* X, int x_dtype, int64_t n,
     P.F = tr + lam * (double)n;   // F(I) = -log det I + tr(S) + lam * n
     P.level_set = false;
     P.perm.clear();
+    P.scache = warm_allowed && !(C.opt.flags & SIC_FLAG_NO_S_CACHE) && warm_store_fits(n);
+    P.s_cached.assign(P.scache ? (size_t)n : 0, 0);
+    if (P.scache) P.Scache.reserve((size_t)n * n);
     P.warm = warm_allowed && !(C.opt.flags & SIC_FLAG_NO_WARM_CG) && warm_store_fits(n);
     if (P.warm) {
         P.Wst.reserve((size_t)n * n);
@@ -553,6 +556,24 @@ void set_level_keys(Context& C, Problem& P, const int64_t* keys, int64_t count) 
 // Returns the profiler record to scale by the sweep count (or -1).
 // S_J of columns [j0, j0+b) in the current sweep's precision (float64 result).
 static void cov_block(Context& C, Problem& P, int64_t j0, int b, double* out, hipStream_t st) {
+    const size_t n = (size_t)P.n, w = sizeof(double) * (size_t)b;
+    if (P.scache) {
+        // With the cache every column is formed once, in float64 whatever the
+        // cycle's precision, and copied out afterwards (the same kernel on the
+        // same samples: the same values); the reduced-precision products run
+        // only without it.
+        if (!std::all_of(P.s_cached.begin() + j0, P.s_cached.begin() + j0 + b,
+                         [](char c) { return c != 0; })) {
+            launch_sj_gemm_f64(P.X.p, P.n, P.m, j0, b, out, st);
+            SIC_HIP(hipMemcpy2DAsync(P.Scache.p + j0, sizeof(double) * n, out, w, w, n,
+                                     hipMemcpyDeviceToDevice, st));
+            std::fill(P.s_cached.begin() + j0, P.s_cached.begin() + j0 + b, 1);
+            return;
+        }
+        SIC_HIP(hipMemcpy2DAsync(out, w, P.Scache.p + j0, sizeof(double) * n, w, n,
+                                 hipMemcpyDeviceToDevice, st));
+        return;
+    }
     if (C.prec != PREC_F64 && P.narrow)
         launch_sj_gemm_low(C.prec == PREC_BF16 ? (const void*)P.Xb.p : (const void*)P.Xf.p,
                            C.prec == PREC_BF16, P.n, P.m, j0, b, out, st);
@@ -1070,6 +1091,7 @@ void cluster_problem(Context& C, Problem& P) {
     P.perm = std::move(composed);
     P.level_set = false;
     if (P.warm) SIC_HIP(hipMemsetAsync(P.Wvalid.p, 0, (size_t)n, s));   // stored columns: old labels
+    std::fill(P.s_cached.begin(), P.s_cached.end(), 0);                  // cached S: old labels
     sync(C);
 }
 

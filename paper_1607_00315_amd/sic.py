@@ -23,7 +23,7 @@ SIC_ENOCONV, SIC_EHIP, SIC_ECANCELED, SIC_ETOOBIG, SIC_EINTERNAL = -5, -6, -7, -
 SIC_FP64, SIC_MIXED = 0, 1
 SIC_X_F64, SIC_X_F32, SIC_X_BF16 = 0, 1, 2
 FLAG_NO_MULTILEVEL, FLAG_FINAL_KKT, FLAG_VERBOSE, FLAG_NO_CERTIFY, FLAG_CLUSTER = 1, 2, 4, 8, 16
-FLAG_CONTINUATION, FLAG_NO_WARM_CG = 32, 64
+FLAG_CONTINUATION, FLAG_NO_WARM_CG, FLAG_NO_S_CACHE = 32, 64, 128
 
 
 class SicError(RuntimeError):

@@ -226,3 +226,21 @@ def test_warm_started_cg_matches_cold(name):
         _check_against_oracle(csr_to_dense(rp, col, val, n), ref, S, lam, info)
         its[warm] = info["cg_iterations"]
     assert its[True] <= its[False], its
+
+
+def test_cached_s_columns_change_nothing():
+    """Columns of S formed in one cycle are copied out in the next instead of
+    formed again: the solve is bit for bit the one that forms every block."""
+    from paper_1607_00315_amd import sic
+    X, P, spec = workload("grid_n900_m600")
+    lam = spec["lam"]
+    out = {}
+    for flags in (0, sic.FLAG_NO_S_CACHE):
+        announce(f"cached S columns grid_n900_m600 flags={flags}")
+        with sic.Context(block=spec["block"], flags=flags) as c:
+            (rp, col, val), info, _ = c.solve(X, lam, 1e-8)
+        assert info["status"] == 0 and info["cycles"] >= 2
+        out[flags] = (rp, col, val, info["objective"])
+    a, b = out[0], out[sic.FLAG_NO_S_CACHE]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2]) and a[3] == b[3]

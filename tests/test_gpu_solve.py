@@ -36,7 +36,8 @@ def _exact_kkt(A, S, lam):
     ("grid_n900_m600", True, "hessian"), ("chain_n200_m100", True, "pcd"),
     ("random_n600_m300", True, "pcd"), ("grid_n900_m600", False, "pcd"),
     ("chain_n200_m100", True, "mixed"), ("random_n600_m300", True, "mixed"),
-    ("grid_n900_m600", True, "mixed")])
+    ("grid_n900_m600", True, "mixed"), ("random_n600_m300", True, "mixed_formed"),
+    ("grid_n900_m600", True, "mixed_formed")])
 def test_solve_matches_oracle(name, multilevel, cd_form):
     from paper_1607_00315_amd import sic
     X, P, spec = workload(name)
@@ -44,12 +45,16 @@ def test_solve_matches_oracle(name, multilevel, cd_form):
     S = core.covariance(X)
     announce(f"solve {name} lam={lam} b={spec['block']} multilevel={multilevel} cd={cd_form}")
     flags = 0 if multilevel else sic.FLAG_NO_MULTILEVEL
-    # mixed: bfloat16 / float S_J and float CG while far from the optimum, then
-    # float64 cycles; the bars below are the float64 path's
+    # mixed: float CG (and float coordinate Hessians) while far from the optimum,
+    # then float64 cycles, S_J from the cached float64 columns; mixed_formed also
+    # forms S_J in bfloat16 / float in those cycles (no cache). The bars below
+    # are the float64 path's
+    if cd_form == "mixed_formed":
+        flags |= sic.FLAG_NO_S_CACHE
     A, info = _solve(X, lam, 1e-7, block=spec["block"], flags=flags,
                      cd_hessian_max=-1 if cd_form == "u" else 0,
                      pcd_min_coords=1 if cd_form == "pcd" else -1,
-                     precision=sic.SIC_MIXED if cd_form == "mixed" else sic.SIC_FP64)
+                     precision=sic.SIC_MIXED if cd_form.startswith("mixed") else sic.SIC_FP64)
     Aq, _ = quic_plain.solve(S, lam, tol=1e-12)
     assert np.array_equal(A, A.T)
     assert np.array_equal(A != 0, Aq != 0), \

@@ -67,10 +67,11 @@ __global__ void k_cg_init(int64_t n, int k, int col_tiles, const int32_t* __rest
                           const double* __restrict__ dinv, double* __restrict__ W,
                           V* __restrict__ R, double* __restrict__ scal,
                           int* __restrict__ tctl, double* __restrict__ tres,
-                          int* __restrict__ mctl, double* __restrict__ mres) {
+                          int* __restrict__ mctl, double* __restrict__ mres, int fill) {
     // x0 = 0, r0 = e_cols[j] over the whole n x k block (rows over workgroups,
-    // columns over threads); z0 = D^{-1} r0 is formed where it is read
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    // columns over threads), unless a warm start writes both (fill = 0);
+    // z0 = D^{-1} r0 is formed where it is read
+    for (int64_t i = blockIdx.x; fill && i < n; i += gridDim.x) {
         for (int j = threadIdx.x; j < k; j += blockDim.x) {
             const int64_t o = i * k + j;
             W[o] = 0.0;
@@ -104,15 +105,13 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadId
 
 // Warm start from the store of inverse columns: x0[:, j] = Ws[cols[j], :]
 // (row c of the store holds column c of A^{-1}, which is symmetric) when the
-// store holds column cols[j], else 0; p = q = 0. One 64 x 64 tile per
-// workgroup, transposed through LDS so both sides are read and written in
-// contiguous runs.
-template <typename V>
+// store holds column cols[j], else 0 (p and q start from zero in the first
+// product after it). One 64 x 64 tile per workgroup, transposed through LDS so
+// both sides are read and written in contiguous runs.
 __global__ __launch_bounds__(256) void k_cg_warm(int64_t n, int k, const int32_t* __restrict__ cols,
                                                  const double* __restrict__ Ws,
                                                  const unsigned char* __restrict__ valid,
-                                                 double* __restrict__ W, V* __restrict__ P,
-                                                 V* __restrict__ Q) {
+                                                 double* __restrict__ W) {
     __shared__ double t[64][65];
     const int64_t i0 = (int64_t)blockIdx.y * 64;
     const int j0 = blockIdx.x * 64;
@@ -127,12 +126,7 @@ __global__ __launch_bounds__(256) void k_cg_warm(int64_t n, int k, const int32_t
     for (int ir = ty; ir < 64; ir += 4) {
         const int64_t i = i0 + ir;
         const int j = j0 + tx;
-        if (i < n && j < k) {
-            const int64_t o = i * k + j;
-            W[o] = t[tx][ir];
-            P[o] = (V)0.0;
-            Q[o] = (V)0.0;
-        }
+        if (i < n && j < k) W[i * k + j] = t[tx][ir];
     }
 }
 
@@ -161,12 +155,6 @@ __global__ __launch_bounds__(256) void k_cg_store(int64_t n, int k, const int32_
     }
 }
 
-// rz of the step before a warm start: 1 (any positive value), so that the
-// first product's beta multiplies p = q = 0.
-__global__ void k_cg_warm_scal(int k, double* __restrict__ scal) {
-    for (int j = threadIdx.x + blockIdx.x * blockDim.x; j < k; j += blockDim.x * gridDim.x)
-        scal[j * 4 + S_RZ0] = 1.0;
-}
 
 // The preconditioned residual z = D^{-1} r of one entry, rounded to the
 // vector type (the value a stored z would hold). It is formed wherever it is
@@ -220,12 +208,15 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
     const V* __restrict__ R, V* __restrict__ P, V* __restrict__ Q, double* __restrict__ scal,
     const double* __restrict__ rzrr, double* __restrict__ part, int* __restrict__ tctl,
     double* __restrict__ tres, int* __restrict__ mctl, double* __restrict__ mres, double tol,
-    int it, int gx, int gy, int64_t rows_per, int mode, int check_only) {
+    int it, int restart, int gx, int gy, int64_t rows_per, int mode, int check_only) {
     const Tile T = cg_tile(mode, gx, gy);
     if (!T.ok) return;
     const int tx = T.tx, ty = T.ty;
     if (tctl[tx * T_INTS + T_DONE]) return;
+    // first: no residual sums yet (a cold start's iteration 0); fresh: p and q
+    // start from zero here (iteration 0, or the first after a warm start)
     const bool first = it == 0;
+    const bool fresh = it == restart;
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
     const int j = tx * 64 + lane;
@@ -308,8 +299,8 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
             nmax = ne[u] > nmax ? ne[u] : nmax;
             o[u] = ic * k + jj;
             zo[u] = zval<V>(dinv[ic], R[o[u]]);
-            po[u] = first ? 0.0 : (double)P[o[u]];
-            qo[u] = first ? 0.0 : (double)Q[o[u]];
+            po[u] = fresh ? 0.0 : (double)P[o[u]];
+            qo[u] = fresh ? 0.0 : (double)Q[o[u]];
             acc[u] = 0.0;
         }
         for (int64_t e = 0; e < nmax; e += CG_GATHER) {
@@ -333,8 +324,8 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_spmm(
 #pragma unroll
             for (int u = 0; u < CG_SROWS; ++u) {
                 if (!has[u]) continue;
-                const V pn = (V)(first ? zo[u] : zo[u] + beta * po[u]);
-                const V qn = (V)(first ? acc[u] : acc[u] + beta * qo[u]);
+                const V pn = (V)(fresh ? zo[u] : zo[u] + beta * po[u]);
+                const V qn = (V)(fresh ? acc[u] : acc[u] + beta * qo[u]);
                 P[o[u]] = pn;
                 Q[o[u]] = qn;
                 pq += (double)pn * (double)qn;
@@ -476,20 +467,23 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_true_residual(
     const int64_t r0 = (int64_t)ty * rows_per;
     const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
     for (int64_t i = r0 + wave; i < r1; i += CG_WAVES) {
-        const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+        const int64_t e0 = rowptr[i], ne = rowptr[i + 1] - e0;
         double acc = 0.0;
-        int64_t e = e0;
-        for (; e + 8 <= e1; e += 8) {
+        // gathers in batches of 8, all issued together; a short batch repeats
+        // the row's last entry with a zero coefficient (adds +0: the sum is the
+        // entry-by-entry one)
+        for (int64_t e = 0; e < ne; e += 8) {
             double wv[8], av[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                av[u] = val[e + u];
-                wv[u] = W[(int64_t)col[e + u] * k + jj];
+                const bool in = e + u < ne;
+                const int64_t x = in ? e0 + e + u : e0 + ne - 1;
+                av[u] = in ? val[x] : 0.0;
+                wv[u] = W[(int64_t)col[x] * k + jj];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc += av[u] * wv[u];
         }
-        for (; e < e1; ++e) acc += val[e] * W[(int64_t)col[e] * k + jj];
         if (jok) {
             const int64_t o = i * k + j;
             const double r = (i == cj ? 1.0 : 0.0) - acc;
@@ -612,20 +606,17 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
     hipLaunchKernelGGL(k_cg_vd, dim3((unsigned)std::min<int64_t>((A.nnz + 255) / 256, 4096)),
                        dim3(256), 0, s, A.col, A.val, bf.dinv, A.nnz, bf.vd);
     SIC_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_cg_init<V>, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, s,
-                       n, k, col_tiles, d_cols, bf.dinv, W, R, bf.scal, bf.flags, tres, hm_ctl,
-                       hm_res);
+    // (with a warm start, init only clears the control words: x0 and r0 come next)
+    hipLaunchKernelGGL(k_cg_init<V>, dim3(ws ? 1u : (unsigned)std::min<int64_t>(n, 4096)), dim3(256),
+                       0, s, n, k, col_tiles, d_cols, bf.dinv, W, R, bf.scal, bf.flags, tres,
+                       hm_ctl, hm_res, ws ? 0 : 1);
     SIC_CHECK_LAUNCH();
     // warm start: x0 from the store, r0 = e - A x0 exactly, and the iterations
-    // begin at 1 with p = q = 0 (the first product's beta then acts on zeros)
+    // begin at 1, the first product starting p and q from zero
     int start = 0;
     if (ws) {
         const dim3 tg((unsigned)((k + 63) / 64), (unsigned)((n + 63) / 64));
-        hipLaunchKernelGGL(k_cg_warm<V>, tg, dim3(256), 0, s, n, k, d_cols, ws->W, ws->valid, W, P,
-                           Q);
-        SIC_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_cg_warm_scal, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, k,
-                           bf.scal);
+        hipLaunchKernelGGL(k_cg_warm, tg, dim3(256), 0, s, n, k, d_cols, ws->W, ws->valid, W);
         SIC_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_cg_true_residual<V>, G.grid, dim3(CG_THREADS), 0, s, A.rowptr, A.col,
                            A.val, n, k, d_cols, bf.dinv, W, R, part_rz, bf.flags, col_tiles,
@@ -663,13 +654,13 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
             if (wide)
                 hipLaunchKernelGGL((k_cg_spmm<V, 16>), G.grid, dim3(CG_THREADS), 0, s, A.rowptr,
                                    A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
-                                   part_pq, bf.flags, tres, hm_ctl, hm_res, tol, it, col_tiles,
-                                   row_tiles, G.rows_per, G.mode, 0);
+                                   part_pq, bf.flags, tres, hm_ctl, hm_res, tol, it, start,
+                                   col_tiles, row_tiles, G.rows_per, G.mode, 0);
             else
                 hipLaunchKernelGGL((k_cg_spmm<V, 8>), G.grid, dim3(CG_THREADS), 0, s, A.rowptr,
                                    A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
-                                   part_pq, bf.flags, tres, hm_ctl, hm_res, tol, it, col_tiles,
-                                   row_tiles, G.rows_per, G.mode, 0);
+                                   part_pq, bf.flags, tres, hm_ctl, hm_res, tol, it, start,
+                                   col_tiles, row_tiles, G.rows_per, G.mode, 0);
             SIC_CHECK_LAUNCH();
             if (bf.prof)
                 r.spmm = prof_end(KK_CG_SPMM, s, mat + (it == 0 ? 3.0 : 5.0) * nkb,
@@ -695,8 +686,8 @@ CGResult block_cg_impl(const CsrView& A, const int32_t* d_cols, int k, double* W
             // the last update's residual has no product after it to test it
             hipLaunchKernelGGL((k_cg_spmm<V, 8>), dim3(col_tiles, 1), dim3(CG_THREADS), 0, s,
                                A.rowptr, A.col, bf.vd, n, k, bf.dinv, R, P, Q, bf.scal, part_rz,
-                               part_pq, bf.flags, tres, hm_ctl, hm_res, tol, launched, col_tiles,
-                               row_tiles, G.rows_per, 0, 1);
+                               part_pq, bf.flags, tres, hm_ctl, hm_res, tol, launched, start,
+                               col_tiles, row_tiles, G.rows_per, 0, 1);
             SIC_CHECK_LAUNCH();
         }
         if (!bf.mirror) {

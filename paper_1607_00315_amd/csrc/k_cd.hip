@@ -566,9 +566,11 @@ constexpr int CDP_CONST = 4 * CDH_K;   // a chunk's 1/a, A, S and W_rc, staged w
 //              g-1 from the tile H[chunk g][chunk g-2]), plus those of g-1
 //              (accumulated by wave 0 during the chain of interval g-1 from
 //              the tile H[chunk g][chunk g-1], staged with that interval's
-//              tiles); wave 0 then runs the chain; waves 1-15 stage the next interval's tiles, form the g-1
-//              contribution for chunk g+1, wave 9 fetches snapshot(g+1) and
-//              wave 10 publishes the step list of interval g-1.
+//              tiles); wave 0 then runs the chain. Meanwhile waves 1-15 stage
+//              the next interval's tiles (H[g+1][g+1] and H[g+2][g+1]) and
+//              constants, waves 1-8 form the steps of interval g-1 on chunk
+//              g+1, wave 9 fetches snapshot(g+1) and wave 10 publishes the
+//              step list of interval g-1.
 // z_k is then sum_t H[k][t] Delta_t summed by interval, and the chain and its
 // visiting order are those of k_cd_dense.
 //

@@ -42,7 +42,7 @@ FP64_PEAK_TFS = 78.6
 # passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB reference copy; valid only
 # while the kernel's source is the one measured (sha256 prefix of the file).
 PMC_TRAFFIC = {
-    "cd": dict(source="paper_1607_00315_amd/csrc/k_cd.hip", sha256="b3b13e70122f3712",
+    "cd": dict(source="paper_1607_00315_amd/csrc/k_cd.hip", sha256="1e13a2e13386d2ba",
                fetch=9988160.0, write=134391.0,
                profile="profiles/cd_grid_n10000_m5000_pmc.md"),
     "chol": dict(source="paper_1607_00315_amd/csrc/k_dense.hip", sha256="53072a36c5a8f075",

@@ -48,89 +48,90 @@ __global__ void k_upd_reset(int64_t ncoord, const int32_t* __restrict__ c_p,
     if (p < b) ANEW[(j0 + ci) * b + p] = 0.0;
 }
 
-__device__ inline int64_t lower_bound_col(const int32_t* __restrict__ col, int64_t lo, int64_t hi,
-                                          int64_t key) {
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (col[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
 // pass 0: count the entries of every new row; pass 1: write them at nrowptr.
-__global__ void k_upd_rows(int pass, int64_t n, int64_t j0, int b,
-                           const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                           const double* __restrict__ val, const int32_t* __restrict__ lmap,
-                           const int64_t* __restrict__ cptr, const int32_t* __restrict__ c_p,
-                           const int32_t* __restrict__ Jp, const double* __restrict__ ANEW,
-                           int32_t* __restrict__ cnt, const int64_t* __restrict__ nrowptr,
-                           int32_t* __restrict__ ncol, double* __restrict__ nval, int64_t cap) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
+// One wavefront per row: the lanes walk a row's entries 64 at a time and the
+// kept ones are compacted in order with a ballot, so a row's dense part over
+// the block columns costs b/64 coalesced loads rather than b serial ones.
+constexpr int UPD_ROWS_PER_WG = 4;
+
+__global__ __launch_bounds__(64 * UPD_ROWS_PER_WG) void k_upd_rows(
+    int pass, int64_t n, int64_t j0, int b, const int64_t* __restrict__ rowptr,
+    const int32_t* __restrict__ col, const double* __restrict__ val,
+    const int32_t* __restrict__ lmap, const int64_t* __restrict__ cptr,
+    const int32_t* __restrict__ c_p, const int32_t* __restrict__ Jp,
+    const double* __restrict__ ANEW, int32_t* __restrict__ cnt,
+    const int64_t* __restrict__ nrowptr, int32_t* __restrict__ ncol,
+    double* __restrict__ nval, int64_t cap) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * UPD_ROWS_PER_WG + (threadIdx.x >> 6);
+    if (r >= n) return;   // whole wavefronts leave together
+    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t j1 = j0 + b;
-    int64_t o = pass ? nrowptr[r] : 0;
-    int64_t count = 0;
-    const double* arow = ANEW + r * b;
-    auto emit = [&](int64_t c, double v) {
-        if (pass) {
-            if (o < cap) {   // the host checks the total against cap after the block
-                ncol[o] = (int32_t)c;
-                nval[o] = v;
+    const int64_t o0 = pass ? nrowptr[r] : 0;
+    int64_t o = o0;
+    // keep (c, v) on the lanes where `keep` holds, in lane order after what is there
+    auto put = [&](bool keep, int64_t c, double v) {
+        const unsigned long long m = __ballot(keep);
+        if (pass && keep) {
+            const int64_t p = o + __popcll(m & below);
+            if (p < cap) {   // the host checks the total against cap after the block
+                ncol[p] = (int32_t)c;
+                nval[p] = v;
             }
-            ++o;
         }
-        ++count;
+        o += __popcll(m);
     };
-    // the dense row over the block columns, 16 loads in flight at a time
-    // (unconditional loads of a clamped index, then a select)
-    auto emit_dense = [&]() {
-        for (int q0 = 0; q0 < b; q0 += 16) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int q = q0 + u < b ? q0 + u : b - 1;
-                v[u] = arow[q];
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (q0 + u < b && v[u] != 0.0) emit(j0 + q0 + u, v[u]);
+    const double* arow = ANEW + r * b;
+    auto put_dense = [&]() {
+        for (int q0 = 0; q0 < b; q0 += 64) {
+            const int q = q0 + lane;
+            const double v = arow[q < b ? q : b - 1];
+            put(q < b && v != 0.0, j0 + q, v);
         }
     };
     if (r >= j0 && r < j1) {
+        // out-of-block coordinates of column r, sorted by row: rows < j0, the
+        // dense row, then rows >= j1 (in-block rows are in the dense row)
         const int ci = (int)(r - j0);
         const int64_t t0 = cptr[ci], t1 = cptr[ci + 1];
-        int64_t t = t0;
-        for (; t < t1; ++t) {   // coordinates are sorted by row: rows < j0 first
-            const int64_t g = Jp[c_p[t]];
-            if (g >= j0) break;
-            const double v = ANEW[g * b + ci];
-            if (v != 0.0) emit(g, v);
-        }
-        emit_dense();
-        for (; t < t1; ++t) {
-            const int64_t g = Jp[c_p[t]];
-            if (g < j1) continue;
-            const double v = ANEW[g * b + ci];
-            if (v != 0.0) emit(g, v);
+        for (int side = 0; side < 2; ++side) {
+            if (side == 1) put_dense();
+            for (int64_t u = t0; u < t1; u += 64) {
+                const int64_t t = u + lane;
+                const bool in = t < t1;
+                const int64_t g = Jp[c_p[in ? t : t0]];
+                const double v = ANEW[g * b + ci];
+                put(in && (side ? g >= j1 : g < j0) && v != 0.0, g, v);
+            }
         }
     } else {
         const int64_t e0 = rowptr[r], e1 = rowptr[r + 1];
-        const bool in_n = lmap[r] >= b;
-        if (!in_n) {
+        if (lmap[r] < b) {   // not in N: the row has no entry in the block columns
             if (pass) {
-                for (int64_t e = e0; e < e1; ++e) emit(col[e], val[e]);
+                for (int64_t u = e0; u < e1; u += 64) {
+                    const int64_t e = u + lane;
+                    const bool in = e < e1;
+                    const int64_t ee = in ? e : e0;
+                    put(in, col[ee], val[ee]);
+                }
             } else {
-                count = e1 - e0;
+                o = e1 - e0;
             }
         } else {
-            const int64_t lo = lower_bound_col(col, e0, e1, j0);
-            const int64_t hi = lower_bound_col(col, lo, e1, j1);
-            for (int64_t e = e0; e < lo; ++e) emit(col[e], val[e]);
-            emit_dense();
-            for (int64_t e = hi; e < e1; ++e) emit(col[e], val[e]);
+            // old entries left of the block, the dense row, old entries right of it
+            for (int side = 0; side < 2; ++side) {
+                if (side == 1) put_dense();
+                for (int64_t u = e0; u < e1; u += 64) {
+                    const int64_t e = u + lane;
+                    const bool in = e < e1;
+                    const int64_t ee = in ? e : e0;
+                    const int64_t c = col[ee];
+                    put(in && (side ? c >= j1 : c < j0), c, val[ee]);
+                }
+            }
         }
     }
-    if (!pass) cnt[r] = (int32_t)count;
+    if (!pass && lane == 0) cnt[r] = (int32_t)(o - o0);
 }
 
 }  // namespace
@@ -157,7 +158,8 @@ void launch_upd_rows(int pass, int64_t n, int64_t j0, int b, const DevCSR& A, co
                      int32_t* cnt, const int64_t* nrowptr, int32_t* ncol, double* nval,
                      hipStream_t s, int64_t cap) {
     prof_begin(KK_UPD_ROWS, s);
-    hipLaunchKernelGGL(k_upd_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pass, n, j0, b,
+    hipLaunchKernelGGL(k_upd_rows, dim3((unsigned)((n + UPD_ROWS_PER_WG - 1) / UPD_ROWS_PER_WG)),
+                       dim3(64 * UPD_ROWS_PER_WG), 0, s, pass, n, j0, b,
                        A.rowptr.p, A.col.p, A.val.p, lmap, cptr, c_p, Jp, ANEW, cnt, nrowptr, ncol,
                        nval, cap);
     SIC_CHECK_LAUNCH();

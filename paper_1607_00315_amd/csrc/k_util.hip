@@ -7,13 +7,24 @@ namespace sic {
 namespace {
 
 constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_WAVES = SCAN_THREADS / 64;
+
+// Inclusive scan of one value per lane across a 64-lane wavefront.
+__device__ inline int64_t wave_inclusive_scan(int64_t x, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up((long long)x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
 
 // Exclusive scan of `count` int32 values into int64 (out has count+1 entries,
 // out[count] = total). One workgroup; each thread owns a contiguous chunk.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_i32(const int32_t* __restrict__ in,
                                                            int64_t count, int64_t* __restrict__ out,
                                                            int64_t* __restrict__ total_out) {
-    __shared__ int64_t sums[SCAN_THREADS];
+    __shared__ int64_t wsum[SCAN_WAVES];
     const int t = threadIdx.x;
     const int64_t chunk = (count + SCAN_THREADS - 1) / SCAN_THREADS;
     const int64_t b0 = t * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
@@ -27,15 +38,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_i32(const int32_t* __rest
         for (int u = 0; u < G; ++u)
             if (i0 + u < b1) s += v[u];
     }
-    sums[t] = s;
+    // chunk sums: inclusive scan within each wavefront, then over the wave totals
+    const int lane = t & 63, w = t >> 6;
+    const int64_t inc = wave_inclusive_scan(s, lane);
+    if (lane == 63) wsum[w] = inc;
     __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        int64_t v = t >= off ? sums[t - off] : 0;
-        __syncthreads();
-        sums[t] += v;
-        __syncthreads();
+    if (w == 0) {
+        const int64_t x = wave_inclusive_scan(lane < SCAN_WAVES ? wsum[lane] : 0, lane);
+        if (lane < SCAN_WAVES) wsum[lane] = x;
     }
-    int64_t run = t > 0 ? sums[t - 1] : 0;
+    __syncthreads();
+    int64_t run = inc - s + (w > 0 ? wsum[w - 1] : 0);
     for (int64_t i0 = b0; i0 < b1; i0 += G) {
         int32_t v[G];
 #pragma unroll
@@ -47,9 +60,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_i32(const int32_t* __rest
             run += v[u];
         }
     }
-    if (t == SCAN_THREADS - 1) {
-        out[count] = sums[t];
-        if (total_out) *total_out = sums[t];
+    if (t == 0) {
+        out[count] = wsum[SCAN_WAVES - 1];
+        if (total_out) *total_out = wsum[SCAN_WAVES - 1];
     }
 }
 
@@ -70,6 +83,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* _
                                                                 int64_t* __restrict__ total) {
     __shared__ int64_t part[CM_GROUPS][CM_COLS];
     __shared__ int64_t cs[CM_COLS];
+    __shared__ int64_t cw[CM_COLS / 64];
     const int t = threadIdx.x;
     const int c = t % CM_COLS, g = t / CM_COLS;
     const bool on = c < b;
@@ -93,26 +107,26 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_colmajor(const int32_t* _
     }
     part[g][c] = on ? s : 0;
     __syncthreads();
-    // column totals, then their inclusive scan over the columns (group 0)
+    // column totals (group 0), scanned within each wavefront of 64 columns;
+    // the exclusive in-wave prefix of every column and the wave totals go to LDS
     if (g == 0) {
         int64_t tot = 0;
         for (int q = 0; q < CM_GROUPS; ++q) tot += part[q][c];
-        cs[c] = tot;
+        const int64_t inc = wave_inclusive_scan(tot, c & 63);
+        cs[c] = inc - tot;
+        if ((c & 63) == 63) cw[c >> 6] = inc;
     }
     __syncthreads();
-    for (int off = 1; off < CM_COLS; off <<= 1) {
-        const int64_t v = (g == 0 && c >= off) ? cs[c - off] : 0;
-        __syncthreads();
-        if (g == 0) cs[c] += v;
-        __syncthreads();
-    }
     // this thread's start: entries of columns < c, then of column c in earlier quarters
-    int64_t run = c > 0 ? cs[c - 1] : 0;
+    int64_t run = cs[c];
+    for (int q = 0; q < (c >> 6); ++q) run += cw[q];
     for (int q = 0; q < g; ++q) run += part[q][c];
     if (g == 0 && on) colptr[c] = run;
     if (t == 0) {
-        colptr[b] = cs[b - 1];
-        if (total) *total = cs[b - 1];
+        int64_t all = 0;
+        for (int q = 0; q < CM_COLS / 64; ++q) all += cw[q];
+        colptr[b] = all;
+        if (total) *total = all;
     }
     for (int q0 = tile0; q0 < tile1; q0 += G) {
         int32_t v[G];

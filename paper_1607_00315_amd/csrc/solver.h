@@ -52,6 +52,11 @@ struct BlockWork {
     HostBuf<int64_t> h_cp;
     HostBuf<int32_t> h_rows;
     HostBuf<double> h_g;
+    // a second set for the initial free set, whose read-backs alternate
+    // between the two while the host records the previous block's pairs
+    HostBuf<int64_t> h_cp_alt;
+    HostBuf<int32_t> h_rows_alt;
+    HostBuf<double> h_g_alt;
     CGWork cg;
     PcdWork pcd;
     int64_t n_init = 0;   // n for which flag/map arrays are initialised

@@ -914,47 +914,45 @@ void initial_free_set(Context& C, Problem& P) {
     hipStream_t s = C.stream;
     BlockWork& W = C.work;
     const int64_t n = P.n;
-    const int b = std::min<int64_t>(C.opt.block, n);
+    const int b = (int)std::min<int64_t>(C.opt.block, n);
     ensure_flags(C, n, b);
     P.rec_key.clear();
     P.rec_g.clear();
     P.rec_seq.clear();
     W.kkt_acc.reserve(2);
-    for (int64_t j0 = 0; j0 < n; j0 += b) {
-        const int bb = (int)std::min<int64_t>(b, n - j0);
-        const size_t nb = (size_t)n * bb;
-        W.SJ.reserve(nb);
-        W.AJ.reserve(nb);
-        W.colptr.reserve(bb + 1);
-        SIC_HIP(hipMemsetAsync(W.AJ.p, 0, sizeof(double) * nb, s));
+    const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
+    // the block-sized buffers at the largest (first) block's size up front: none
+    // is reallocated while the stream may still read it
+    W.SJ.reserve((size_t)n * b);
+    W.AJ.reserve((size_t)n * b);
+    W.colptr.reserve(b + 1);
+    W.tilecount.reserve((size_t)tiles * b);
+    W.offsets.reserve((size_t)tiles * b);
+    W.kkt.reserve(2 * (size_t)tiles);
+    // count pass of a block: S_J and A_J, then the free pairs per (tile, column)
+    // and their total, which the scan writes straight into pinned staging
+    auto count_pairs = [&](int64_t j0, int bb) {
+        SIC_HIP(hipMemsetAsync(W.AJ.p, 0, sizeof(double) * (size_t)n * bb, s));
         launch_scatter_aj(P.Acur(), j0, bb, W.AJ.p, s);
-        cov_block(C, P, j0, bb, W.SJ.p, C.stream);
-        const int tiles = (int)((n + ROWS_PER_TILE - 1) / ROWS_PER_TILE);
-        W.tilecount.reserve((size_t)tiles * bb);
-        W.offsets.reserve((size_t)tiles * bb);
-        W.kkt.reserve(2 * (size_t)tiles);
+        cov_block(C, P, j0, bb, W.SJ.p, s);
         launch_screen_fine(0, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, nullptr, W.AJ.p,
                            W.tilecount.p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                            W.nflag.p, W.kkt.p, s);
         launch_scan_colmajor(W.tilecount.p, tiles, bb, W.offsets.p, W.colptr.p, C.h_i64, s);
-        sync(C);
-        const int64_t E = C.h_i64[0];
-        const size_t Es = (size_t)std::max<int64_t>(E, 1);
-        W.e_row.reserve(Es); W.e_g.reserve(Es); W.e_s.reserve(Es); W.e_a.reserve(Es); W.e_w.reserve(Es);
-        launch_screen_fine(1, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, nullptr, W.AJ.p,
-                           W.tilecount.p, W.offsets.p, W.e_row.p, W.e_g.p, W.e_s.p, W.e_a.p,
-                           W.e_w.p, W.nflag.p, W.kkt.p, s);
-        std::vector<int64_t> cp(bb + 1);
-        std::vector<int32_t> rows(Es);
-        std::vector<double> g(Es);
-        SIC_HIP(hipMemcpyAsync(cp.data(), W.colptr.p, sizeof(int64_t) * (bb + 1), hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(rows.data(), W.e_row.p, sizeof(int32_t) * Es, hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemcpyAsync(g.data(), W.e_g.p, sizeof(double) * Es, hipMemcpyDeviceToHost, s));
-        SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, s));
-        sync(C);
+    };
+    // block k's pairs come back into pinned slot k % 2; the host records them
+    // while the stream screens block k + 1
+    HostBuf<int64_t>* h_cp[2] = {&W.h_cp, &W.h_cp_alt};
+    HostBuf<int32_t>* h_rows[2] = {&W.h_rows, &W.h_rows_alt};
+    HostBuf<double>* h_g[2] = {&W.h_g, &W.h_g_alt};
+    struct Pending { int64_t j0 = 0; int bb = 0; int q = 0; bool on = false; } pend;
+    auto record_pairs = [&](const Pending& pd) {
+        const int64_t* cp = h_cp[pd.q]->p;
+        const int32_t* rows = h_rows[pd.q]->p;
+        const double* g = h_g[pd.q]->p;
         int64_t seq = (int64_t)P.rec_seq.size();
-        for (int ci = 0; ci < bb; ++ci) {
-            const int64_t c = j0 + ci;
+        for (int ci = 0; ci < pd.bb; ++ci) {
+            const int64_t c = pd.j0 + ci;
             for (int64_t e = cp[ci]; e < cp[ci + 1]; ++e) {
                 const int64_t r = rows[e];
                 const int64_t key = r <= c ? r * n + c : c * n + r;
@@ -963,7 +961,35 @@ void initial_free_set(Context& C, Problem& P) {
                 P.rec_seq.push_back(seq++);
             }
         }
+    };
+    const int64_t nblocks = (n + b - 1) / b;
+    count_pairs(0, b);
+    for (int64_t k = 0; k < nblocks; ++k) {
+        const int64_t j0 = k * b;
+        const int bb = (int)std::min<int64_t>(b, n - j0);
+        // block k is counted, and block k - 1's pairs are in their pinned slot;
+        // nothing is queued on the stream here
+        sync(C);
+        const int64_t E = C.h_i64[0];
+        const size_t Es = (size_t)std::max<int64_t>(E, 1);
+        W.e_row.reserve(Es); W.e_g.reserve(Es); W.e_s.reserve(Es); W.e_a.reserve(Es); W.e_w.reserve(Es);
+        const int q = (int)(k & 1);
+        h_cp[q]->reserve_grow(bb + 1);
+        h_rows[q]->reserve_grow(Es);
+        h_g[q]->reserve_grow(Es);
+        launch_screen_fine(1, n, j0, bb, ROWS_PER_TILE, tiles, P.lam, W.SJ.p, nullptr, W.AJ.p,
+                           W.tilecount.p, W.offsets.p, W.e_row.p, W.e_g.p, W.e_s.p, W.e_a.p,
+                           W.e_w.p, W.nflag.p, W.kkt.p, s);
+        SIC_HIP(hipMemcpyAsync(h_cp[q]->p, W.colptr.p, sizeof(int64_t) * (bb + 1), hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(h_rows[q]->p, W.e_row.p, sizeof(int32_t) * Es, hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemcpyAsync(h_g[q]->p, W.e_g.p, sizeof(double) * Es, hipMemcpyDeviceToHost, s));
+        SIC_HIP(hipMemsetAsync(W.nflag.p, 0, sizeof(int32_t) * n, s));
+        if (k + 1 < nblocks) count_pairs(j0 + b, (int)std::min<int64_t>(b, n - j0 - b));
+        if (pend.on) record_pairs(pend);
+        pend = Pending{j0, bb, q, true};
     }
+    sync(C);
+    if (pend.on) record_pairs(pend);
     finish_records(P);
 }
 
